@@ -1,0 +1,199 @@
+"""Pins for the oracle's energy, statistics and gradient (CPU only).
+
+P5 energy closed forms, P6 variational inequality, P7 finite differences, P8 score
+identity, P9 baseline bias of the batch-mean estimator."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import made, energy, estimator, exact, philox, sampling
+from paper_2106_13308_amd import inputs
+
+
+# ---------------------------------------------------------------- energy (P5)
+
+def test_P5_cut_identity_integer_exact():
+    edges = inputs.random_regular_graph(60, 5, 3)
+    w = inputs.integer_weights(len(edges), 1, 5, 4)
+    S = inputs.random_spins(500, 60, 5)
+    E = energy.energy_edges(edges, w, S)
+    assert E.dtype == np.int64
+    W_tot = energy.total_weight(w)
+    cut = energy.cut_value(edges, w, S)
+    assert np.array_equal((W_tot - E) % 2, np.zeros_like(E))
+    assert np.array_equal((W_tot - E) // 2, cut)
+
+
+def test_P5_all_equal_spins_and_bipartite():
+    n = 30
+    edges = inputs.cycle_graph(n)
+    w = inputs.integer_weights(n, 1, 5, 1)
+    W_tot = energy.total_weight(w)
+    ones = np.ones((2, n), np.int8)
+    ones[1] = -1
+    assert (energy.energy_edges(edges, w, ones) == W_tot).all()
+    alt = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)[None, :]
+    E = energy.energy_edges(edges, w, alt)
+    assert (W_tot - E[0]) // 2 == W_tot          # every edge of the even cycle is cut
+
+
+@pytest.mark.parametrize("n", [7, 10])
+def test_P5_complete_graph_max_cut_brute_force(n):
+    edges = inputs.complete_graph(n)
+    w = inputs.unit_weights(len(edges))
+    E = energy.energy_edges(edges, w, exact.all_strings(n))
+    best, _ = exact.max_cut_brute(n, E, energy.total_weight(w))
+    assert best == (n // 2) * ((n + 1) // 2)
+
+
+def test_P5_odd_cycle_max_cut():
+    n = 11
+    edges = inputs.cycle_graph(n)
+    E = energy.energy_edges(edges, inputs.unit_weights(n), exact.all_strings(n))
+    best, _ = exact.max_cut_brute(n, E, n)
+    assert best == n - 1
+
+
+def test_P5_dense_energy_matches_edge_form_and_quadratic_form():
+    n = 25
+    edges = inputs.erdos_renyi_graph(n, 0.3, 2)
+    w = np.random.default_rng(0).standard_normal(len(edges)).astype(np.float32)
+    J = np.zeros((n, n), np.float32)
+    J[edges[:, 0], edges[:, 1]] = w
+    J[edges[:, 1], edges[:, 0]] = w
+    S = inputs.random_spins(200, n, 7)
+    Ed = energy.energy_dense(J, S)
+    Ee = energy.energy_edges(edges, w, S)
+    Sf = S.astype(np.float64)
+    quad = 0.5 * np.einsum("bi,ij,bj->b", Sf, J.astype(np.float64), Sf)
+    assert np.allclose(Ed, Ee, rtol=0, atol=1e-12)
+    assert np.allclose(Ed, quad, rtol=0, atol=1e-12)
+
+
+def test_P5_maxcut20_instance_brute_force_optimum_and_P6_variational_bound():
+    w = inputs.WORKLOADS["maxcut20"]
+    inst = inputs.make_instance(w)
+    allS = exact.all_strings(w.n)
+    E = energy.energy_edges(inst["edges"], inst["weights"], allS)
+    W_tot = energy.total_weight(inst["weights"])
+    assert W_tot == 30 and len(inst["edges"]) == 30          # 3-regular, n = 20
+    best, Emin = exact.max_cut_brute(w.n, E, W_tot)
+    # a cut of a cubic graph never exceeds |E|, and the 3-regular max cut is >= 2|E|/3
+    assert 20 <= best <= 30
+    # the optimum is attained by s and by -s (spin-flip symmetry)
+    opt = np.nonzero(E == Emin)[0]
+    assert len(opt) >= 2 and len(opt) % 2 == 0
+    # variational inequality: exact L and every batch mean are >= lambda_min
+    ex = exact.exact_objective(inst, E)
+    assert ex["L"] >= Emin
+    U = philox.uniforms(2, 0, np.arange(w.B), w.n)
+    S, _ = sampling.sample_plain(inst, U)
+    Eb = energy.energy_edges(inst["edges"], inst["weights"], S)
+    assert Eb.min() >= Emin and Eb.mean() >= Emin
+
+
+# ---------------------------------------------------------------- statistics
+
+def test_batch_stats_closed_forms():
+    E = np.array([3, -1, 4, -1, 5], dtype=np.int64)
+    st = estimator.batch_stats(E, W_tot=9)
+    assert st["mean"] == 2.0
+    assert st["var"] == pytest.approx(((1 + 9 + 4 + 9 + 9) / 5), abs=0)
+    assert st["min"] == -1 and st["argmin"] == 1
+    assert np.allclose(st["coef"], (E - 2.0) / 5)
+    assert st["best_cut"] == 5 and st["mean_cut"] == 3.5
+
+
+# ---------------------------------------------------------------- gradient (P7, P8, P9)
+
+def test_P7_finite_differences_small():
+    n, h, B = 6, 9, 5
+    p = inputs.made_init(n, h, 3)
+    p["W1"] *= 3
+    p["W2"] *= 3
+    S = inputs.random_spins(B, n, 4)
+    coef = np.random.default_rng(1).standard_normal(B)
+    g = estimator.logp_grad(p, S, coef)
+    fd = estimator.finite_difference_grad(p, S, coef)
+    M1, M2 = made.masks(n, p["degrees"])
+    for k in g:
+        scale = np.abs(fd[k]).max()
+        assert np.abs(g[k] - fd[k]).max() <= 1e-7 * max(scale, 1.0), k
+    # masked weights: derivative is 0 both ways
+    assert (fd["W1"][M1 == 0] == 0).all() and (fd["W2"][M2 == 0] == 0).all()
+    assert (g["W1"][M1 == 0] == 0).all() and (g["W2"][M2 == 0] == 0).all()
+
+
+@pytest.mark.slow
+def test_P7_finite_differences_maxcut20():
+    w = inputs.WORKLOADS["maxcut20"]
+    p = inputs.make_instance(w)
+    B = 12
+    S = inputs.random_spins(B, w.n, 8)
+    coef = np.random.default_rng(2).standard_normal(B)
+    g = estimator.logp_grad(p, S, coef)
+    fd = estimator.finite_difference_grad(p, S, coef)
+    for k in g:
+        err = np.abs(g[k] - fd[k]).max()
+        assert err <= 1e-8 * max(np.abs(fd[k]).max(), 1.0), (k, err)
+
+
+def test_P7_gradient_matches_torch_autograd_float64():
+    n, h, B = 11, 17, 33
+    p = inputs.made_init(n, h, 6)
+    S = inputs.random_spins(B, n, 2)
+    coef = np.random.default_rng(3).standard_normal(B)
+    g = estimator.logp_grad(p, S, coef)
+    M1, M2 = (torch.from_numpy(m) for m in made.masks(n, p["degrees"]))
+    T = {k: torch.tensor(p[k], dtype=torch.float64, requires_grad=True) for k in ("W1", "b1", "W2", "b2")}
+    St = torch.from_numpy(S.astype(np.float64))
+    a = St @ (M1 * T["W1"]).T + T["b1"]
+    z = torch.relu(a) @ (M2 * T["W2"]).T + T["b2"]
+    lp = torch.nn.functional.logsigmoid(St * z).sum(1)
+    (torch.from_numpy(coef) @ lp).backward()
+    for k in T:
+        assert np.allclose(g[k], T[k].grad.numpy(), rtol=1e-12, atol=1e-13), k
+
+
+def test_P8_score_identity_by_enumeration():
+    n, h = 10, 14
+    p = inputs.made_init(n, h, 9)
+    p["W1"] *= 3
+    p["W2"] *= 3
+    pi = np.exp(exact.log_probs(p, n))
+    g = estimator.logp_grad(p, exact.all_strings(n), pi)    # E_pi[grad log pi]
+    for k in g:
+        assert np.abs(g[k]).max() < 1e-12, k
+
+
+@pytest.mark.parametrize("n,B", [(6, 2), (4, 3)])
+def test_P9_batch_mean_baseline_bias(n, B):
+    """E[g] over B i.i.d. samples equals (1 - 1/B) grad L exactly (diagonal H)."""
+    h = 7
+    p = inputs.made_init(n, h, 12)
+    p["W1"] *= 3
+    p["W2"] *= 3
+    allS = exact.all_strings(n)
+    edges = inputs.complete_graph(n)
+    w = inputs.integer_weights(len(edges), 1, 5, 3)
+    E = energy.energy_edges(edges, w, allS).astype(np.float64)
+    ex = exact.exact_objective(p, E)
+    pi = ex["pi"]
+    N = allS.shape[0]
+    # per-string gradients of log pi
+    per = [estimator.logp_grad(p, allS[i:i + 1], np.ones(1)) for i in range(N)]
+    keys = ("W1", "b1", "W2", "b2")
+    flat = np.stack([np.concatenate([g[k].ravel() for k in keys]) for g in per])
+    expect = np.zeros(flat.shape[1])
+    for tup in itertools.product(range(N), repeat=B):
+        idx = np.array(tup)
+        prob = np.prod(pi[idx])
+        Eb = E[idx]
+        c = (Eb - Eb.mean()) / B
+        expect += prob * (c @ flat[idx])
+    gL = np.concatenate([ex["grad"][k].ravel() for k in keys])
+    assert np.abs(gL).max() > 1e-3
+    assert np.allclose(expect, (1 - 1 / B) * gL, rtol=0, atol=1e-12)
