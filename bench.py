@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Throughput of one VQMC optimisation step on one MI355X.
+
+A step is the whole hot path on one batch: incremental autoregressive sampling of B
+strings (Algorithm 1), the Max-Cut local energy, FP64 batch statistics, and the
+score-function gradient through the masked network (log p forward recomputation plus
+the backward), i.e. one ``vqmc_step`` call.  The Adam update is outside the step.
+
+Workload (default): Max-Cut on a seeded random 10-regular graph with n = 10000 vertices
+and integer weights in {1..5} (CSR), MADE with h = 1000 hidden units in BF16 weights,
+B = 2048 samples per step.  Inputs are synthetic and resident in HBM before timing.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+
+Prints one JSON line.  Besides the headline BF16 + incremental step it reports the same
+step in FP32 + incremental and FP32 + the paper's n-pass full recompute (``forms``),
+per-call times, the roofline of the dominant kernel and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "samples/s per VQMC step (sample+energy+grad) at n=10k, BF16 vs FP32 at equal cut"
+PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "fp32_vector_tflops": 157.3,
+        "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="maxcut10k")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP32 comparison forms")
+    ap.add_argument("--cpu-samples", type=int, default=96)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + timed steps only (for rocprofv3)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp32_plain"],
+                    help="step form timed by --profile-only")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def setup(workload: str, wdtype):
+    import torch
+    from paper_2106_13308_amd import binding as B
+    from paper_2106_13308_amd import inputs
+    w = inputs.WORKLOADS[workload]
+    inst = inputs.make_instance(w)
+    made = B.Made.from_dense(inst["W1"], inst["b1"], inst["W2"], inst["b2"], inst["degrees"],
+                             wdtype=wdtype, device="cuda")
+    if "edges" in inst:
+        H = B.Hamiltonian.from_edges(w.n, inst["edges"], inst["weights"], device="cuda")
+    else:
+        H = B.Hamiltonian.dense(inst["J"], device="cuda")
+    torch.cuda.synchronize()
+    return w, inst, made, H
+
+
+def time_steps(made, H, B_, steps, warmup, algo=0, seed=2):
+    """Median-free whole-window timing: W untimed steps, then K steps between two
+    synchronisations (plus HIP events on the launch stream)."""
+    import torch
+    from paper_2106_13308_amd import binding as B
+    bufs = B.StepBuffers.allocate(made, H, B_)
+    for i in range(warmup):
+        B.step(made, H, B_, seed, i, bufs, algo=algo)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(steps):
+        B.step(made, H, B_, seed, warmup + i, bufs, algo=algo)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / steps, wall / steps, bufs
+
+
+def time_calls(made, H, B_, reps=10, seed=2):
+    """Average duration of each library call of the step, HIP events on its stream."""
+    import torch
+    from paper_2106_13308_amd import binding as B
+    bufs = B.StepBuffers.allocate(made, H, B_)
+    B.step(made, H, B_, seed, 0, bufs)
+    ws_bw = B.workspace(B.WS_BACKWARD, made, B_)
+    calls = {
+        "sample": lambda: B.sample(made, B_, seed, 1, S=bufs.S, logp=bufs.logp),
+        "energy": lambda: B.energy(H, bufs.S, B_),
+        "stats": lambda: B.batch_stats(bufs.E),
+        "logprob_backward": lambda: B.logprob_backward(made, bufs.S, bufs.coef, ws=ws_bw),
+        "logprob": lambda: B.logprob(made, bufs.S),
+    }
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def algorithmic_work(w, made, H):
+    """Algorithmic flops / bytes per launch of each call."""
+    c = made.c.cpu().numpy().astype(np.int64)
+    n, h, B_ = w.n, w.h, w.B
+    sum_c = int(c.sum())                     # sum_d c[d]: second-layer MACs per sample
+    nh = n * h
+    es = 2 if made.wdtype == 2 else 4
+    work = {
+        # sampler: n*h MACs per sample (dot over complete units + rank-1 update)
+        "sample": {"flops": 2.0 * nh * B_, "bytes": nh * es + B_ * (n + 4)},
+        # energy: read the spins once (+ the CSR, L2 resident) and write E
+        "energy": {"bytes": B_ * n + (H.nnz * 8 + (n + 1) * 8) + B_ * 8},
+        # forward: first layer sum_d (h - c[d]) + second layer sum_d c[d] = n*h MACs
+        "logprob": {"flops": 2.0 * nh * B_},
+        # backward: forward recompute (n*h) + hidden adjoint (sum_c) + weight gradient (n*h)
+        "logprob_backward": {"flops": 2.0 * (2 * nh + sum_c) * B_},
+    }
+    return work
+
+
+def cpu_baseline(w, inst, nsamp):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import energy as oen, estimator as oest, philox as oph, sampling as osmp
+    from oracle import bf16 as obf16
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+    except Exception:
+        threads = 1
+    p = dict(inst)
+    p["W1"] = obf16.round_to_bf16(inst["W1"])
+    p["W2"] = obf16.round_to_bf16(inst["W2"])
+    t0 = time.perf_counter()
+    U = oph.uniforms(2, 0, np.arange(nsamp), w.n)
+    S, lp = osmp.sample_plain(p, U)
+    E = oen.energy_edges(inst["edges"], inst["weights"], S)
+    st = oest.batch_stats(E)
+    oest.logp_grad(p, S, st["coef"])
+    dt = time.perf_counter() - t0
+    return {"value": nsamp / dt, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nsamp} of the {w.B} samples of one step (sample_plain + energy + stats + "
+                      f"analytic gradient, FP64 NumPy), {dt:.1f} s; cost is linear in B",
+            "seconds": dt, "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU data parallelism "
+                                   "is design-only (see DESIGN.md)", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2106_13308_amd import binding as B
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"device {torch.cuda.get_device_name(0)}; workload {a.workload}")
+    if a.calib_copy:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 256 MiB device-to-device")
+        del x, y
+    wd = B.F32 if (a.workload == "maxcut500" or a.form != "bf16") else B.BF16
+    w, inst, made, H = setup(a.workload, wd)
+    log(f"setup done: n={w.n} h={w.h} B={w.B}")
+    if a.profile_only and a.form == "fp32_plain":
+        ms, wall_ms, _ = time_steps(made, H, w.B, a.steps, a.warmup, algo=1)
+        log(f"fp32 plain step: {ms:.3f} ms")
+        return
+    ms, wall_ms, bufs = time_steps(made, H, w.B, a.steps, a.warmup)
+    log(f"bf16 incremental step: {ms:.3f} ms (event), {wall_ms * 1e3:.3f} ms (wall)")
+    if a.profile_only:
+        return
+    value = w.B / (ms / 1e3)
+    st = B.stats_to_dict(bufs.stats)
+    calls = time_calls(made, H, w.B)
+    log("per-call ms: " + json.dumps({k: round(v, 4) for k, v in calls.items()}))
+    work = algorithmic_work(w, made, H)
+    kernels = {}
+    for name, t in calls.items():
+        wk = work.get(name, {})
+        d = {"ms": t}
+        if "flops" in wk:
+            d["tflops"] = wk["flops"] / (t / 1e3) / 1e12
+        if "bytes" in wk:
+            d["gbs"] = wk["bytes"] / (t / 1e3) / 1e9
+        kernels[name] = d
+    step_calls = {k: calls[k] for k in ("sample", "energy", "stats", "logprob_backward")}
+    dom = max(step_calls, key=step_calls.get)
+    if dom == "sample":
+        ach = kernels["sample"]["tflops"]
+        roof = {"kernel": "sample_incremental_kernel", "bound": "alu", "achieved": ach,
+                "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["fp32_vector_tflops"], "traffic": None}
+    elif dom == "energy":
+        ach = kernels["energy"]["gbs"]
+        roof = {"kernel": "energy_csr_kernel", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"],
+                "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"], "traffic": None}
+    else:
+        ach = kernels["logprob_backward"]["tflops"]
+        roof = {"kernel": "logprob_backward (4 MFMA kernels)", "bound": "mfma", "achieved": ach,
+                "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["bf16_mfma_tflops"], "traffic": None}
+    forms = {"bf16_incremental": {"ms_per_step": ms, "samples_per_s": value}}
+    if not a.no_forms:
+        made32 = B.Made(made.n, made.h, made.P32, made.b1, made.b2, made.c, wdtype=B.F32)
+        ms32, _, _ = time_steps(made32, H, w.B, max(3, a.steps // 4), 1)
+        forms["fp32_incremental"] = {"ms_per_step": ms32, "samples_per_s": w.B / (ms32 / 1e3)}
+        log(f"fp32 incremental step: {ms32:.3f} ms")
+        # the paper's form: n full forward passes per sample batch (one timed step)
+        msp, _, _ = time_steps(made32, H, w.B, 1, 0, algo=1)
+        forms["fp32_plain"] = {"ms_per_step": msp, "samples_per_s": w.B / (msp / 1e3),
+                               "note": "one timed step, no warmup step (launch-bound form)"}
+        log(f"fp32 plain step: {msp:.1f} ms")
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "h": w.h, "global_batch": w.B,
+                   "graph": "random 10-regular, integer weights 1..5, CSR",
+                   "sampler": "incremental", "weights": "bf16", "parallelism": "single GPU"},
+        "roofline": roof, "kernels": kernels, "forms": forms,
+        "step_stats": {"mean_E": st["mean"], "min_E": st["min"], "var_E": st["var"]},
+    }
+    if not a.no_cpu:
+        log(f"oracle CPU baseline on {a.cpu_samples} samples ...")
+        out["cpu_baseline"] = cpu_baseline(w, inst, a.cpu_samples)
+        log(f"oracle: {out['cpu_baseline']['value']:.3f} samples/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

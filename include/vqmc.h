@@ -1,0 +1,200 @@
+/*
+ * vqmc.h - C ABI of the MI355X (gfx950) hot path of autoregressive-model VQMC for
+ * diagonal Ising / Max-Cut Hamiltonians (Zhao, De, Chen, Stokes, Veerapaneni,
+ * "Overcoming barriers to scalability in variational quantum Monte Carlo",
+ * arXiv:2106.13308).
+ *
+ * One optimisation step (paper Sec. 4, "Algorithm Parallelization": sample, measure,
+ * back-propagate) is
+ *   1. exact ancestral sampling of B spin strings from a MADE        (Algorithm 1)
+ *   2. the diagonal local energy E(s) = sum_{i<j} J_ij s_i s_j          (eq. hamiltonian)
+ *   3. batch statistics and the baseline coefficients c_b             (Sec. 2.1)
+ *   4. the score-function gradient g = sum_b c_b grad log pi(s_b)      (Sec. 2.1)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Spins are int8 in {-1,+1}; network input s = 1 - 2x for the binary x of eq. (e:tim).
+ *  - The MADE (Sec. 2.3, MADE layer; Sec. 5.1 architecture) has one hidden layer of h
+ *    units with sorted 1-based degrees m(k) in [1, n-1].  Unit k receives input site d
+ *    (1-based) iff d <= m(k) and feeds output d iff d > m(k).  With 0-based sites and
+ *    c[d] = #{k : m(k) <= d} (non-decreasing, c[0] = 0, c[n-1] = h), unit k feeds
+ *    output d iff k < c[d] and receives input d iff k >= c[d]: the two masks are
+ *    complementary, so all n*h unmasked weights fit one packed n x h matrix
+ *        P[d][k] = W2[d][k] if k < c[d] else W1[k][d].
+ *  - sigma(z_d) is P(s_d = +1 | s_<d); log pi(s) = sum_d log sigma(s_d z_d).
+ *  - Uniform u[b][d] = (Philox4x32-10(ctr = (d/4, b+offset, step, tag), key = seed)
+ *    word d%4 >> 8) * 2^-24 (Salmon et al., SC'11), and s_d = +1 iff u < sigma(z_d).
+ *  - Leading dimensions: every row-major device array the library defines is padded
+ *    to vqmc_ld(x) = x rounded up to VQMC_PAD elements.  A spin batch is B rows of
+ *    vqmc_ld(n) int8 (columns >= n are written as 0 by the sampler and ignored by
+ *    readers).
+ *  - All pointers are DEVICE pointers owned by the caller unless stated "host".  The
+ *    library allocates nothing persistent and never reads device data on the host.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls are asynchronous: they
+ *    validate their arguments on the host, enqueue kernels and return.
+ *  - Errors: return codes only.  Invalid arguments return VQMC_EINVAL (or EDTYPE /
+ *    EWORKSPACE) and enqueue nothing; a failed launch returns VQMC_EHIP.
+ *    vqmc_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef VQMC_H
+#define VQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VQMC_PAD 64
+
+typedef enum { VQMC_F64 = 0, VQMC_F32 = 1, VQMC_BF16 = 2 } vqmc_dtype;
+
+typedef enum {
+  VQMC_OK = 0,
+  VQMC_EINVAL = -1,     /* bad size, null pointer, unsorted degrees ...            */
+  VQMC_EDTYPE = -2,     /* dtype not supported by this call                        */
+  VQMC_EWORKSPACE = -3, /* workspace smaller than vqmc_workspace_bytes()           */
+  VQMC_EHIP = -4,       /* a HIP launch or copy failed                             */
+  VQMC_ENONFINITE = -5  /* reserved: non-finite parameters                         */
+} vqmc_status;
+
+/* MADE parameters in the kernels' working precision (produced by vqmc_cast).
+ *   P  : n rows x vqmc_ld(h) columns, dtype wdtype, zero padding.
+ *   Pt : h rows x vqmc_ld(n) columns, the transpose of P (same values), zero padding.
+ *   b1 : h floats (hidden bias), b2 : n floats (output bias), c : n int32 (see above). */
+typedef struct {
+  int32_t n, h;
+  int32_t wdtype; /* VQMC_F32 or VQMC_BF16 */
+  const void* P;
+  const void* Pt;
+  const float* b1;
+  const float* b2;
+  const int32_t* c;
+} vqmc_made;
+
+typedef enum { VQMC_H_CSR_INT = 0, VQMC_H_CSR_F32 = 1, VQMC_H_DENSE_F32 = 2 } vqmc_hkind;
+
+/* Diagonal Hamiltonian E(s) = sum_{i<j} J_ij s_i s_j (eq. hamiltonian with alpha_i =
+ * beta_i = 0; Max-Cut: J_ij = w_ij and cut = (W_tot - E) / 2).
+ *   CSR kinds: the strict upper triangle (each edge once, row i < col j), rowptr n+1
+ *   int64, col nnz int32, w nnz int32 (CSR_INT) or float (CSR_F32).
+ *   DENSE_F32: J is n x n float, row-major, symmetric with zero diagonal (only the
+ *   strict upper triangle is read). */
+typedef struct {
+  int32_t n;
+  int32_t kind;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* w;
+  const float* J;
+} vqmc_hamiltonian;
+
+/* Batch statistics (Sec. 2.1 estimators, population variance), device-resident. */
+typedef struct {
+  double mean_E; /* sum_b E_b / B                 */
+  double var_E;  /* sum_b (E_b - mean)^2 / B      */
+  double min_E;  /* min_b E_b                     */
+  int64_t argmin;/* first b attaining min_E       */
+  double sum_E;
+} vqmc_stats;
+
+/* ------------------------------------------------------------------ sizes, errors */
+int64_t vqmc_ld(int64_t x);
+const char* vqmc_error_string(int status);
+const char* vqmc_last_error(void);
+
+enum { VQMC_WS_LOGPROB = 0, VQMC_WS_BACKWARD = 1, VQMC_WS_SAMPLE_PLAIN = 2, VQMC_WS_STEP = 3 };
+/* Workspace bytes needed by a call (host function, no device access). */
+size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
+
+/* ------------------------------------------------------------------ parameters */
+/* Pack dense float32 MADE weights into the master packed matrix (Sec. 2.3 MADE layer;
+ * masks by the degree rule above).  W1: h x n, W2: n x h (row-major, device).
+ * degrees: HOST array of h sorted 1-based degrees in [1, n-1] (validated: EINVAL if
+ * unsorted or out of range).  Writes P32 (n x h float, unpadded) and c (n int32). */
+int vqmc_pack(int32_t n, int32_t h, const float* W1, const float* W2, const int32_t* degrees,
+              float* P32, int32_t* c, void* stream);
+
+/* Inverse of vqmc_pack: dense W1 (h x n) and W2 (n x h) with masked entries set to 0.
+ * Used to export parameters or a packed gradient in the paper's W1/W2 form. */
+int vqmc_unpack(int32_t n, int32_t h, const float* P32, const int32_t* c, float* W1, float* W2,
+                void* stream);
+
+/* Working-precision copies for the kernels: P (n x ld(h)) and Pt (h x ld(n)) in dtype
+ * (F32: exact copy; BF16: round-to-nearest-even), padding zeroed.  P32 is n x h. */
+int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt,
+              void* stream);
+
+/* ------------------------------------------------------------------ the hot path */
+/* Algorithm 1 (autoregressive sampling), incremental form: each sample keeps its h
+ * hidden pre-activations on chip; after drawing s_d it adds s_d * W1[k][d] to the
+ * units that receive site d, and each logit is a dot product over the units already
+ * complete.  Exactly the conditionals of n full forward passes, O(nh) per sample.
+ * Writes S (B x ld(n) int8) and, if logp != NULL, log pi(S) (B floats). */
+int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                uint32_t tag, int8_t* S, float* logp, void* stream);
+
+/* Algorithm 1 as the paper runs it: n forward passes of the masked network over the
+ * partially drawn batch, drawing site d after pass d (O(n^2 h) per sample).  Same
+ * draws as vqmc_sample up to rounding.  Needs VQMC_WS_SAMPLE_PLAIN workspace. */
+int vqmc_sample_plain(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step,
+                      int64_t sample_offset, uint32_t tag, int8_t* S, float* logp, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Local energy of a diagonal Hamiltonian (Sec. 2.1 local energy = H_xx).  E is int64
+ * for CSR_INT (exact), double otherwise (FP64 accumulation of exact products).
+ * The dense kind needs vqmc_energy_workspace_bytes() of workspace (CSR kinds need none;
+ * ws may then be NULL). */
+int vqmc_energy(const vqmc_hamiltonian* H, const int8_t* S, int64_t B, void* E, void* ws,
+                size_t ws_bytes, void* stream);
+size_t vqmc_energy_workspace_bytes(const vqmc_hamiltonian* H, int64_t B);
+
+/* Batch statistics and baseline coefficients c_b = (E_b - mean) / B (Sec. 2.1 gradient
+ * population form with the batch mean as baseline).  e_is_int: E is int64 (else
+ * double).  Deterministic fixed-order FP64 reductions.  coef may be NULL. */
+int vqmc_batch_stats(const void* E, int32_t e_is_int, int64_t B, vqmc_stats* stats, float* coef,
+                     void* stream);
+
+/* log pi(S) by one dense masked forward pass (MaskedFC1 -> ReLU -> MaskedFC2 ->
+ * log-sigmoid, Sec. 5.1) on MFMA; skips the masked half of both products.
+ * logp: B floats.  Z (nullable): B x ld(n) float logits. */
+int vqmc_logprob(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, float* Z, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Gradient of F = sum_b coef_b log pi(s_b) (the surrogate whose gradient is the
+ * score-function estimator of Sec. 2.1 when coef = c).  Recomputes the forward pass
+ * (nothing is kept from vqmc_logprob).  dP: n x h float (packed like P32), db1: h,
+ * db2: n.  Outputs are overwritten. */
+int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef,
+                          float* dP, float* db1, float* db2, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
+ * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,
+ * E, stats, coef and the gradient (dP, db1, db2). */
+int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed,
+              uint64_t step, int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E,
+              vqmc_stats* stats, float* coef, float* dP, float* db1, float* db2, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* The uniforms the samplers consume (the Bernoulli draw of Algorithm 1, "Sample y_i"):
+ * u[b][d] for b < B, d < n as defined above, written to u (B x n float, unpadded).
+ * Exposed so that the device Philox4x32-10 can be checked against an independent
+ * implementation; not needed on the hot path. */
+int vqmc_uniforms(int32_t n, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                  uint32_t tag, float* u, void* stream);
+
+/* ------------------------------------------------------------------ host helper */
+/* Build the strict-upper CSR of an undirected edge list (HOST pointers).  edges: m
+ * pairs (i, j), i != j, each undirected edge once in either orientation; w: m int32
+ * (wkind CSR_INT) or float (CSR_F32).  Outputs (host, caller-sized): rowptr n+1,
+ * col m, w_out m, rows sorted by column.  EINVAL on out-of-range or self loops. */
+int vqmc_csr_from_edges(int32_t n, int64_t m, const int32_t* edges, const void* w, int32_t wkind,
+                        int64_t* rowptr, int32_t* col, void* w_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VQMC_H */

@@ -1,0 +1,344 @@
+"""ctypes binding of ``libvqmc.so``: argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; torch supplies device
+memory and the current HIP stream.  If the library has not been built, importing this
+module raises (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvqmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_13308_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+PAD = 64
+F64, F32, BF16 = 0, 1, 2
+OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
+H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
+WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP = 0, 1, 2, 3
+TAG_TRAIN, TAG_EVAL = 0, 1
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+
+
+class MadeC(ctypes.Structure):
+    _fields_ = [("n", _i32), ("h", _i32), ("wdtype", _i32), ("P", _vp), ("Pt", _vp),
+                ("b1", _vp), ("b2", _vp), ("c", _vp)]
+
+
+class HamC(ctypes.Structure):
+    _fields_ = [("n", _i32), ("kind", _i32), ("nnz", _i64), ("rowptr", _vp), ("col", _vp),
+                ("w", _vp), ("J", _vp)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("mean_E", ctypes.c_double), ("var_E", ctypes.c_double), ("min_E", ctypes.c_double),
+                ("argmin", _i64), ("sum_E", ctypes.c_double)]
+
+
+STATS_BYTES = ctypes.sizeof(StatsC)
+
+_SIGS = {
+    "vqmc_ld": (_i64, [_i64]),
+    "vqmc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "vqmc_last_error": (ctypes.c_char_p, []),
+    "vqmc_workspace_bytes": (_sz, [ctypes.c_int, _i32, _i32, _i64, _i32]),
+    "vqmc_pack": (ctypes.c_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vqmc_unpack": (ctypes.c_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
+    "vqmc_sample_plain": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp,
+                                         _vp, _sz, _vp]),
+    "vqmc_energy": (ctypes.c_int, [ctypes.POINTER(HamC), _vp, _i64, _vp, _vp, _sz, _vp]),
+    "vqmc_energy_workspace_bytes": (_sz, [ctypes.POINTER(HamC), _i64]),
+    "vqmc_batch_stats": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp]),
+    "vqmc_logprob": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
+                                             _sz, _vp]),
+    "vqmc_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(HamC), _i64, _u64, _u64, _i64, _i32,
+                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vqmc_csr_from_edges": (ctypes.c_int, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "vqmc_uniforms": (ctypes.c_int, [_i32, _i64, _u64, _u64, _i64, _u32, _vp, _vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+lib = _lib
+
+
+class VqmcError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = _lib.vqmc_last_error().decode(errors="replace")
+        super().__init__(f"{fn} failed: {_lib.vqmc_error_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(fn: str, status: int):
+    if status != OK:
+        raise VqmcError(fn, status)
+
+
+def ld(x: int) -> int:
+    return int(_lib.vqmc_ld(x))
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t
+
+
+# ---------------------------------------------------------------- parameters
+class Made:
+    """MADE parameters: the FP32 master packed matrix P32 (n x h), biases, the
+    staircase index c, and the kernels' working copies (P, Pt) in ``wdtype``."""
+
+    def __init__(self, n: int, h: int, P32: torch.Tensor, b1: torch.Tensor, b2: torch.Tensor,
+                 c: torch.Tensor, wdtype: int = F32):
+        self.n, self.h = int(n), int(h)
+        self.P32, self.b1, self.b2, self.c = P32, b1, b2, c
+        self.wdtype = wdtype
+        dev = P32.device
+        tdt = torch.bfloat16 if wdtype == BF16 else torch.float32
+        self.P = torch.zeros((self.n, ld(self.h)), dtype=tdt, device=dev)
+        self.Pt = torch.zeros((self.h, ld(self.n)), dtype=tdt, device=dev)
+        self.refresh()
+
+    @classmethod
+    def from_dense(cls, W1, b1, W2, b2, degrees, wdtype: int = F32, device="cuda"):
+        """Pack dense float32 weights (numpy or torch) on the device."""
+        W1 = torch.as_tensor(np.asarray(W1, np.float32), device=device).contiguous()
+        W2 = torch.as_tensor(np.asarray(W2, np.float32), device=device).contiguous()
+        h, n = W1.shape
+        deg = np.ascontiguousarray(np.asarray(degrees, np.int32))
+        P32 = torch.empty((n, h), dtype=torch.float32, device=device)
+        c = torch.empty(n, dtype=torch.int32, device=device)
+        _check("vqmc_pack", _lib.vqmc_pack(n, h, W1.data_ptr(), W2.data_ptr(),
+                                           deg.ctypes.data_as(_vp), P32.data_ptr(), c.data_ptr(), _stream()))
+        b1t = torch.as_tensor(np.asarray(b1, np.float32), device=device).contiguous()
+        b2t = torch.as_tensor(np.asarray(b2, np.float32), device=device).contiguous()
+        return cls(n, h, P32, b1t, b2t, c, wdtype)
+
+    def refresh(self):
+        """Re-derive the working copies after P32 changed (e.g. after an optimiser step)."""
+        _check("vqmc_cast", _lib.vqmc_cast(self.n, self.h, self.P32.data_ptr(), self.wdtype,
+                                           self.P.data_ptr(), self.Pt.data_ptr(), _stream()))
+
+    def cstruct(self) -> MadeC:
+        return MadeC(self.n, self.h, self.wdtype, self.P.data_ptr(), self.Pt.data_ptr(),
+                     self.b1.data_ptr(), self.b2.data_ptr(), self.c.data_ptr())
+
+    def unpack(self, P32: torch.Tensor | None = None):
+        """Dense (W1, W2) from a packed matrix (default: the master weights)."""
+        P32 = self.P32 if P32 is None else P32
+        W1 = torch.empty((self.h, self.n), dtype=torch.float32, device=P32.device)
+        W2 = torch.empty((self.n, self.h), dtype=torch.float32, device=P32.device)
+        _check("vqmc_unpack", _lib.vqmc_unpack(self.n, self.h, _dev(P32).data_ptr(), self.c.data_ptr(),
+                                               W1.data_ptr(), W2.data_ptr(), _stream()))
+        return W1, W2
+
+
+class Hamiltonian:
+    """Diagonal Hamiltonian sum_{i<j} J_ij s_i s_j on the device."""
+
+    def __init__(self, n: int, kind: int, rowptr=None, col=None, w=None, J=None, W_tot=None):
+        self.n, self.kind = int(n), kind
+        self.rowptr, self.col, self.w, self.J = rowptr, col, w, J
+        self.nnz = 0 if col is None else int(col.numel())
+        self.W_tot = W_tot
+
+    @classmethod
+    def from_edges(cls, n: int, edges, weights, device="cuda"):
+        edges = np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2))
+        weights = np.asarray(weights)
+        integer = np.issubdtype(weights.dtype, np.integer)
+        kind = H_CSR_INT if integer else H_CSR_F32
+        w = np.ascontiguousarray(weights.astype(np.int32 if integer else np.float32))
+        m = edges.shape[0]
+        rowptr = np.zeros(n + 1, np.int64)
+        col = np.zeros(max(m, 1), np.int32)
+        wout = np.zeros(max(m, 1), w.dtype)
+        _check("vqmc_csr_from_edges", _lib.vqmc_csr_from_edges(
+            n, m, edges.ctypes.data_as(_vp), w.ctypes.data_as(_vp), kind, rowptr.ctypes.data_as(_vp),
+            col.ctypes.data_as(_vp), wout.ctypes.data_as(_vp)))
+        W_tot = int(w.astype(np.int64).sum()) if integer else float(w.astype(np.float64).sum())
+        return cls(n, kind, torch.from_numpy(rowptr).to(device), torch.from_numpy(col[:m].copy()).to(device),
+                   torch.from_numpy(wout[:m].copy()).to(device), None, W_tot)
+
+    @classmethod
+    def dense(cls, J, device="cuda"):
+        J = torch.as_tensor(np.asarray(J, np.float32), device=device).contiguous()
+        return cls(J.shape[0], H_DENSE_F32, J=J)
+
+    def cstruct(self) -> HamC:
+        return HamC(self.n, self.kind, self.nnz, _ptr(self.rowptr), _ptr(self.col), _ptr(self.w), _ptr(self.J))
+
+    @property
+    def e_is_int(self) -> bool:
+        return self.kind == H_CSR_INT
+
+    def energy_dtype(self):
+        return torch.int64 if self.e_is_int else torch.float64
+
+
+# ---------------------------------------------------------------- calls
+def workspace(which: int, made: Made, B: int) -> torch.Tensor:
+    nb = int(_lib.vqmc_workspace_bytes(which, made.n, made.h, B, made.wdtype))
+    return torch.empty(max(nb, 256), dtype=torch.uint8, device=made.P.device)
+
+
+def empty_spins(B: int, n: int, device="cuda") -> torch.Tensor:
+    return torch.empty((B, ld(n)), dtype=torch.int8, device=device)
+
+
+def sample(made: Made, B: int, seed: int, step: int = 0, offset: int = 0, tag: int = TAG_TRAIN,
+           S: torch.Tensor | None = None, logp: torch.Tensor | None = None, want_logp: bool = True):
+    """Incremental sampler.  Returns (S [B x ld(n) int8], logp [B] or None)."""
+    dev = made.P.device
+    S = empty_spins(B, made.n, dev) if S is None else _dev(S)
+    if want_logp and logp is None:
+        logp = torch.empty(B, dtype=torch.float32, device=dev)
+    m = made.cstruct()
+    _check("vqmc_sample", _lib.vqmc_sample(ctypes.byref(m), B, seed, step, offset, tag, S.data_ptr(),
+                                           _ptr(logp), _stream()))
+    return S, logp
+
+
+def uniforms(n: int, B: int, seed: int, step: int = 0, offset: int = 0, tag: int = TAG_TRAIN,
+             device="cuda") -> torch.Tensor:
+    """The device Philox uniforms u[b][d] (B x n float32)."""
+    u = torch.empty((B, n), dtype=torch.float32, device=device)
+    _check("vqmc_uniforms", _lib.vqmc_uniforms(n, B, seed, step, offset, tag, u.data_ptr(), _stream()))
+    return u
+
+
+def sample_plain(made: Made, B: int, seed: int, step: int = 0, offset: int = 0, tag: int = TAG_TRAIN,
+                 ws: torch.Tensor | None = None):
+    dev = made.P.device
+    S = empty_spins(B, made.n, dev)
+    logp = torch.empty(B, dtype=torch.float32, device=dev)
+    ws = workspace(WS_SAMPLE_PLAIN, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_sample_plain", _lib.vqmc_sample_plain(ctypes.byref(m), B, seed, step, offset, tag,
+                                                       S.data_ptr(), logp.data_ptr(), ws.data_ptr(),
+                                                       ws.numel(), _stream()))
+    return S, logp
+
+
+def energy(H: Hamiltonian, S: torch.Tensor, B: int | None = None) -> torch.Tensor:
+    B = S.shape[0] if B is None else B
+    E = torch.empty(B, dtype=H.energy_dtype(), device=S.device)
+    hc = H.cstruct()
+    nb = int(_lib.vqmc_energy_workspace_bytes(ctypes.byref(hc), B))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=S.device)
+    _check("vqmc_energy", _lib.vqmc_energy(ctypes.byref(hc), _dev(S).data_ptr(), B, E.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), _stream()))
+    return E
+
+
+def batch_stats(E: torch.Tensor, want_coef: bool = True):
+    """Returns (stats dict tensor-backed, coef [B] float32)."""
+    B = E.shape[0]
+    st = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=E.device)
+    coef = torch.empty(B, dtype=torch.float32, device=E.device) if want_coef else None
+    _check("vqmc_batch_stats", _lib.vqmc_batch_stats(_dev(E).data_ptr(), int(E.dtype == torch.int64), B,
+                                                     st.data_ptr(), _ptr(coef), _stream()))
+    return st, coef
+
+
+def stats_to_dict(st: torch.Tensor) -> dict:
+    raw = st.cpu().numpy().tobytes()
+    s = StatsC.from_buffer_copy(raw)
+    return {"mean": s.mean_E, "var": s.var_E, "min": s.min_E, "argmin": int(s.argmin), "sum": s.sum_E}
+
+
+def logprob(made: Made, S: torch.Tensor, B: int | None = None, want_z: bool = False,
+            ws: torch.Tensor | None = None):
+    B = S.shape[0] if B is None else B
+    dev = S.device
+    logp = torch.empty(B, dtype=torch.float32, device=dev)
+    Z = torch.empty((B, ld(made.n)), dtype=torch.float32, device=dev) if want_z else None
+    ws = workspace(WS_LOGPROB, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_logprob", _lib.vqmc_logprob(ctypes.byref(m), _dev(S).data_ptr(), B, logp.data_ptr(),
+                                             _ptr(Z), ws.data_ptr(), ws.numel(), _stream()))
+    return (logp, Z) if want_z else logp
+
+
+def logprob_backward(made: Made, S: torch.Tensor, coef: torch.Tensor, B: int | None = None,
+                     ws: torch.Tensor | None = None):
+    B = S.shape[0] if B is None else B
+    dev = S.device
+    dP = torch.empty((made.n, made.h), dtype=torch.float32, device=dev)
+    db1 = torch.empty(made.h, dtype=torch.float32, device=dev)
+    db2 = torch.empty(made.n, dtype=torch.float32, device=dev)
+    ws = workspace(WS_BACKWARD, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_logprob_backward", _lib.vqmc_logprob_backward(
+        ctypes.byref(m), _dev(S).data_ptr(), B, _dev(coef).data_ptr(), dP.data_ptr(), db1.data_ptr(),
+        db2.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return dP, db1, db2
+
+
+@dataclass
+class StepBuffers:
+    """Caller-owned buffers of one optimisation step (allocated once, reused)."""
+    S: torch.Tensor
+    logp: torch.Tensor
+    E: torch.Tensor
+    stats: torch.Tensor
+    coef: torch.Tensor
+    dP: torch.Tensor
+    db1: torch.Tensor
+    db2: torch.Tensor
+    ws: torch.Tensor
+
+    @classmethod
+    def allocate(cls, made: Made, H: Hamiltonian, B: int):
+        dev = made.P.device
+        return cls(
+            S=empty_spins(B, made.n, dev),
+            logp=torch.empty(B, dtype=torch.float32, device=dev),
+            E=torch.empty(B, dtype=H.energy_dtype(), device=dev),
+            stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev),
+            coef=torch.empty(B, dtype=torch.float32, device=dev),
+            dP=torch.empty((made.n, made.h), dtype=torch.float32, device=dev),
+            db1=torch.empty(made.h, dtype=torch.float32, device=dev),
+            db2=torch.empty(made.n, dtype=torch.float32, device=dev),
+            ws=workspace(WS_STEP, made, B),
+        )
+
+
+def step(made: Made, H: Hamiltonian, B: int, seed: int, step_idx: int, bufs: StepBuffers,
+         algo: int = 0, offset: int = 0):
+    """One optimisation step (sample, energy, statistics, gradient) into ``bufs``."""
+    m = made.cstruct()
+    hc = H.cstruct()
+    _check("vqmc_step", _lib.vqmc_step(
+        ctypes.byref(m), ctypes.byref(hc), B, seed, step_idx, offset, algo, bufs.S.data_ptr(),
+        bufs.logp.data_ptr(), bufs.E.data_ptr(), bufs.stats.data_ptr(), bufs.coef.data_ptr(),
+        bufs.dP.data_ptr(), bufs.db1.data_ptr(), bufs.db2.data_ptr(), bufs.ws.data_ptr(),
+        bufs.ws.numel(), _stream()))
+    return bufs

@@ -1,0 +1,262 @@
+// C ABI entry points: host-side validation, workspace accounting, kernel dispatch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace vqmc;
+
+namespace {
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return VQMC_OK;
+  return fail(VQMC_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int kMaxSamplerH = 4096;  // units held per thread: 16 x 256
+
+int check_made(const vqmc_made* m, bool need_pt) {
+  if (!m) return fail(VQMC_EINVAL, "made is NULL");
+  if (m->n < 2 || m->h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1 (n=%d h=%d)", m->n, m->h);
+  if (m->wdtype != VQMC_F32 && m->wdtype != VQMC_BF16)
+    return fail(VQMC_EDTYPE, "weight dtype %d not supported (F32 or BF16)", m->wdtype);
+  if (!m->P || !m->b1 || !m->b2 || !m->c) return fail(VQMC_EINVAL, "null parameter pointer");
+  if (need_pt && !m->Pt) return fail(VQMC_EINVAL, "Pt is NULL");
+  return VQMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t vqmc_ld(int64_t x) { return round_up(x, kPad); }
+
+const char* vqmc_error_string(int status) {
+  switch (status) {
+    case VQMC_OK: return "ok";
+    case VQMC_EINVAL: return "invalid argument";
+    case VQMC_EDTYPE: return "unsupported dtype";
+    case VQMC_EWORKSPACE: return "workspace too small";
+    case VQMC_EHIP: return "HIP error";
+    case VQMC_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* vqmc_last_error(void) { return g_err; }
+
+size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  if (n < 2 || h < 1 || B < 1) return 0;
+  switch (which) {
+    case VQMC_WS_LOGPROB: return logprob_ws_bytes(n, h, B, wdtype, false);
+    case VQMC_WS_BACKWARD: return logprob_ws_bytes(n, h, B, wdtype, true);
+    case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
+    case VQMC_WS_STEP: {
+      // the step runs sample (plain form needs its own), energy and backward in order
+      const size_t bw = logprob_ws_bytes(n, h, B, wdtype, true);
+      const size_t sp = sample_plain_ws_bytes(n, h, B, wdtype);
+      const size_t en = (size_t)((n + 63) / 64) * (size_t)B * sizeof(double);
+      return std::max(bw, std::max(sp, en));
+    }
+    default: return 0;
+  }
+}
+
+int vqmc_pack(int32_t n, int32_t h, const float* W1, const float* W2, const int32_t* degrees,
+              float* P32, int32_t* c, void* stream) {
+  if (n < 2 || h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1");
+  if (!W1 || !W2 || !degrees || !P32 || !c) return fail(VQMC_EINVAL, "null pointer");
+  for (int k = 0; k < h; ++k) {
+    if (degrees[k] < 1 || degrees[k] > n - 1)
+      return fail(VQMC_EINVAL, "degree[%d] = %d outside [1, n-1]", k, degrees[k]);
+    if (k && degrees[k] < degrees[k - 1]) return fail(VQMC_EINVAL, "degrees not sorted at %d", k);
+  }
+  // c[d] = #{k : m(k) <= d} for 0-based site d (m is 1-based)
+  std::vector<int32_t> ch(n);
+  int k = 0;
+  for (int d = 0; d < n; ++d) {
+    while (k < h && degrees[k] <= d) ++k;
+    ch[d] = k;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(c, ch.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_status(e, "vqmc_pack copy");
+  // the host vector must outlive the copy
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_status(e, "vqmc_pack sync");
+  return hip_status(launch_pack(n, h, W1, W2, c, P32, st), "vqmc_pack");
+}
+
+int vqmc_unpack(int32_t n, int32_t h, const float* P32, const int32_t* c, float* W1, float* W2,
+                void* stream) {
+  if (n < 2 || h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1");
+  if (!P32 || !c || !W1 || !W2) return fail(VQMC_EINVAL, "null pointer");
+  return hip_status(launch_unpack(n, h, P32, c, W1, W2, (hipStream_t)stream), "vqmc_unpack");
+}
+
+int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt, void* stream) {
+  if (n < 2 || h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1");
+  if (dtype != VQMC_F32 && dtype != VQMC_BF16) return fail(VQMC_EDTYPE, "cast dtype %d", dtype);
+  if (!P32 || !P || !Pt) return fail(VQMC_EINVAL, "null pointer");
+  return hip_status(launch_cast(n, h, P32, dtype, P, Pt, (hipStream_t)stream), "vqmc_cast");
+}
+
+int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                uint32_t tag, int8_t* S, float* logp, void* stream) {
+  int r = check_made(m, false);
+  if (r) return r;
+  if (B < 1) return fail(VQMC_EINVAL, "B must be >= 1");
+  if (!S) return fail(VQMC_EINVAL, "S is NULL");
+  if (sample_offset < 0) return fail(VQMC_EINVAL, "sample_offset < 0");
+  if (m->h > kMaxSamplerH) return fail(VQMC_EINVAL, "h = %d exceeds the sampler limit %d", m->h, kMaxSamplerH);
+  return hip_status(
+      launch_sample_incremental(*m, B, seed, step, sample_offset, tag, S, logp, (hipStream_t)stream),
+      "vqmc_sample");
+}
+
+int vqmc_sample_plain(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                      uint32_t tag, int8_t* S, float* logp, void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1) return fail(VQMC_EINVAL, "B must be >= 1");
+  if (!S || !ws) return fail(VQMC_EINVAL, "null pointer");
+  if (sample_offset < 0) return fail(VQMC_EINVAL, "sample_offset < 0");
+  const size_t need = sample_plain_ws_bytes(m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_sample_plain(*m, B, seed, step, sample_offset, tag, S, logp, ws,
+                                        (hipStream_t)stream),
+                    "vqmc_sample_plain");
+}
+
+static int check_ham(const vqmc_hamiltonian* H) {
+  if (!H) return fail(VQMC_EINVAL, "hamiltonian is NULL");
+  if (H->n < 2) return fail(VQMC_EINVAL, "hamiltonian n < 2");
+  if (H->kind == VQMC_H_DENSE_F32) {
+    if (!H->J) return fail(VQMC_EINVAL, "dense J is NULL");
+    return VQMC_OK;
+  }
+  if (H->kind != VQMC_H_CSR_INT && H->kind != VQMC_H_CSR_F32)
+    return fail(VQMC_EINVAL, "unknown hamiltonian kind %d", H->kind);
+  if (H->n > 49152) return fail(VQMC_EINVAL, "CSR energy supports n <= 49152");
+  if (!H->rowptr || (H->nnz > 0 && (!H->col || !H->w))) return fail(VQMC_EINVAL, "null CSR pointer");
+  return VQMC_OK;
+}
+
+int vqmc_energy(const vqmc_hamiltonian* H, const int8_t* S, int64_t B, void* E, void* ws,
+                size_t ws_bytes, void* stream) {
+  int r = check_ham(H);
+  if (r) return r;
+  if (B < 1 || !S || !E) return fail(VQMC_EINVAL, "bad batch arguments");
+  const size_t need = energy_workspace_bytes(*H, B);
+  if (ws_bytes < need || (need && !ws)) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_energy(*H, S, B, E, ws, (hipStream_t)stream), "vqmc_energy");
+}
+
+size_t vqmc_energy_workspace_bytes(const vqmc_hamiltonian* H, int64_t B) {
+  if (!H || B < 1) return 0;
+  return energy_workspace_bytes(*H, B);
+}
+
+int vqmc_batch_stats(const void* E, int32_t e_is_int, int64_t B, vqmc_stats* stats, float* coef,
+                     void* stream) {
+  if (!E || !stats || B < 1) return fail(VQMC_EINVAL, "bad stats arguments");
+  return hip_status(launch_stats(E, e_is_int, B, stats, coef, (hipStream_t)stream), "vqmc_batch_stats");
+}
+
+int vqmc_logprob(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, float* Z, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !logp || !ws) return fail(VQMC_EINVAL, "bad logprob arguments");
+  const size_t need = logprob_ws_bytes(m->n, m->h, B, m->wdtype, false);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_logprob(*m, S, B, logp, Z, ws, (hipStream_t)stream), "vqmc_logprob");
+}
+
+int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, float* dP,
+                          float* db1, float* db2, void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !coef || !dP || !db1 || !db2 || !ws) return fail(VQMC_EINVAL, "bad backward arguments");
+  const size_t need = logprob_ws_bytes(m->n, m->h, B, m->wdtype, true);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_backward(*m, S, B, coef, dP, db1, db2, ws, (hipStream_t)stream),
+                    "vqmc_logprob_backward");
+}
+
+int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed, uint64_t step,
+              int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E, vqmc_stats* stats,
+              float* coef, float* dP, float* db1, float* db2, void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if ((r = check_ham(H))) return r;
+  if (H->n != m->n) return fail(VQMC_EINVAL, "hamiltonian n=%d != model n=%d", H->n, m->n);
+  if (B < 1 || !S || !E || !stats || !coef || !dP || !db1 || !db2 || !ws)
+    return fail(VQMC_EINVAL, "bad step arguments");
+  if (algo != 0 && algo != 1) return fail(VQMC_EINVAL, "algo must be 0 (incremental) or 1 (plain)");
+  if (algo == 0 && m->h > kMaxSamplerH) return fail(VQMC_EINVAL, "h exceeds the sampler limit");
+  const size_t need = vqmc_workspace_bytes(VQMC_WS_STEP, m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = (algo == 0)
+                     ? launch_sample_incremental(*m, B, seed, step, sample_offset, 0, S, logp, st)
+                     : launch_sample_plain(*m, B, seed, step, sample_offset, 0, S, logp, ws, st);
+  if (e != hipSuccess) return hip_status(e, "vqmc_step sample");
+  if ((e = launch_energy(*H, S, B, E, ws, st)) != hipSuccess) return hip_status(e, "vqmc_step energy");
+  if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, st)) != hipSuccess)
+    return hip_status(e, "vqmc_step stats");
+  if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st)) != hipSuccess)
+    return hip_status(e, "vqmc_step backward");
+  return VQMC_OK;
+}
+
+int vqmc_uniforms(int32_t n, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset, uint32_t tag,
+                  float* u, void* stream) {
+  if (n < 1 || B < 1 || !u || sample_offset < 0) return fail(VQMC_EINVAL, "bad uniforms arguments");
+  return hip_status(launch_uniforms(n, B, seed, step, sample_offset, tag, u, (hipStream_t)stream),
+                    "vqmc_uniforms");
+}
+
+int vqmc_csr_from_edges(int32_t n, int64_t m, const int32_t* edges, const void* w, int32_t wkind,
+                        int64_t* rowptr, int32_t* col, void* w_out) {
+  if (n < 2 || m < 0) return fail(VQMC_EINVAL, "bad sizes");
+  if (wkind != VQMC_H_CSR_INT && wkind != VQMC_H_CSR_F32) return fail(VQMC_EINVAL, "bad weight kind");
+  if (m > 0 && (!edges || !w || !col || !w_out)) return fail(VQMC_EINVAL, "null pointer");
+  if (!rowptr) return fail(VQMC_EINVAL, "rowptr is NULL");
+  struct E3 { int32_t i, j; int64_t idx; };
+  std::vector<E3> es((size_t)m);
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t a = edges[2 * e], b = edges[2 * e + 1];
+    if (a < 0 || b < 0 || a >= n || b >= n) return fail(VQMC_EINVAL, "edge %lld out of range", (long long)e);
+    if (a == b) return fail(VQMC_EINVAL, "self loop at edge %lld", (long long)e);
+    if (a > b) std::swap(a, b);
+    es[(size_t)e] = {a, b, e};
+  }
+  std::sort(es.begin(), es.end(), [](const E3& x, const E3& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+  for (size_t e = 1; e < es.size(); ++e)
+    if (es[e].i == es[e - 1].i && es[e].j == es[e - 1].j) return fail(VQMC_EINVAL, "duplicate edge");
+  for (int i = 0; i <= n; ++i) rowptr[i] = 0;
+  for (const E3& x : es) rowptr[x.i + 1]++;
+  for (int i = 0; i < n; ++i) rowptr[i + 1] += rowptr[i];
+  for (size_t e = 0; e < es.size(); ++e) {
+    col[e] = es[e].j;
+    if (wkind == VQMC_H_CSR_INT) ((int32_t*)w_out)[e] = ((const int32_t*)w)[es[e].idx];
+    else ((float*)w_out)[e] = ((const float*)w)[es[e].idx];
+  }
+  return VQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Shared device helpers for the VQMC library (gfx950 / CDNA4 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vqmc.h"
+
+namespace vqmc {
+
+typedef uint16_t bf16_t;  // raw bfloat16 bits
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(4))) float floatx4_t;
+typedef __attribute__((ext_vector_type(4))) double doublex4_t;
+
+constexpr int kPad = VQMC_PAD;  // leading-dimension padding (elements)
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------- bfloat16
+// float32 -> bfloat16, round to nearest even (NaN stays a quiet NaN).
+__device__ inline bf16_t f32_to_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (bf16_t)((b >> 16) | 0x0040u);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (bf16_t)(b >> 16);
+}
+__device__ inline float bf16_to_f32(bf16_t x) { return __uint_as_float(((uint32_t)x) << 16); }
+
+template <typename T> __device__ inline float to_f32(T x);
+template <> __device__ inline float to_f32<float>(float x) { return x; }
+template <> __device__ inline float to_f32<bf16_t>(bf16_t x) { return bf16_to_f32(x); }
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon et al., SC'11: 10 rounds of the 4x32 Philox bijection with Weyl key schedule.
+__device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Four consecutive site uniforms u[b, 4*blk .. 4*blk+3] (24-bit dyadic in [0,1)).
+// Counter = (site block, global sample index, step, tag), key = seed.
+__device__ inline float4 site_uniforms(uint64_t seed, uint64_t step, uint32_t tag, uint64_t sample,
+                                       uint32_t blk) {
+  const uint4 r = philox4x32_10(make_uint4(blk, (uint32_t)sample, (uint32_t)step, tag),
+                                (uint32_t)seed, (uint32_t)(seed >> 32));
+  const float s = 5.9604644775390625e-8f;  // 2^-24
+  return make_float4((float)(r.x >> 8) * s, (float)(r.y >> 8) * s, (float)(r.z >> 8) * s,
+                     (float)(r.w >> 8) * s);
+}
+
+// ---------------------------------------------------------------- numerics
+// log sigma(t) = min(t, 0) - log1p(exp(-|t|)), stable for large |t|.
+__device__ inline float log_sigmoid(float t) { return fminf(t, 0.f) - log1pf(__expf(-fabsf(t))); }
+// sigma(t) for any t without overflow.
+__device__ inline float sigmoid(float t) {
+  const float e = __expf(-fabsf(t));
+  const float r = 1.f / (1.f + e);
+  return t >= 0.f ? r : e * r;
+}
+
+// ---------------------------------------------------------------- wave reductions (wave64)
+#define VQMC_DPP(v, ctrl) \
+  __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false))
+
+// Sum over all 64 lanes; result is wave-uniform.
+__device__ inline float wave_sum(float v) {
+  v += VQMC_DPP(v, 0xB1);   // quad_perm [1,0,3,2]
+  v += VQMC_DPP(v, 0x4E);   // quad_perm [2,3,0,1]
+  v += VQMC_DPP(v, 0x141);  // row_half_mirror
+  v += VQMC_DPP(v, 0x140);  // row_mirror  -> every lane holds its 16-lane row sum
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+__device__ inline float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+}  // namespace vqmc

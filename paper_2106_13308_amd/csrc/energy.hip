@@ -1,0 +1,270 @@
+// Diagonal local energy and batch statistics.
+//
+// Local energy (Sec. 2.1): l(x) = (H psi)(x) / psi(x), which for a diagonal H
+// (alpha_i = 0 in eq. hamiltonian) is H_xx = sum_{i<j} J_ij s_i s_j with beta_i = 0.
+// Statistics (Sec. 2.1, eq. stochastic_variance and the gradient population form):
+// mean, population variance, min/argmin and baseline coefficients c_b = (E_b - mean)/B.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace vqmc {
+
+// ---------------------------------------------------------------- sparse (CSR upper)
+// One workgroup handles MSE samples: their spins are staged in LDS (int8), each thread
+// walks whole CSR rows (edges i<j) and accumulates w_ij s_i s_j for every staged
+// sample.  Integer weights accumulate exactly in int64; float weights in double (the
+// products w * (+-1) are exact).  Fixed thread->row map and a fixed-shape tree make the
+// result deterministic.
+template <typename WT, typename AT>
+__global__ __launch_bounds__(256) void energy_csr_kernel(int n, int64_t lds, const int64_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const WT* __restrict__ w,
+                                                          const int8_t* __restrict__ S, int64_t B,
+                                                          int mse, AT* __restrict__ E) {
+  extern __shared__ int8_t sh[];  // mse * n spins, then reduction scratch
+  const int t = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * mse;
+  const int nq = (int)min<int64_t>(mse, B - b0);
+  for (int q = 0; q < nq; ++q)
+    for (int i = t; i < n; i += 256) sh[q * n + i] = S[(b0 + q) * lds + i];
+  __syncthreads();
+  AT acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0;
+  for (int i = t; i < n; i += 256) {
+    const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+    AT row[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) row[q] = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int j = col[e];
+      const AT we = (AT)w[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) row[q] += we * (AT)sh[q * n + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nq) acc[q] += row[q] * (AT)sh[q * n + i];
+  }
+  // block tree reduction, one sample at a time
+  AT* red = (AT*)(sh + ((mse * n + 15) / 16) * 16);
+  for (int q = 0; q < nq; ++q) {
+    red[t] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    if (t == 0) E[b0 + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- dense J (FP64)
+// E_b = sum_i s_bi * y_bi with y_bi = sum_{j>i} J_ij s_bj (strict upper triangle only).
+// Tile: 64 samples x 64 rows i per workgroup, K loop over j >= i0 in chunks of 32,
+// FP64 MFMA 16x16x4 on exact operands (+-1 and float32 J widened to double).
+// Each workgroup writes one partial per sample; a second pass sums the partials of
+// the row tiles in a fixed order.
+constexpr int DT = 64, DK = 16;
+__global__ __launch_bounds__(256) void energy_dense_kernel(int n, int64_t lds, const float* __restrict__ J,
+                                                            const int8_t* __restrict__ S, int64_t B,
+                                                            double* __restrict__ part) {
+  __shared__ double Ss[DT][DK + 1];
+  __shared__ double Js[DT][DK + 1];
+  __shared__ double rowsum[2][DT];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;  // wave sub-tile: samples x rows
+  const int64_t m0 = (int64_t)blockIdx.y * DT;          // samples
+  const int i0 = blockIdx.x * DT;                       // rows i
+  doublex4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (doublex4_t){0, 0, 0, 0};
+  const int jbeg = (i0 / DK) * DK;
+  for (int j0 = jbeg; j0 < n; j0 += DK) {
+    // stage: 64 rows x 16 columns each, 4 elements per thread
+    {
+      const int r = t >> 2, q = (t & 3) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = j0 + q + e;
+        const int64_t b = m0 + r;
+        Ss[r][q + e] = (b < B && j < n) ? (double)S[b * lds + j] : 0.0;
+        const int i = i0 + r;
+        Js[r][q + e] = (i < n && j < n && j > i) ? (double)J[(int64_t)i * n + j] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < DK; kk += 4) {
+      double a[2], bb[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) a[mi] = Ss[wm + mi * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) bb[ni] = Js[wn + ni * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], bb[ni], acc[mi][ni], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue: the FP64 MFMA accumulator layout puts element e of lane l at row
+  // 4*e + l/16, column l%16 (unlike the FP32 16x16 layout, row 4*(l/16) + e);
+  // multiply by s_bi and sum over i.
+  double ps[2][4];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double v = 0.0;
+      const int64_t b = m0 + wm + mi * 16 + 4 * e + (lane >> 4);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int i = i0 + wn + ni * 16 + (lane & 15);
+        const double si = (b < B && i < n) ? (double)S[b * lds + i] : 0.0;
+        v += si * acc[mi][ni][e];
+      }
+      ps[mi][e] = v;
+    }
+  // reduce over the 16 lanes of a row (lane & 15) with a fixed butterfly
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double v = ps[mi][e];
+      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+      ps[mi][e] = v;
+    }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rowsum[wn >> 5][wm + mi * 16 + 4 * e + (lane >> 4)] = ps[mi][e];
+  }
+  __syncthreads();
+  if (t < DT) {
+    const int64_t b = m0 + t;
+    if (b < B) part[(int64_t)blockIdx.x * B + b] = rowsum[0][t] + rowsum[1][t];
+  }
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ part, int ntiles, int64_t B,
+                                    double* __restrict__ E) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+  for (int tt = 0; tt < ntiles; ++tt) s += part[(int64_t)tt * B + b];
+  E[b] = s;
+}
+
+size_t energy_workspace_bytes(const vqmc_hamiltonian& H, int64_t B) {
+  if (H.kind != VQMC_H_DENSE_F32) return 0;
+  const int64_t ntiles = (H.n + DT - 1) / DT;
+  return (size_t)(ntiles * B * sizeof(double));
+}
+
+hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, void* E, void* ws,
+                         hipStream_t st) {
+  const int n = H.n;
+  const int64_t lds = round_up(n, kPad);
+  if (H.kind == VQMC_H_DENSE_F32) {
+    const int ntiles = (n + DT - 1) / DT;
+    dim3 grid(ntiles, (unsigned)((B + DT - 1) / DT));
+    energy_dense_kernel<<<grid, 256, 0, st>>>(n, lds, H.J, S, B, (double*)ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sum_partials_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>((const double*)ws, ntiles, B,
+                                                                       (double*)E);
+    return hipGetLastError();
+  }
+  const int mse = std::min(8, std::max(1, 49152 / n));
+  const size_t shbytes = (size_t)(((mse * n + 15) / 16) * 16) + 256 * 8;
+  const unsigned grid = (unsigned)((B + mse - 1) / mse);
+  if (H.kind == VQMC_H_CSR_INT)
+    energy_csr_kernel<int32_t, int64_t><<<grid, 256, shbytes, st>>>(
+        n, lds, H.rowptr, H.col, (const int32_t*)H.w, S, B, mse, (int64_t*)E);
+  else
+    energy_csr_kernel<float, double><<<grid, 256, shbytes, st>>>(
+        n, lds, H.rowptr, H.col, (const float*)H.w, S, B, mse, (double*)E);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- statistics
+// One workgroup of 1024 threads; every reduction has a fixed shape, so the result is
+// bit-reproducible.  int64 energies are summed exactly before the single division.
+template <typename ET>
+__global__ __launch_bounds__(1024) void stats_kernel(const ET* __restrict__ E, int64_t B,
+                                                      vqmc_stats* __restrict__ out,
+                                                      float* __restrict__ coef) {
+  __shared__ ET ssum[1024];
+  __shared__ double sd[1024];
+  __shared__ ET smin[1024];
+  __shared__ int64_t sarg[1024];
+  const int t = threadIdx.x;
+  ET s = 0;
+  ET mn = 0;
+  int64_t am = -1;
+  for (int64_t b = t; b < B; b += 1024) {
+    const ET v = E[b];
+    s += v;
+    if (am < 0 || v < mn) {
+      mn = v;
+      am = b;
+    }
+  }
+  ssum[t] = s;
+  smin[t] = mn;
+  sarg[t] = am;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      ssum[t] += ssum[t + w];
+      const int64_t ao = sarg[t + w];
+      if (ao >= 0 && (sarg[t] < 0 || smin[t + w] < smin[t] ||
+                      (smin[t + w] == smin[t] && ao < sarg[t]))) {
+        smin[t] = smin[t + w];
+        sarg[t] = ao;
+      }
+    }
+    __syncthreads();
+  }
+  const double mean = (double)ssum[0] / (double)B;
+  double v2 = 0.0;
+  for (int64_t b = t; b < B; b += 1024) {
+    const double dv = (double)E[b] - mean;
+    v2 += dv * dv;
+  }
+  sd[t] = v2;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) sd[t] += sd[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    out->mean_E = mean;
+    out->var_E = sd[0] / (double)B;
+    out->min_E = (double)smin[0];
+    out->argmin = sarg[0];
+    out->sum_E = (double)ssum[0];
+  }
+  if (coef)
+    for (int64_t b = t; b < B; b += 1024) coef[b] = (float)(((double)E[b] - mean) / (double)B);
+}
+
+hipError_t launch_stats(const void* E, int e_is_int, int64_t B, vqmc_stats* stats, float* coef,
+                        hipStream_t st) {
+  if (e_is_int)
+    stats_kernel<int64_t><<<1, 1024, 0, st>>>((const int64_t*)E, B, stats, coef);
+  else
+    stats_kernel<double><<<1, 1024, 0, st>>>((const double*)E, B, stats, coef);
+  return hipGetLastError();
+}
+
+}  // namespace vqmc

@@ -1,0 +1,43 @@
+// Internal launchers (host functions) shared by the C ABI implementation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vqmc.h"
+
+namespace vqmc {
+
+// pack.hip
+hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int32_t* c, float* P32,
+                       hipStream_t st);
+hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float* W1, float* W2,
+                         hipStream_t st);
+hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st);
+
+// energy.hip
+hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, void* E,
+                         void* ws, hipStream_t st);
+size_t energy_workspace_bytes(const vqmc_hamiltonian& H, int64_t B);
+hipError_t launch_stats(const void* E, int e_is_int, int64_t B, vqmc_stats* stats, float* coef,
+                        hipStream_t st);
+
+// sample.hip
+hipError_t launch_sample_incremental(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
+                                     int64_t offset, uint32_t tag, int8_t* S, float* logp,
+                                     hipStream_t st);
+hipError_t launch_uniforms(int n, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
+                           float* u, hipStream_t st);
+
+// gemm.hip : masked forward / backward on MFMA
+struct FwdWorkspace;
+size_t logprob_ws_bytes(int n, int h, int64_t B, int dtype, bool backward);
+hipError_t launch_logprob(const vqmc_made& m, const int8_t* S, int64_t B, float* logp, float* Z,
+                          void* ws, hipStream_t st);
+hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
+                           float* dP, float* db1, float* db2, void* ws, hipStream_t st);
+size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
+hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
+                               int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,
+                               hipStream_t st);
+
+}  // namespace vqmc

@@ -1,0 +1,124 @@
+"""Training-side glue: the autograd wrapper of log pi and the VQMC optimisation loop.
+
+Sec. 4 of the paper: each iteration samples a batch, computes the local energies,
+back-propagates the score-function surrogate and applies the optimiser update (Adam,
+Sec. 5.1).  All compute runs in ``libvqmc.so``; torch holds the FP32 master parameters
+and runs Adam on them.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import torch
+
+from . import binding as B
+
+
+class LogProb(torch.autograd.Function):
+    """log pi(S) with a hand-written adjoint.
+
+    forward(P32, b1, b2, made, S) calls ``vqmc_logprob``; backward(grad) calls
+    ``vqmc_logprob_backward`` with coef = grad, which recomputes the hidden activations
+    instead of keeping B x h of them alive between the two passes.  ``made`` supplies
+    the working-precision copies of P32 (call ``made.refresh()`` after changing P32)."""
+
+    @staticmethod
+    def forward(ctx, P32, b1, b2, made: B.Made, S):
+        ctx.made = made
+        ctx.save_for_backward(S)
+        return B.logprob(made, S)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (S,) = ctx.saved_tensors
+        dP, db1, db2 = B.logprob_backward(ctx.made, S, grad.contiguous().float())
+        return dP, db1, db2, None, None
+
+
+def log_prob(made: B.Made, S: torch.Tensor) -> torch.Tensor:
+    return LogProb.apply(made.P32, made.b1, made.b2, made, S)
+
+
+class Trainer:
+    """VQMC with a MADE on a diagonal Hamiltonian, minimising E = sum_{i<j} J_ij s_i s_j.
+
+    Each ``step()`` is one optimisation iteration: ``vqmc_step`` (sample, energy,
+    statistics, gradient) followed by Adam on the FP32 master parameters and a refresh
+    of the working-precision copies."""
+
+    def __init__(self, made: B.Made, H: B.Hamiltonian, batch: int, seed: int = 2, lr: float = 1e-3,
+                 algo: int = 0, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.made, self.H, self.batch, self.seed, self.algo = made, H, batch, seed, algo
+        for t in (made.P32, made.b1, made.b2):
+            t.requires_grad_(True)
+        self.opt = torch.optim.Adam([made.P32, made.b1, made.b2], lr=lr, betas=betas, eps=eps)
+        self.bufs = B.StepBuffers.allocate(made, H, batch)
+        self.t = 0
+        self.best_E = None
+
+    def step(self, log: bool = True) -> dict | None:
+        with torch.no_grad():
+            B.step(self.made, self.H, self.batch, self.seed, self.t, self.bufs, algo=self.algo)
+            self.made.P32.grad = self.bufs.dP
+            self.made.b1.grad = self.bufs.db1
+            self.made.b2.grad = self.bufs.db2
+            self.opt.step()
+            self.made.refresh()
+        self.t += 1
+        if not log:
+            return None
+        st = B.stats_to_dict(self.bufs.stats)
+        if self.best_E is None or st["min"] < self.best_E:
+            self.best_E = st["min"]
+        out = {"step": self.t, "mean_E": st["mean"], "var_E": st["var"], "min_E": st["min"],
+               "best_E": self.best_E}
+        if self.H.W_tot is not None:
+            out["best_cut"] = (self.H.W_tot - self.best_E) / 2
+            out["mean_cut"] = (self.H.W_tot - st["mean"]) / 2
+        return out
+
+    def evaluate(self, batch: int = 1024) -> dict:
+        """Mean energy of a fresh batch drawn with the evaluation tag (Sec. 5.1: a batch of
+        test samples from the trained model, report their mean energy)."""
+        S, _ = B.sample(self.made, batch, self.seed, self.t, tag=B.TAG_EVAL, want_logp=False)
+        E = B.energy(self.H, S, batch)
+        st, _ = B.batch_stats(E, want_coef=False)
+        d = B.stats_to_dict(st)
+        if self.H.W_tot is not None:
+            d["mean_cut"] = (self.H.W_tot - d["mean"]) / 2
+            d["best_cut"] = (self.H.W_tot - d["min"]) / 2
+        return d
+
+
+def train(trainer: Trainer, steps: int, jsonl: str | None = None, target_cut=None, every: int = 1):
+    """Run ``steps`` iterations; optionally stop at the first step whose best cut reaches
+    ``target_cut`` (hitting-time protocol of Sec. 6: evaluation excluded from timing)."""
+    f = open(jsonl, "a") if jsonl else None
+    wall = 0.0
+    hit = None
+    rec = None
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trainer.step(log=False)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        if (i + 1) % every == 0 or i + 1 == steps or target_cut is not None:
+            st = B.stats_to_dict(trainer.bufs.stats)
+            if trainer.best_E is None or st["min"] < trainer.best_E:
+                trainer.best_E = st["min"]
+            rec = {"step": trainer.t, "wall_s": wall, "mean_E": st["mean"], "var_E": st["var"],
+                   "min_E": st["min"], "best_E": trainer.best_E}
+            if trainer.H.W_tot is not None:
+                rec["best_cut"] = (trainer.H.W_tot - trainer.best_E) / 2
+                rec["mean_cut"] = (trainer.H.W_tot - st["mean"]) / 2
+            if f:
+                f.write(json.dumps(rec) + "\n")
+                f.flush()
+            if target_cut is not None and rec.get("best_cut", -1) >= target_cut and hit is None:
+                hit = rec
+                break
+    if f:
+        f.close()
+    return rec, hit

@@ -1,0 +1,328 @@
+"""GPU <-> oracle parity through the C ABI (runs on an MI355X).
+
+Bars (stated per test): int64 energies bit-exact; Philox uniforms bit-exact; BF16
+rounding bit-exact; logits / log p within a normalised 1e-5 (FP32) or 2e-2 (BF16) of the
+FP64 oracle; sampled spins identical to the oracle's draw on the GPU's own prefix
+wherever |u - p_ref| > 1e-4 (teacher forcing), and free-running strings identical to
+the oracle's when no site is ambiguous."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bf16 as obf16
+from oracle import energy as oen
+from oracle import estimator as oest
+from oracle import made as omade
+from oracle import philox as oph
+from oracle import sampling as osmp
+from paper_2106_13308_amd import inputs
+
+from gpu_util import DEV, build_made, instance, logit_scale, logp_bound, oracle_params, spins_np
+
+pytestmark = pytest.mark.gpu
+
+B_ = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    global B_
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2106_13308_amd import binding
+    B_ = binding
+    yield binding
+
+
+def _banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+# ---------------------------------------------------------------- RNG and packing
+@pytest.mark.parametrize("n,B,seed,step,off,tag", [(10, 7, 2, 0, 0, 0), (1003, 65, 2 ** 40 + 9, 17, 123, 1)])
+def test_device_philox_uniforms_bit_exact(n, B, seed, step, off, tag):
+    _banner(f"uniforms n={n} B={B}")
+    u = B_.uniforms(n, B, seed, step, off, tag).cpu().numpy().astype(np.float64)
+    ref = oph.uniforms(seed, step, np.arange(off, off + B), n, tag)
+    assert np.array_equal(u, ref)
+
+
+@pytest.mark.parametrize("n,h", [(20, 40), (67, 33), (500, 500)])
+def test_pack_unpack_roundtrip(n, h):
+    _banner(f"pack n={n} h={h}")
+    p = inputs.made_init(n, h, 3)
+    M = build_made(p, B_.F32)
+    W1, W2 = M.unpack()
+    M1, M2 = omade.masks(n, p["degrees"])
+    assert np.array_equal(W1.cpu().numpy(), (M1 * p["W1"]).astype(np.float32))
+    assert np.array_equal(W2.cpu().numpy(), (M2 * p["W2"]).astype(np.float32))
+    c = M.c.cpu().numpy()
+    assert c[0] == 0 and c[-1] == h and (np.diff(c) >= 0).all()
+
+
+@pytest.mark.parametrize("n,h", [(20, 40), (130, 70)])
+def test_cast_bf16_bits_and_transpose(n, h):
+    _banner(f"cast n={n} h={h}")
+    p = inputs.made_init(n, h, 4)
+    M = build_made(p, B_.BF16)
+    P32 = M.P32.cpu().numpy()
+    P = M.P.view(torch.int16).cpu().numpy().view(np.uint16)
+    Pt = M.Pt.view(torch.int16).cpu().numpy().view(np.uint16)
+    want = obf16.bf16_bits(P32)
+    assert np.array_equal(P[:, :h], want) and (P[:, h:] == 0).all()
+    assert np.array_equal(Pt[:, :n], want.T) and (Pt[:, n:] == 0).all()
+
+
+# ---------------------------------------------------------------- energy and statistics
+@pytest.mark.parametrize("n,deg,B", [(20, 3, 1024), (500, 0, 4096), (10000, 10, 2048), (37, 4, 5)])
+def test_energy_csr_int_bit_exact(n, deg, B):
+    _banner(f"energy csr int n={n} B={B}")
+    edges = inputs.erdos_renyi_graph(n, 0.02, 0) if deg == 0 else inputs.random_regular_graph(n, deg, 0)
+    w = inputs.integer_weights(len(edges), 1, 5, 1)
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    S_np = inputs.random_spins(B, n, 2)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    E = B_.energy(H, S).cpu().numpy()
+    ref = oen.energy_edges(edges, w, S_np)
+    assert E.dtype == np.int64 and np.array_equal(E, ref)
+    # all-equal strings: E = W_tot
+    S[:] = 0
+    S[:, :n] = 1
+    assert (B_.energy(H, S).cpu().numpy() == int(w.sum())).all()
+
+
+def test_energy_csr_f32_and_dense():
+    _banner("energy csr f32 / dense")
+    n, B = 300, 130
+    edges = inputs.erdos_renyi_graph(n, 0.1, 5)
+    w = np.random.default_rng(1).standard_normal(len(edges)).astype(np.float32)
+    S_np = inputs.random_spins(B, n, 6)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    ref = oen.energy_edges(edges, w, S_np)
+    E = B_.energy(B_.Hamiltonian.from_edges(n, edges, w, device=DEV), S).cpu().numpy()
+    assert np.allclose(E, ref, rtol=0, atol=1e-12 * np.abs(w).sum())
+    J = np.zeros((n, n), np.float32)
+    J[edges[:, 0], edges[:, 1]] = w
+    J[edges[:, 1], edges[:, 0]] = w
+    Ed = B_.energy(B_.Hamiltonian.dense(J, device=DEV), S).cpu().numpy()
+    assert np.allclose(Ed, ref, rtol=0, atol=1e-12 * np.abs(w).sum())
+
+
+@pytest.mark.parametrize("n,B", [(2000, 8192), (70, 33)])
+def test_energy_dense_sk(n, B):
+    _banner(f"energy dense SK n={n} B={B}")
+    J = inputs.sk_couplings(n, 0)
+    S_np = inputs.random_spins(B, n, 3)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    E = B_.energy(B_.Hamiltonian.dense(J, device=DEV), S).cpu().numpy()
+    idx = np.arange(0, B, max(1, B // 256))
+    ref = oen.energy_dense(J, S_np[idx])
+    # FP64 sums of exact products: only the summation order differs
+    bound = 1e-13 * (np.abs(np.triu(J.astype(np.float64), 1)).sum() + 1)
+    assert np.abs(E[idx] - ref).max() <= bound
+
+
+@pytest.mark.parametrize("B", [1, 5, 1024, 4097])
+def test_batch_stats(B):
+    _banner(f"stats B={B}")
+    rng = np.random.default_rng(B)
+    Ei = rng.integers(-5000, 5000, size=B).astype(np.int64)
+    st, coef = B_.batch_stats(torch.from_numpy(Ei).to(DEV))
+    d = B_.stats_to_dict(st)
+    ref = oest.batch_stats(Ei)
+    assert d["mean"] == ref["mean"]          # exact integer sum, one division
+    assert abs(d["var"] - ref["var"]) <= 1e-12 * max(ref["var"], 1)
+    assert d["min"] == ref["min"] and d["argmin"] == ref["argmin"]
+    assert np.allclose(coef.cpu().numpy(), ref["coef"].astype(np.float32), rtol=1e-6, atol=1e-9)
+    Ef = rng.standard_normal(B)
+    st, _ = B_.batch_stats(torch.from_numpy(Ef).to(DEV))
+    d = B_.stats_to_dict(st)
+    ref = oest.batch_stats(Ef)
+    assert abs(d["mean"] - ref["mean"]) <= 1e-14 * (np.abs(Ef).sum() / B + 1)
+    assert abs(d["var"] - ref["var"]) <= 1e-12 * (ref["var"] + 1)
+    assert d["argmin"] == ref["argmin"]
+
+
+# ---------------------------------------------------------------- log p forward
+FWD_CASES = [(20, 40, 64), (67, 33, 100), (130, 200, 65), (500, 500, 256), (2000, 2000, 128), (10000, 1000, 64)]
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", FWD_CASES)
+def test_logprob_and_logits(n, h, B, wd):
+    _banner(f"logprob n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    rtol = 1e-5 if wd == "f32" else 2e-2
+    p, _ = instance(n, h, seed=5, graph=None, scale=2.0)
+    M = build_made(p, wdtype)
+    S_np = inputs.random_spins(B, n, 7)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    lp, Z = B_.logprob(M, S, want_z=True)
+    lp = lp.cpu().numpy().astype(np.float64)
+    Z = Z[:, :n].cpu().numpy().astype(np.float64)
+    q = oracle_params(p, wdtype)
+    f, sc = logit_scale(q, S_np)
+    assert (np.abs(Z - f["Z"]) <= rtol * sc["z"] + 1e-30).all()
+    assert (np.abs(lp - f["logp"]) <= logp_bound(f, S_np, sc["z"], rtol)).all()
+
+
+# ---------------------------------------------------------------- backward
+BWD_CASES = [(20, 40, 64), (67, 33, 100), (500, 500, 512), (2000, 2000, 256), (10000, 1000, 64)]
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", BWD_CASES)
+def test_logprob_backward(n, h, B, wd):
+    _banner(f"backward n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, _ = instance(n, h, seed=6, graph=None, scale=2.0)
+    M = build_made(p, wdtype)
+    S_np = inputs.random_spins(B, n, 8)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    coef = np.random.default_rng(9).standard_normal(B).astype(np.float32) / B
+    dP, db1, db2 = B_.logprob_backward(M, S, torch.from_numpy(coef).to(DEV))
+    dW1, dW2 = M.unpack(dP)
+    q = oracle_params(p, wdtype)
+    g = oest.logp_grad(q, S_np, coef.astype(np.float64))
+    got = {"W1": dW1.cpu().numpy(), "W2": dW2.cpu().numpy(), "b1": db1.cpu().numpy(), "b2": db2.cpu().numpy()}
+    # FP32: each entry is a sum of B products of FP32-accurate factors; BF16 rounds
+    # the activations and adjoints (8 significant bits) before the MFMA products.
+    tol = 2e-5 if wd == "f32" else 3e-2
+    for k in ("W1", "W2", "b1", "b2"):
+        ref = g[k]
+        err = np.abs(got[k] - ref).max()
+        scale = np.abs(ref).max()
+        print(f"  {k}: max err {err:.3e}  max |ref| {scale:.3e}  ratio {err / max(scale, 1e-30):.2e}")
+        assert err <= tol * scale + 1e-12, k
+    # masked entries are exactly zero by layout
+    M1, M2 = omade.masks(n, p["degrees"])
+    assert (got["W1"][M1 == 0] == 0).all() and (got["W2"][M2 == 0] == 0).all()
+
+
+# ---------------------------------------------------------------- sampling
+SAMPLE_CASES = [(20, 40, 1024), (67, 33, 100), (500, 500, 4096), (200, 300, 257), (2, 1, 9), (10000, 1000, 2048)]
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", SAMPLE_CASES)
+def test_sample_incremental_teacher_forced(n, h, B, wd):
+    _banner(f"sample n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, _ = instance(n, h, seed=10, graph=None, scale=3.0)
+    M = build_made(p, wdtype)
+    seed, step = 2, 3
+    S, lp = B_.sample(M, B, seed, step)
+    S_all = S.cpu().numpy()
+    assert (S_all[:, n:] == 0).all()
+    S_np = S_all[:, :n].astype(np.int8)
+    assert np.isin(S_np, [-1, 1]).all()
+    # oracle on a bounded subset at the largest sizes
+    idx = np.arange(B) if n * h * B <= 2e9 else np.linspace(0, B - 1, 24).astype(int)
+    q = oracle_params(p, wdtype)
+    U = oph.uniforms(seed, step, idx, n)
+    mism, amb, pref = osmp.teacher_forced_check(q, S_np[idx], U, 1e-4)
+    print(f"  mismatches {mism}, ambiguous sites {amb} of {U.size}")
+    assert mism == 0
+    f, sc = logit_scale(q, S_np[idx])
+    lpg = lp.cpu().numpy().astype(np.float64)[idx]
+    assert (np.abs(lpg - f["logp"]) <= logp_bound(f, S_np[idx], sc["z"], 1e-5)).all()
+
+
+def test_sample_free_running_equals_oracle_maxcut20():
+    _banner("sample free running n=20")
+    w = inputs.WORKLOADS["maxcut20"]
+    p = inputs.make_instance(w)
+    M = build_made(p, B_.F32)
+    S, lp = B_.sample(M, w.B, 2, 0)
+    S_np = spins_np(S, w.n)
+    U = oph.uniforms(2, 0, np.arange(w.B), w.n)
+    So, lpo = osmp.sample_plain(p, U)
+    pref = omade.conditionals(p, So)
+    clean = (np.abs(U - pref) > 1e-4).all(axis=1)
+    assert clean.mean() > 0.99
+    assert np.array_equal(S_np[clean], So[clean])
+    assert np.allclose(lp.cpu().numpy()[clean], lpo[clean], rtol=1e-5, atol=1e-5)
+
+
+def test_sample_distribution_small_n():
+    """Empirical string frequencies vs the exact pi (total variation)."""
+    _banner("sample distribution n=8")
+    from oracle import exact
+    n, h, B = 8, 12, 1 << 20
+    p = inputs.made_init(n, h, 8)
+    p["W1"] *= 5
+    p["W2"] *= 5
+    M = build_made(p, B_.F32)
+    S, _ = B_.sample(M, B, 31, 0)
+    S_np = spins_np(S, n)
+    idx = ((1 - S_np.astype(np.int64)) // 2) @ (1 << np.arange(n - 1, -1, -1))
+    freq = np.bincount(idx, minlength=2 ** n) / B
+    pi = np.exp(exact.log_probs(p, n))
+    assert 0.5 * np.abs(freq - pi).sum() < 0.01
+
+
+def test_sample_offset_shards_reproduce_full_batch():
+    _banner("sample offset")
+    p, _ = instance(100, 80, seed=3, graph=None, scale=2.0)
+    M = build_made(p, B_.F32)
+    S, lp = B_.sample(M, 64, 5, 1)
+    S2, lp2 = B_.sample(M, 24, 5, 1, offset=40)
+    assert torch.equal(S[40:], S2) and torch.equal(lp[40:], lp2)
+
+
+def test_sample_deterministic():
+    _banner("sample determinism")
+    p, _ = instance(300, 200, seed=3, graph=None, scale=2.0)
+    M = build_made(p, B_.BF16)
+    a = B_.sample(M, 300, 9, 4)
+    b = B_.sample(M, 300, 9, 4)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("n,h,B", [(20, 40, 128), (67, 33, 70), (130, 130, 64)])
+def test_sample_plain_matches_incremental(n, h, B):
+    _banner(f"plain sampler n={n} h={h} B={B}")
+    p, _ = instance(n, h, seed=12, graph=None, scale=3.0)
+    M = build_made(p, B_.F32)
+    Si, lpi = B_.sample(M, B, 4, 2)
+    Sp, lpp = B_.sample_plain(M, B, 4, 2)
+    Sp_np = spins_np(Sp, n)
+    U = oph.uniforms(4, 2, np.arange(B), n)
+    mism, amb, pref = osmp.teacher_forced_check(p, Sp_np, U, 1e-4)
+    assert mism == 0
+    clean = (np.abs(U - pref) > 1e-4).all(axis=1)
+    assert np.array_equal(spins_np(Si, n)[clean], Sp_np[clean])
+    assert np.allclose(lpi.cpu().numpy()[clean], lpp.cpu().numpy()[clean], rtol=1e-5, atol=1e-4)
+
+
+# ---------------------------------------------------------------- the full step
+@pytest.mark.parametrize("algo", [0, 1])
+def test_step_matches_oracle(algo):
+    _banner(f"step algo={algo}")
+    n, h, B = 60, 90, 200
+    p, edges = instance(n, h, seed=13, graph="regular", deg=4, scale=2.0)
+    w = inputs.integer_weights(len(edges), 1, 5, 2)
+    M = build_made(p, B_.F32)
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    bufs = B_.StepBuffers.allocate(M, H, B)
+    B_.step(M, H, B, 7, 11, bufs, algo=algo)
+    S_np = spins_np(bufs.S, n)
+    U = oph.uniforms(7, 11, np.arange(B), n)
+    mism, _, _ = osmp.teacher_forced_check(p, S_np, U, 1e-4)
+    assert mism == 0
+    E = bufs.E.cpu().numpy()
+    assert np.array_equal(E, oen.energy_edges(edges, w, S_np))
+    st = B_.stats_to_dict(bufs.stats)
+    ref = oest.batch_stats(E)
+    assert st["mean"] == ref["mean"] and st["argmin"] == ref["argmin"]
+    g = oest.logp_grad(p, S_np, bufs.coef.cpu().numpy().astype(np.float64))
+    dW1, dW2 = M.unpack(bufs.dP)
+    for k, got in (("W1", dW1), ("W2", dW2), ("b1", bufs.db1), ("b2", bufs.db2)):
+        got = got.cpu().numpy()
+        assert np.abs(got - g[k]).max() <= 2e-5 * np.abs(g[k]).max() + 1e-12, k
