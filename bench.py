@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--workload", default="maxcut10k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 comparison forms")
-    ap.add_argument("--cpu-samples", type=int, default=96)
+    ap.add_argument("--cpu-samples", type=int, default=2048)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--calib-copy", action="store_true",

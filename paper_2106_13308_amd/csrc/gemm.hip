@@ -14,67 +14,71 @@
 // The masks are staircases in (d, k), so every product only visits the K range a
 // tile can see (about half of the dense work) and masks inside the diagonal tiles.
 //
-// Tile engine: 64 x 64 output tile per workgroup of 4 waves (2 x 2 waves of 32 x 32,
-// each 2 x 2 MFMA 16x16 blocks).  Operands are staged through LDS as [row][K] with K
-// contiguous (one 16-byte load per thread per operand per K step).  T = bf16 uses
-// v_mfma_f32_16x16x32_bf16 (BK = 32); T = float uses v_mfma_f32_16x16x4_f32 (BK = 16).
-// Accumulation is always FP32.  Intermediates that a later product contracts over
-// the batch (R, G, S, D) are written batch-contiguous (transposed) by the producing
-// epilogue, which the MFMA accumulator layout makes a contiguous 4-element store.
+// Tile engine: a BM x BN output tile per workgroup of 4 waves (2 x 2 waves of
+// BM/2 x BN/2, each a grid of MFMA 16x16 blocks).  Operands are staged through LDS as
+// [row][K] with K contiguous; the next K step is loaded into registers while the
+// current one is multiplied, with two LDS buffers and one barrier per K step.  T = bf16
+// uses v_mfma_f32_16x16x32_bf16 (BK = 32); T = float uses v_mfma_f32_16x16x4_f32
+// (BK = 16).  Accumulation is always FP32.  Intermediates that a later product
+// contracts over the batch (R, G, S, D) are written batch-contiguous (transposed) by
+// the producing epilogue, which the MFMA accumulator layout makes a 4-element store.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace vqmc {
 
-constexpr int TM = 64, TN = 64;
 constexpr int ROWB = 80;  // LDS row stride in bytes (64 data + 16 pad)
+
+// 16-byte vector of T
+template <typename T>
+struct Vec {
+  T v[16 / sizeof(T)];
+};
 
 template <typename T>
 struct Mfma;
 template <>
 struct Mfma<bf16_t> {
   static constexpr int BK = 32, VEC = 8;
+  template <int FM, int FN>
   __device__ static inline void tile(const uint8_t* As, const uint8_t* Bs, int wm, int wn, int lane,
-                                     floatx4_t acc[2][2]) {
-    bf16x8_t a[2], b[2];
+                                     floatx4_t (&acc)[FM][FN]) {
+    bf16x8_t a[FM], b[FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < FM; ++i)
       a[i] = *(const bf16x8_t*)(As + (wm + i * 16 + (lane & 15)) * ROWB + (lane >> 4) * 16);
-      b[i] = *(const bf16x8_t*)(Bs + (wn + i * 16 + (lane & 15)) * ROWB + (lane >> 4) * 16);
-    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < FN; ++j)
+      b[j] = *(const bf16x8_t*)(Bs + (wn + j * 16 + (lane & 15)) * ROWB + (lane >> 4) * 16);
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 };
 template <>
 struct Mfma<float> {
   static constexpr int BK = 16, VEC = 4;
+  template <int FM, int FN>
   __device__ static inline void tile(const uint8_t* As, const uint8_t* Bs, int wm, int wn, int lane,
-                                     floatx4_t acc[2][2]) {
+                                     floatx4_t (&acc)[FM][FN]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      float a[2], b[2];
+      float a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < FM; ++i)
         a[i] = *(const float*)(As + (wm + i * 16 + (lane & 15)) * ROWB + (q * 4 + (lane >> 4)) * 4);
-        b[i] = *(const float*)(Bs + (wn + i * 16 + (lane & 15)) * ROWB + (q * 4 + (lane >> 4)) * 4);
-      }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < FN; ++j)
+        b[j] = *(const float*)(Bs + (wn + j * 16 + (lane & 15)) * ROWB + (q * 4 + (lane >> 4)) * 4);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-};
-
-// 16-byte vector of VEC elements of T
-template <typename T>
-struct Vec {
-  T v[16 / sizeof(T)];
 };
 
 template <typename T>
@@ -93,13 +97,6 @@ __device__ inline bf16_t spin_val<bf16_t>(int8_t s) {
   return s == 0 ? (bf16_t)0 : (s > 0 ? (bf16_t)0x3F80 : (bf16_t)0xBF80);
 }
 
-__device__ inline void zero_acc(floatx4_t acc[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-}
-
 // number of d in [0, n) with c[d] <= x  (c non-decreasing)
 __device__ inline int count_le(const int32_t* c, int n, int x) {
   int lo = 0, hi = n;
@@ -108,13 +105,6 @@ __device__ inline int count_le(const int32_t* c, int n, int x) {
     if (c[mid] <= x) lo = mid + 1; else hi = mid;
   }
   return lo;
-}
-
-// ---------------------------------------------------------------- stage helpers
-// Thread t stages row r = t/4, element chunk q = (t%4)*VEC of a 64 x BK tile.
-template <typename T>
-__device__ inline void store_lds(uint8_t* tile, int t, const Vec<T>& v) {
-  *(uint4*)(tile + (t >> 2) * ROWB + (t & 3) * 16) = *(const uint4*)&v;
 }
 
 // spins S[b][d0 .. d0+VEC) -> T  (rows b beyond B and sites beyond n read as 0)
@@ -150,6 +140,72 @@ __device__ inline Vec<T> load_rows(const T* X, int64_t ld, int64_t r, int64_t R,
   return out;
 }
 
+template <typename T>
+__device__ inline void store4(T* p, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 2) *(uint2*)p = *(const uint2*)v;
+  else *(uint4*)p = *(const uint4*)v;
+}
+
+// ---------------------------------------------------------------- tile engine
+// Thread t stages rows (t / 4) + 64 v, element chunk (t % 4) * VEC of each operand.
+// LA(row, kq, v) / LB(row, kq, v) return the 16-byte vector of tile row `row` at K
+// index kq (absolute); PRE(k0) runs once per stage before the loads (shared state).
+template <typename T, int BM, int BN>
+struct Engine {
+  static constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
+  static constexpr int FM = BM / 32, FN = BN / 32;
+  static constexpr int AV = BM / 64, BV = BN / 64;
+  static constexpr int STAGE = (BM + BN) * ROWB;
+  static constexpr int SMEM = 2 * STAGE;
+
+  template <class LA, class LB>
+  __device__ static void run(uint8_t* smem, int kbeg, int kend, const LA& la, const LB& lb,
+                             floatx4_t (&acc)[FM][FN]) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
+    const int r0 = t >> 2, q = (t & 3) * VEC;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+    if (kbeg >= kend) return;
+    Vec<T> ra[AV], rb[BV];
+#pragma unroll
+    for (int v = 0; v < AV; ++v) ra[v] = la(r0 + 64 * v, kbeg + q);
+#pragma unroll
+    for (int v = 0; v < BV; ++v) rb[v] = lb(r0 + 64 * v, kbeg + q);
+    auto store = [&](uint8_t* st) {
+#pragma unroll
+      for (int v = 0; v < AV; ++v) *(uint4*)(st + (r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&ra[v];
+#pragma unroll
+      for (int v = 0; v < BV; ++v)
+        *(uint4*)(st + (BM + r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&rb[v];
+    };
+    store(smem);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool nxt = k0 + BK < kend;
+      if (nxt) {
+#pragma unroll
+        for (int v = 0; v < AV; ++v) ra[v] = la(r0 + 64 * v, k0 + BK + q);
+#pragma unroll
+        for (int v = 0; v < BV; ++v) rb[v] = lb(r0 + 64 * v, k0 + BK + q);
+      }
+      const uint8_t* st = smem + cur * STAGE;
+      Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
+      if (nxt) store(smem + (cur ^ 1) * STAGE);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+};
+
+// tile shapes of the four products
+constexpr int H_BM = 128, H_BN = 64;    // hidden-layer products (N = h)
+constexpr int O_BM = 128, O_BN = 128;   // output-layer product (N = n)
+constexpr int W_BM = 128, W_BN = 128;   // weight gradient (M = n, N = h)
+
 // ---------------------------------------------------------------- K1: first layer
 // A = S * P_upper + b1 ; writes R = relu(A) (B x ldh) and optionally Rt (h x ldB).
 template <typename T, bool WRITE_T>
@@ -159,41 +215,33 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
                                                           const int32_t* __restrict__ c, int n, int h,
                                                           int64_t B, T* __restrict__ R, int64_t ldh,
                                                           T* __restrict__ Rt, int64_t ldB) {
-  constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
-  __shared__ __attribute__((aligned(16))) uint8_t As[TM * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ROWB];
+  using E = Engine<T, H_BM, H_BN>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
   __shared__ int kend_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  const int64_t m0 = (int64_t)blockIdx.y * TM;  // samples
-  const int n0 = blockIdx.x * TN;               // units
-  if (t == 0) kend_s = count_le(c, n, n0 + TN - 1);
+  const int wm = (wv >> 1) * (H_BM / 2), wn = (wv & 1) * (H_BN / 2);
+  const int64_t m0 = (int64_t)blockIdx.y * H_BM;  // samples
+  const int n0 = blockIdx.x * H_BN;               // units
+  if (t == 0) kend_s = count_le(c, n, n0 + H_BN - 1);
   __syncthreads();
   const int kend = kend_s;
-  floatx4_t acc[2][2];
-  zero_acc(acc);
-  const int r = t >> 2, q = (t & 3) * VEC;
-  for (int k0 = 0; k0 < kend; k0 += BK) {
-    store_lds<T>(As, t, load_spins<T>(S, lds, m0 + r, B, k0 + q, n));
-    // B operand: Pt[unit][site], kept where c[site] <= unit
-    {
-      const int unit = n0 + r;
-      Vec<T> v = load_rows<T>(Pt, ldn, unit, h, k0 + q, n);
+  auto la = [&](int row, int kq) { return load_spins<T>(S, lds, m0 + row, B, kq, n); };
+  auto lb = [&](int row, int kq) {
+    const int unit = n0 + row;
+    Vec<T> v = load_rows<T>(Pt, ldn, unit, h, kq, n);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int d = k0 + q + e;
-        if (d >= n || c[d] > unit) v.v[e] = (T)0;
-      }
-      store_lds<T>(Bs, t, v);
+    for (int e = 0; e < E::VEC; ++e) {
+      const int d = kq + e;
+      if (d >= n || c[d] > unit) v.v[e] = (T)0;  // unit receives site d iff c[d] <= unit
     }
-    __syncthreads();
-    Mfma<T>::tile(As, Bs, wm, wn, lane, acc);
-    __syncthreads();
-  }
+    return v;
+  };
+  floatx4_t acc[E::FM][E::FN];
+  E::run(smem, 0, kend, la, lb, acc);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < E::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < E::FN; ++j) {
       const int k = n0 + wn + j * 16 + (lane & 15);
       const float bias = (k < h) ? b1[k] : 0.f;
       const int64_t bb = m0 + wm + i * 16 + 4 * (lane >> 4);
@@ -201,18 +249,10 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float a = acc[i][j][e] + bias;
-        vals[e] = from_f32<T>((k < h) ? fmaxf(a, 0.f) : 0.f);
+        vals[e] = from_f32<T>((k < h && bb + e < B) ? fmaxf(a, 0.f) : 0.f);
         if (bb + e < B && k < ldh) R[(bb + e) * ldh + k] = vals[e];
       }
-      if (WRITE_T && k < h) {
-        if (bb + 3 < ldB) {
-          T tmp[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) tmp[e] = (bb + e < B) ? vals[e] : (T)0;
-          if constexpr (sizeof(T) == 2) *(uint2*)(Rt + (int64_t)k * ldB + bb) = *(uint2*)tmp;
-          else *(uint4*)(Rt + (int64_t)k * ldB + bb) = *(uint4*)tmp;
-        }
-      }
+      if (WRITE_T && k < h && bb + 3 < ldB) store4<T>(Rt + (int64_t)k * ldB + bb, vals);
     }
 }
 
@@ -227,49 +267,69 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
     T* __restrict__ G, T* __restrict__ Gt, T* __restrict__ St, int64_t ldB,
     float* __restrict__ db2_part, int dsel, uint64_t seed, uint64_t step, int64_t offset,
     uint32_t tag, float* __restrict__ lp_acc) {
-  constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
-  __shared__ __attribute__((aligned(16))) uint8_t As[TM * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ROWB];
-  __shared__ float rowacc[2][TM];
-  __shared__ float colacc[2][TN];
+  using E = Engine<T, O_BM, O_BN>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
+  __shared__ float rowacc[2][O_BM];
+  __shared__ float colacc[2][O_BN];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  const int64_t m0 = (int64_t)blockIdx.y * TM;                       // samples
-  const int d0 = (MODE == 2) ? (dsel / TN) * TN : blockIdx.x * TN;  // sites
-  const int dlast = min(d0 + TN - 1, n - 1);
-  const int kend = c[dlast];
-  floatx4_t acc[2][2];
-  zero_acc(acc);
-  const int r = t >> 2, q = (t & 3) * VEC;
-  for (int k0 = 0; k0 < kend; k0 += BK) {
-    store_lds<T>(As, t, load_rows<T>(R, ldh, m0 + r, B, k0 + q, h));
-    {
-      const int d = d0 + r;
-      Vec<T> v = load_rows<T>(P, ldh, d, n, k0 + q, h);
-      const int cd = (d < n) ? c[d] : 0;
+  const int wm = (wv >> 1) * (O_BM / 2), wn = (wv & 1) * (O_BN / 2);
+  const int64_t m0 = (int64_t)blockIdx.y * O_BM;                         // samples
+  const int d0 = (MODE == 2) ? (dsel / O_BN) * O_BN : blockIdx.x * O_BN;  // sites
+  const int kend = c[min(d0 + O_BN - 1, n - 1)];
+  auto la = [&](int row, int kq) { return load_rows<T>(R, ldh, m0 + row, B, kq, h); };
+  auto lb = [&](int row, int kq) {
+    const int d = d0 + row;
+    Vec<T> v = load_rows<T>(P, ldh, d, n, kq, h);
+    const int cd = (d < n) ? c[d] : 0;
 #pragma unroll
-      for (int e = 0; e < VEC; ++e)
-        if (k0 + q + e >= cd) v.v[e] = (T)0;
-      store_lds<T>(Bs, t, v);
+    for (int e = 0; e < E::VEC; ++e)
+      if (kq + e >= cd) v.v[e] = (T)0;  // unit k feeds site d iff k < c[d]
+    return v;
+  };
+  floatx4_t acc[E::FM][E::FN];
+  E::run(smem, 0, kend, la, lb, acc);
+  if constexpr (MODE == 2) {
+    // draw s_d for d = dsel from sigma(z_d): the lanes holding column dsel park the
+    // logits in LDS, then one thread per sample draws
+    const int col = dsel - d0 - wn;  // column inside this wave's sub-tile
+    if (col >= 0 && col < O_BN / 2 && (col & 15) == (lane & 15)) {
+#pragma unroll
+      for (int j = 0; j < E::FN; ++j)
+        if (j == (col >> 4)) {
+#pragma unroll
+          for (int i = 0; i < E::FM; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rowacc[0][wm + i * 16 + 4 * (lane >> 4) + e] = acc[i][j][e];
+        }
     }
     __syncthreads();
-    Mfma<T>::tile(As, Bs, wm, wn, lane, acc);
-    __syncthreads();
+    if (t < O_BM && m0 + t < B) {
+      const int64_t b = m0 + t;
+      const float z = rowacc[0][t] + b2[dsel];
+      const float4 u4 = site_uniforms(seed, step, tag, (uint64_t)(b + offset), (uint32_t)(dsel >> 2));
+      const int w = dsel & 3;
+      const float u = w == 0 ? u4.x : (w == 1 ? u4.y : (w == 2 ? u4.z : u4.w));
+      const float sg = (u < sigmoid(z)) ? 1.f : -1.f;
+      S[b * lds + dsel] = (int8_t)sg;
+      lp_acc[b] += log_sigmoid(sg * z);
+    }
+    return;
   }
-  float rs[2][4];
-  float cs[2];
+  float rs[E::FM][4];
+  float cs[E::FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < E::FM; ++i)
 #pragma unroll
     for (int e = 0; e < 4; ++e) rs[i][e] = 0.f;
-  cs[0] = cs[1] = 0.f;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < E::FN; ++j) cs[j] = 0.f;
+#pragma unroll
+  for (int j = 0; j < E::FN; ++j) {
     const int d = d0 + wn + j * 16 + (lane & 15);
     const bool dv = d < n;
     const float bias = dv ? b2[d] : 0.f;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < E::FM; ++i) {
       const int64_t bb = m0 + wm + i * 16 + 4 * (lane >> 4);
       T gv[4], sv[4];
 #pragma unroll
@@ -277,17 +337,6 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
         const int64_t b = bb + e;
         const bool ok = dv && b < B;
         const float z = acc[i][j][e] + bias;
-        if (MODE == 2) {
-          if (ok && d == dsel) {
-            const float4 u4 = site_uniforms(seed, step, tag, (uint64_t)(b + offset), (uint32_t)(d >> 2));
-            const int w = d & 3;
-            const float u = w == 0 ? u4.x : (w == 1 ? u4.y : (w == 2 ? u4.z : u4.w));
-            const float sg = (u < sigmoid(z)) ? 1.f : -1.f;
-            S[b * lds + d] = (int8_t)sg;
-            lp_acc[b] += log_sigmoid(sg * z);
-          }
-          continue;
-        }
         const float s = ok ? (float)S[b * lds + d] : 0.f;
         const float tt = s * z;
         if (ok) rs[i][e] += log_sigmoid(tt);
@@ -301,20 +350,14 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
         }
       }
       if (MODE == 1 && d < n && bb + 3 < ldB) {
-        if constexpr (sizeof(T) == 2) {
-          *(uint2*)(Gt + (int64_t)d * ldB + bb) = *(uint2*)gv;
-          *(uint2*)(St + (int64_t)d * ldB + bb) = *(uint2*)sv;
-        } else {
-          *(uint4*)(Gt + (int64_t)d * ldB + bb) = *(uint4*)gv;
-          *(uint4*)(St + (int64_t)d * ldB + bb) = *(uint4*)sv;
-        }
+        store4<T>(Gt + (int64_t)d * ldB + bb, gv);
+        store4<T>(St + (int64_t)d * ldB + bb, sv);
       }
     }
   }
-  if (MODE == 2) return;
   // row sums of log sigma over this tile's sites (16-lane rows, then the two wn waves)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < E::FM; ++i)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       float v = rs[i][e];
@@ -326,14 +369,14 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
     }
   if ((lane & 15) == 0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < E::FM; ++i)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) rowacc[wn >> 5][wm + i * 16 + 4 * (lane >> 4) + e] = rs[i][e];
+      for (int e = 0; e < 4; ++e) rowacc[wv & 1][wm + i * 16 + 4 * (lane >> 4) + e] = rs[i][e];
   }
   if (MODE == 1) {
     // column sums of G over this tile's samples
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < E::FN; ++j) {
       float v = cs[j];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
@@ -341,16 +384,17 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
     }
     if (lane < 16) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) colacc[wm >> 5][wn + j * 16 + lane] = cs[j];
+      for (int j = 0; j < E::FN; ++j) colacc[wv >> 1][wn + j * 16 + lane] = cs[j];
     }
   }
   __syncthreads();
-  if (t < TM) {
+  if (t < O_BM) {
     const int64_t b = m0 + t;
     if (b < B) lp_part[(int64_t)blockIdx.x * B + b] = rowacc[0][t] + rowacc[1][t];
-  } else if (MODE == 1 && t < TM + TN) {
-    const int d = d0 + (t - TM);
-    if (d < ldn) db2_part[(int64_t)blockIdx.y * ldn + d] = colacc[0][t - TM] + colacc[1][t - TM];
+  } else if (MODE == 1) {
+    const int dl = t - O_BM;
+    const int d = d0 + dl;
+    if (dl < O_BN && d < ldn) db2_part[(int64_t)blockIdx.y * ldn + d] = colacc[0][dl] + colacc[1][dl];
   }
 }
 
@@ -363,43 +407,38 @@ __global__ __launch_bounds__(256) void bwd_hidden_kernel(const T* __restrict__ G
                                                           int64_t B, const T* __restrict__ Rt,
                                                           T* __restrict__ Dt, int64_t ldB,
                                                           float* __restrict__ db1_part, int64_t ldh) {
-  constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
-  __shared__ __attribute__((aligned(16))) uint8_t As[TM * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ROWB];
-  __shared__ float colacc[2][TN];
+  using E = Engine<T, H_BM, H_BN>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
+  __shared__ float colacc[2][H_BN];
   __shared__ int kbeg_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  const int64_t m0 = (int64_t)blockIdx.y * TM;  // samples
-  const int n0 = blockIdx.x * TN;               // units
-  if (t == 0) kbeg_s = count_le(c, n, n0);      // first site with c[d] > n0
+  const int wm = (wv >> 1) * (H_BM / 2), wn = (wv & 1) * (H_BN / 2);
+  const int64_t m0 = (int64_t)blockIdx.y * H_BM;  // samples
+  const int n0 = blockIdx.x * H_BN;               // units
+  if (t == 0) kbeg_s = count_le(c, n, n0);        // first site with c[d] > n0
   __syncthreads();
-  const int kbeg = (kbeg_s / BK) * BK;
-  floatx4_t acc[2][2];
-  zero_acc(acc);
-  const int r = t >> 2, q = (t & 3) * VEC;
-  for (int k0 = kbeg; k0 < n; k0 += BK) {
-    store_lds<T>(As, t, load_rows<T>(G, ldn, m0 + r, B, k0 + q, n));
-    {
-      const int unit = n0 + r;
-      Vec<T> v = load_rows<T>(Pt, ldn, unit, h, k0 + q, n);
+  const int kbeg = (kbeg_s / E::BK) * E::BK;
+  auto la = [&](int row, int kq) { return load_rows<T>(G, ldn, m0 + row, B, kq, n); };
+  auto lb = [&](int row, int kq) {
+    const int unit = n0 + row;
+    Vec<T> v = load_rows<T>(Pt, ldn, unit, h, kq, n);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int d = k0 + q + e;
-        if (d >= n || c[d] <= unit) v.v[e] = (T)0;
-      }
-      store_lds<T>(Bs, t, v);
+    for (int e = 0; e < E::VEC; ++e) {
+      const int d = kq + e;
+      if (d >= n || c[d] <= unit) v.v[e] = (T)0;  // unit feeds site d iff unit < c[d]
     }
-    __syncthreads();
-    Mfma<T>::tile(As, Bs, wm, wn, lane, acc);
-    __syncthreads();
-  }
-  float cs[2] = {0.f, 0.f};
+    return v;
+  };
+  floatx4_t acc[E::FM][E::FN];
+  E::run(smem, kbeg, n, la, lb, acc);
+  float cs[E::FN];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < E::FN; ++j) cs[j] = 0.f;
+#pragma unroll
+  for (int j = 0; j < E::FN; ++j) {
     const int k = n0 + wn + j * 16 + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < E::FM; ++i) {
       const int64_t bb = m0 + wm + i * 16 + 4 * (lane >> 4);
       if (k < h && bb + 3 < ldB) {
         T rv[4], dvv[4];
@@ -411,13 +450,12 @@ __global__ __launch_bounds__(256) void bwd_hidden_kernel(const T* __restrict__ G
           cs[j] += dl;
           dvv[e] = from_f32<T>(dl);
         }
-        if constexpr (sizeof(T) == 2) *(uint2*)(Dt + (int64_t)k * ldB + bb) = *(uint2*)dvv;
-        else *(uint4*)(Dt + (int64_t)k * ldB + bb) = *(uint4*)dvv;
+        store4<T>(Dt + (int64_t)k * ldB + bb, dvv);
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < E::FN; ++j) {
     float v = cs[j];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
@@ -425,62 +463,45 @@ __global__ __launch_bounds__(256) void bwd_hidden_kernel(const T* __restrict__ G
   }
   if (lane < 16) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) colacc[wm >> 5][wn + j * 16 + lane] = cs[j];
+    for (int j = 0; j < E::FN; ++j) colacc[wv >> 1][wn + j * 16 + lane] = cs[j];
   }
   __syncthreads();
-  if (t < TN) {
+  if (t < H_BN) {
     const int k = n0 + t;
     if (k < ldh) db1_part[(int64_t)blockIdx.y * ldh + k] = colacc[0][t] + colacc[1][t];
   }
 }
 
 // ---------------------------------------------------------------- K4: weight gradient
-// dP[d][k] = sum_b Gt[d][b] Rt[k][b]  (k < c[d])  or  sum_b St[d][b] Dt[k][b]  (k >= c[d]).
-template <typename T>
-__global__ __launch_bounds__(256) void bwd_weight_kernel(const T* __restrict__ Gt, const T* __restrict__ St,
-                                                          const T* __restrict__ Rt,
-                                                          const T* __restrict__ Dt, int64_t ldB,
-                                                          const int32_t* __restrict__ c, int n, int h,
-                                                          float* __restrict__ dP) {
-  constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
-  __shared__ __attribute__((aligned(16))) uint8_t As[TM * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t As2[TM * ROWB];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs2[TN * ROWB];
+// UPPER = false: dP[d][k] = sum_b Gt[d][b] Rt[k][b] where k < c[d]   (dF/dW2)
+// UPPER = true:  dP[d][k] = sum_b St[d][b] Dt[k][b] where k >= c[d]  (dF/dW1)
+// Tiles without any element of their half return at once.
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(256) void bwd_weight_kernel(const T* __restrict__ X, const T* __restrict__ Y,
+                                                          int64_t ldB, const int32_t* __restrict__ c,
+                                                          int n, int h, float* __restrict__ dP) {
+  using E = Engine<T, W_BM, W_BN>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  const int d0 = blockIdx.y * TM;  // sites
-  const int k0u = blockIdx.x * TN; // units
-  const int dlast = min(d0 + TM - 1, n - 1);
-  const bool lower = k0u < c[dlast];           // some (d, k) with k < c[d]
-  const bool upper = k0u + TN - 1 >= c[d0];    // some (d, k) with k >= c[d]
-  floatx4_t accL[2][2], accU[2][2];
-  zero_acc(accL);
-  zero_acc(accU);
-  const int r = t >> 2, q = (t & 3) * VEC;
-  for (int kb = 0; kb < ldB; kb += BK) {
-    if (lower) {
-      store_lds<T>(As, t, load_rows<T>(Gt, ldB, d0 + r, n, kb + q, (int)ldB));
-      store_lds<T>(Bs, t, load_rows<T>(Rt, ldB, k0u + r, h, kb + q, (int)ldB));
-    }
-    if (upper) {
-      store_lds<T>(As2, t, load_rows<T>(St, ldB, d0 + r, n, kb + q, (int)ldB));
-      store_lds<T>(Bs2, t, load_rows<T>(Dt, ldB, k0u + r, h, kb + q, (int)ldB));
-    }
-    __syncthreads();
-    if (lower) Mfma<T>::tile(As, Bs, wm, wn, lane, accL);
-    if (upper) Mfma<T>::tile(As2, Bs2, wm, wn, lane, accU);
-    __syncthreads();
-  }
+  const int wm = (wv >> 1) * (W_BM / 2), wn = (wv & 1) * (W_BN / 2);
+  const int d0 = blockIdx.y * W_BM;   // sites
+  const int k0u = blockIdx.x * W_BN;  // units
+  const int dlast = min(d0 + W_BM - 1, n - 1);
+  const bool any = UPPER ? (k0u + W_BN - 1 >= c[d0]) : (k0u < c[dlast]);
+  if (!any) return;
+  auto la = [&](int row, int kq) { return load_rows<T>(X, ldB, d0 + row, n, kq, (int)ldB); };
+  auto lb = [&](int row, int kq) { return load_rows<T>(Y, ldB, k0u + row, h, kq, (int)ldB); };
+  floatx4_t acc[E::FM][E::FN];
+  E::run(smem, 0, (int)ldB, la, lb, acc);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < E::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < E::FN; ++j) {
       const int k = k0u + wn + j * 16 + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int d = d0 + wm + i * 16 + 4 * (lane >> 4) + e;
-        if (d < n && k < h) dP[(int64_t)d * h + k] = (k < c[d]) ? accL[i][j][e] : accU[i][j][e];
+        if (d < n && k < h && (UPPER ? (k >= c[d]) : (k < c[d]))) dP[(int64_t)d * h + k] = acc[i][j][e];
       }
     }
 }
@@ -506,14 +527,38 @@ __global__ void fill_i8_kernel(int8_t* __restrict__ x, int64_t len) {
 }
 
 // ---------------------------------------------------------------- workspace layout
+struct Geom {
+  int n, h;
+  int64_t B, ldh, ldn, ldB;
+  int mt_h, nt_h;   // hidden-layer grid: M tiles (batch) x N tiles (units)
+  int mt_o, nt_o;   // output-layer grid: M tiles (batch) x N tiles (sites)
+  int mt_w, nt_w;   // weight-gradient grid: M tiles (sites) x N tiles (units)
+};
+
+static Geom geom(int n, int h, int64_t B) {
+  Geom g;
+  g.n = n;
+  g.h = h;
+  g.B = B;
+  g.ldh = round_up(h, kPad);
+  g.ldn = round_up(n, kPad);
+  g.ldB = round_up(B, kPad);
+  g.mt_h = (int)((g.ldB + H_BM - 1) / H_BM);
+  g.nt_h = (int)((g.ldh + H_BN - 1) / H_BN);
+  g.mt_o = (int)((g.ldB + O_BM - 1) / O_BM);
+  g.nt_o = (int)((g.ldn + O_BN - 1) / O_BN);
+  g.mt_w = (int)((g.ldn + W_BM - 1) / W_BM);
+  g.nt_w = (int)((g.ldh + W_BN - 1) / W_BN);
+  return g;
+}
+
 struct WsLayout {
   size_t R, Rt, G, Gt, St, Dt, lp_part, db2_part, db1_part, lp_acc, total;
 };
 
 static WsLayout layout(int n, int h, int64_t B, int dtype, int which) {
   const size_t es = (dtype == VQMC_BF16) ? 2 : 4;
-  const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad), ldB = round_up(B, kPad);
-  const int64_t ntile_n = ldn / TN, ntile_b = ldB / TM;
+  const Geom g = geom(n, h, B);
   WsLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -521,16 +566,16 @@ static WsLayout layout(int n, int h, int64_t B, int dtype, int which) {
     off += round_up((int64_t)bytes, 256);
     return o;
   };
-  L.R = take((size_t)B * ldh * es);
-  L.lp_part = take((size_t)ntile_n * B * 4);
+  L.R = take((size_t)B * g.ldh * es);
+  L.lp_part = take((size_t)g.nt_o * B * 4);
   if (which == 1) {  // backward
-    L.Rt = take((size_t)h * ldB * es);
-    L.G = take((size_t)B * ldn * es);
-    L.Gt = take((size_t)n * ldB * es);
-    L.St = take((size_t)n * ldB * es);
-    L.Dt = take((size_t)h * ldB * es);
-    L.db2_part = take((size_t)ntile_b * ldn * 4);
-    L.db1_part = take((size_t)ntile_b * ldh * 4);
+    L.Rt = take((size_t)h * g.ldB * es);
+    L.G = take((size_t)B * g.ldn * es);
+    L.Gt = take((size_t)n * g.ldB * es);
+    L.St = take((size_t)n * g.ldB * es);
+    L.Dt = take((size_t)h * g.ldB * es);
+    L.db2_part = take((size_t)g.mt_o * g.ldn * 4);
+    L.db1_part = take((size_t)g.mt_h * g.ldh * 4);
   }
   if (which == 2) L.lp_acc = take((size_t)B * 4);  // plain sampler
   L.total = off;
@@ -545,32 +590,28 @@ size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype) { return layout
 template <typename T>
 static hipError_t logprob_t(const vqmc_made& m, const int8_t* S, int64_t B, float* logp, float* Z,
                             void* ws, hipStream_t st) {
-  const int n = m.n, h = m.h;
-  const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad), ldB = round_up(B, kPad);
-  const WsLayout L = layout(n, h, B, m.wdtype, 0);
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 0);
   uint8_t* w = (uint8_t*)ws;
   T* R = (T*)(w + L.R);
   float* lp_part = (float*)(w + L.lp_part);
-  dim3 g1((unsigned)(ldh / TN), (unsigned)(ldB / TM));
-  fwd_hidden_kernel<T, false><<<g1, 256, 0, st>>>(S, ldn, (const T*)m.Pt, ldn, m.b1, m.c, n, h, B, R,
-                                                  ldh, nullptr, ldB);
+  fwd_hidden_kernel<T, false><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1,
+                                                                     m.c, m.n, m.h, B, R, g.ldh, nullptr, g.ldB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 g2((unsigned)(ldn / TN), (unsigned)(ldB / TM));
-  fwd_out_kernel<T, 0><<<g2, 256, 0, st>>>(R, ldh, (const T*)m.P, m.b2, m.c, n, h, B, (int8_t*)S, ldn,
-                                           ldn, lp_part, Z, nullptr, nullptr, nullptr, nullptr, ldB,
-                                           nullptr, 0, 0, 0, 0, 0, nullptr);
+  fwd_out_kernel<T, 0><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, Z, nullptr, nullptr,
+      nullptr, nullptr, g.ldB, nullptr, 0, 0, 0, 0, 0, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  sum_rows_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(lp_part, (int)(ldn / TN), B, B, logp);
+  sum_rows_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(lp_part, g.nt_o, B, B, logp);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
                              float* dP, float* db1, float* db2, void* ws, hipStream_t st) {
-  const int n = m.n, h = m.h;
-  const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad), ldB = round_up(B, kPad);
-  const WsLayout L = layout(n, h, B, m.wdtype, 1);
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
   uint8_t* w = (uint8_t*)ws;
   T* R = (T*)(w + L.R);
   T* Rt = (T*)(w + L.Rt);
@@ -582,25 +623,23 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
   float* db2_part = (float*)(w + L.db2_part);
   float* db1_part = (float*)(w + L.db1_part);
   hipError_t e;
-  dim3 g1((unsigned)(ldh / TN), (unsigned)(ldB / TM));
-  fwd_hidden_kernel<T, true><<<g1, 256, 0, st>>>(S, ldn, (const T*)m.Pt, ldn, m.b1, m.c, n, h, B, R, ldh,
-                                                 Rt, ldB);
+  fwd_hidden_kernel<T, true><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c,
+                                                                    m.n, m.h, B, R, g.ldh, Rt, g.ldB);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 g2((unsigned)(ldn / TN), (unsigned)(ldB / TM));
-  fwd_out_kernel<T, 1><<<g2, 256, 0, st>>>(R, ldh, (const T*)m.P, m.b2, m.c, n, h, B, (int8_t*)S, ldn,
-                                           ldn, lp_part, nullptr, coef, G, Gt, St, ldB, db2_part, 0, 0, 0,
-                                           0, 0, nullptr);
+  fwd_out_kernel<T, 1><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, nullptr, coef, G, Gt,
+      St, g.ldB, db2_part, 0, 0, 0, 0, 0, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 g3((unsigned)(ldh / TN), (unsigned)(ldB / TM));
-  bwd_hidden_kernel<T><<<g3, 256, 0, st>>>(G, ldn, (const T*)m.Pt, m.c, n, h, B, Rt, Dt, ldB, db1_part,
-                                           ldh);
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 g4((unsigned)(ldh / TN), (unsigned)(ldn / TM));
-  bwd_weight_kernel<T><<<g4, 256, 0, st>>>(Gt, St, Rt, Dt, ldB, m.c, n, h, dP);
+  bwd_weight_kernel<T, false><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(Gt, Rt, g.ldB, m.c, m.n, m.h, dP);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  sum_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(db2_part, (int)(ldB / TM), ldn, n, db2);
+  bwd_weight_kernel<T, true><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(St, Dt, g.ldB, m.c, m.n, m.h, dP);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  sum_rows_kernel<<<(unsigned)((h + 255) / 256), 256, 0, st>>>(db1_part, (int)(ldB / TM), ldh, h, db1);
+  sum_rows_kernel<<<(unsigned)((m.n + 255) / 256), 256, 0, st>>>(db2_part, g.mt_o, g.ldn, m.n, db2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  sum_rows_kernel<<<(unsigned)((m.h + 255) / 256), 256, 0, st>>>(db1_part, g.mt_h, g.ldh, m.h, db1);
   return hipGetLastError();
 }
 
@@ -608,27 +647,26 @@ template <typename T>
 static hipError_t sample_plain_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                  int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,
                                  hipStream_t st) {
-  const int n = m.n, h = m.h;
-  const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad), ldB = round_up(B, kPad);
-  const WsLayout L = layout(n, h, B, m.wdtype, 2);
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 2);
   uint8_t* w = (uint8_t*)ws;
   T* R = (T*)(w + L.R);
   float* lp_acc = (float*)(w + L.lp_acc);
   hipError_t e;
   // Algorithm 1's initial state: unsampled sites are never read (masks); start from 0.
-  fill_i8_kernel<<<(unsigned)((B * ldn + 255) / 256), 256, 0, st>>>(S, B * ldn);
+  fill_i8_kernel<<<(unsigned)((B * g.ldn + 255) / 256), 256, 0, st>>>(S, B * g.ldn);
   fill_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(lp_acc, B, 0.f);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 g1((unsigned)(ldh / TN), (unsigned)(ldB / TM));
-  dim3 g2(1, (unsigned)(ldB / TM));
-  for (int d = 0; d < n; ++d) {
+  for (int d = 0; d < m.n; ++d) {
     // forward pass d over the partially drawn batch ...
-    fwd_hidden_kernel<T, false><<<g1, 256, 0, st>>>(S, ldn, (const T*)m.Pt, ldn, m.b1, m.c, n, h, B, R,
-                                                    ldh, nullptr, ldB);
+    fwd_hidden_kernel<T, false><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1,
+                                                                       m.c, m.n, m.h, B, R, g.ldh, nullptr,
+                                                                       g.ldB);
     // ... then the output layer for the tile holding site d, and the draw of s_d
-    fwd_out_kernel<T, 2><<<g2, 256, 0, st>>>(R, ldh, (const T*)m.P, m.b2, m.c, n, h, B, S, ldn, ldn,
-                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ldB,
-                                             nullptr, d, seed, step, offset, tag, lp_acc);
+    fwd_out_kernel<T, 2><<<dim3(1, g.mt_o), 256, 0, st>>>(R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, S,
+                                                          g.ldn, g.ldn, nullptr, nullptr, nullptr, nullptr,
+                                                          nullptr, nullptr, g.ldB, nullptr, d, seed, step,
+                                                          offset, tag, lp_acc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (logp) return hipMemcpyAsync(logp, lp_acc, (size_t)B * 4, hipMemcpyDeviceToDevice, st);

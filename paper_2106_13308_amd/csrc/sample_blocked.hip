@@ -1,0 +1,364 @@
+// Blocked incremental sampler (Algorithm 1 of the paper, with the per-site forward
+// pass replaced by an incremental update of the hidden pre-activations).
+//
+// Notation: packed weights P[d][k] (k < c[d]: W2[d][k]; k >= c[d]: W1[k][d]), state
+// A[s][k] = b1[k] + sum_{received sites d'} s_d' P[d'][k] of each sample s.  Site d is
+//   z_d = b2[d] + sum_{k < c[d]} P[d][k] relu(A[k]),  s_d = +1 iff u < sigma(z_d)
+// and afterwards every unit k >= c[d] adds s_d P[d][k].
+//
+// Sites are processed in blocks [d0, d1) of at most 64 sites.  With c0 = c[d0] and
+// c1 = c[d1-1]:
+//  phase 1  units k < c0 are complete before the block starts, so their whole
+//           contribution to every site of the block is one product
+//           Zp[d][s] = b2[d] + sum_{k<c0} P[d][k] relu(A[s][k])           (MFMA)
+//  phase 2  the units [c0, c1) complete inside the block; they are the only serial
+//           part.  The block is split into runs of consecutive sites with equal c[d];
+//           the sites of a run depend only on units already complete, so a whole run
+//           is decided at once, then the in-block units receive the run's spins, and
+//           the units completing after the run add their contribution to the pending
+//           sites.
+//  phase 3  units k >= c1 receive the block's spins in one rank-T update
+//           A[s][k] += sum_{d in block} s_d P[d][k]                       (MFMA)
+// In exact arithmetic this is the same sequence of conditionals as n full forward
+// passes.
+//
+// Arithmetic: the state is FP32.  With BF16 weights both products run on
+// v_mfma_f32_16x16x32_bf16: phase 3 multiplies exact +-1 spins by BF16 weights, and
+// phase 1 splits each FP32 activation into three BF16 terms (hi + mid + lo represents
+// it exactly), so both are FP32-accurate.  With FP32 weights phase 1 uses
+// v_mfma_f32_16x16x4_f32 and phase 3 splits the weights into three BF16 terms.
+// The Bernoulli draw compares z with logit(u), which is the draw u < sigma(z).
+//
+// One workgroup (4 waves) owns 16 samples; the state lives in LDS as [16][LDA] floats.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace vqmc {
+
+constexpr int SB_MS = 16;   // samples per workgroup
+constexpr int SB_T = 64;    // max sites per block
+constexpr int SB_UB = 32;   // in-block units whose weights are staged in LDS
+
+__host__ __device__ inline int sb_lda(int h) { return (int)round_up(h, 32) + 4; }
+
+__host__ inline size_t sb_smem_bytes(int h) {
+  const size_t st = (size_t)SB_MS * sb_lda(h) * 4;
+  const size_t red = 2 * SB_T * SB_MS * 4;
+  const size_t zp = SB_MS * SB_T * 4, thr = SB_MS * SB_T * 4;
+  const size_t pb = SB_T * SB_UB * 4;
+  const size_t sbk = SB_MS * SB_T, cb = (SB_T + 4) * 4;
+  return st + red + zp + thr + pb + sbk + cb;
+}
+
+// exact 3-term BF16 split of 8 floats
+__device__ inline void split3(const float r[8], bf16x8_t& hi, bf16x8_t& mid, bf16x8_t& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const bf16_t h = f32_to_bf16(r[e]);
+    const float r1 = r[e] - bf16_to_f32(h);
+    const bf16_t m = f32_to_bf16(r1);
+    const float r2 = r1 - bf16_to_f32(m);
+    const bf16_t l = f32_to_bf16(r2);
+    hi[e] = __builtin_bit_cast(__bf16, h);
+    mid[e] = __builtin_bit_cast(__bf16, m);
+    lo[e] = __builtin_bit_cast(__bf16, l);
+  }
+}
+
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline bf16x8_t load_bf16x8(const bf16_t* p) {
+  return __builtin_bit_cast(bf16x8_t, *(const uint4*)p);
+}
+__device__ inline void load_bf16x4x2(const bf16_t* p0, const bf16_t* p1, bf16x8_t& out) {
+  const uint2 a = *(const uint2*)p0, b = *(const uint2*)p1;
+  out = __builtin_bit_cast(bf16x8_t, make_uint4(a.x, a.y, b.x, b.y));
+}
+
+template <typename WT>
+__global__ __launch_bounds__(256) void sample_blocked_kernel(
+    const WT* __restrict__ P, const WT* __restrict__ Pt, int64_t ldh, int64_t ldn,
+    const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
+    int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
+    int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  float* st = (float*)smem;                 // [16][LDA]   state A
+  float* red = st + SB_MS * LDA;            // [2][64][16] phase-1 partials
+  float* zp = red + 2 * SB_T * SB_MS;       // [16][64]    running logits of the block
+  float* thr = zp + SB_MS * SB_T;           // [16][64]    logit(u); then s*z
+  float* pb = thr + SB_MS * SB_T;           // [64][UB]    P[d0+j][c0+u]
+  int8_t* sbk = (int8_t*)(pb + SB_T * SB_UB);  // [16][64] spins of the block
+  int* cb = (int*)(sbk + SB_MS * SB_T);     // [65]        c[d0+j], sentinel c1
+
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t b0 = (int64_t)blockIdx.x * SB_MS;
+
+  for (int i = t; i < SB_MS * LDA; i += 256) {
+    const int k = i % LDA;
+    st[i] = (k < h) ? b1[k] : 0.f;
+  }
+  float lp_part = 0.f;
+  __syncthreads();
+
+  for (int d0 = 0; d0 < n;) {
+    // ---------------- block bounds (uniform)
+    const int c0 = c[d0];
+    int d1 = min(d0 + SB_T, n);
+    while (d1 - d0 > 8 && c[d1 - 1] - c0 > SB_UB) d1 = d0 + ((d1 - d0 - 1) >> 3) * 8;
+    const int Tb = d1 - d0;
+    const int c1 = c[d1 - 1];
+    const int U = c1 - c0;
+    const bool fastpb = U <= SB_UB;
+
+    // ---------------- staging (no conflict with phase 1)
+    if (t < Tb) cb[t] = c[d0 + t];
+    if (t == 0) cb[Tb] = c1;
+    {
+      const int s = t >> 4, q4 = t & 15;  // 16 samples x 16 groups of 4 sites
+      if (4 * q4 < Tb) {
+        const float4 u4 = site_uniforms(seed, step, tag, (uint64_t)(b0 + s + offset), (uint32_t)((d0 >> 2) + q4));
+        const float uv[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float u = uv[e];
+          // s = +1 iff u < sigma(z) iff z > log(u) - log(1-u); u = 0 gives -inf (always +1)
+          thr[s * SB_T + 4 * q4 + e] = __logf(u) - log1pf(-u);
+        }
+      }
+    }
+    if (fastpb) {
+      for (int i = t; i < Tb * U; i += 256) {
+        const int j = i / U, uu = i % U;
+        pb[j * SB_UB + uu] = to_f32(P[(int64_t)(d0 + j) * ldh + c0 + uu]);
+      }
+    }
+
+    // ---------------- phase 1: Zp = relu(A[:, :c0]) P[block, :c0]^T
+    {
+      const int kh = wv & 1, mh = wv >> 1;
+      floatx4_t acc[2];
+      acc[0] = acc[1] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+      if constexpr (sizeof(WT) == 2) {
+        const int nchunk = (c0 + 31) >> 5;
+        for (int ch = kh; ch < nchunk; ch += 2) {
+          const int k0 = ch * 32;
+          const float* srow = st + l16 * LDA + k0 + 4 * g;
+          const float4 ra = *(const float4*)srow;
+          const float4 rb = *(const float4*)(srow + 16);
+          float r[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int kk = k0 + 4 * g + (e & 3) + ((e >> 2) << 4);
+            r[e] = (kk < c0) ? fmaxf(r[e], 0.f) : 0.f;
+          }
+          bf16x8_t hi, mid, lo;
+          split3(r, hi, mid, lo);
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const int d = d0 + 32 * mh + 16 * mt + l16;
+            bf16x8_t a;
+            if (d < n) {
+              const bf16_t* prow = (const bf16_t*)P + (int64_t)d * ldh + k0 + 4 * g;
+              load_bf16x4x2(prow, prow + 16, a);
+            } else {
+              a = __builtin_bit_cast(bf16x8_t, make_uint4(0, 0, 0, 0));
+            }
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc[mt], 0, 0, 0);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, mid, acc[mt], 0, 0, 0);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc[mt], 0, 0, 0);
+          }
+        }
+      } else {
+        const int nchunk = (c0 + 3) >> 2;
+        for (int ch = kh; ch < nchunk; ch += 2) {
+          const int k = ch * 4 + g;
+          const float r = (k < c0) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const int d = d0 + 32 * mh + 16 * mt + l16;
+            const float a = (d < n && k < c0) ? ((const float*)P)[(int64_t)d * ldh + k] : 0.f;
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r, acc[mt], 0, 0, 0);
+          }
+        }
+      }
+      // C layout: lane l holds rows (sites) 4*(l/16)+e, column (sample) l%16
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 32 * mh + 16 * mt + 4 * g + e;
+          red[(kh * SB_T + j) * SB_MS + l16] = acc[mt][e];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      const int j = idx >> 4, s = idx & 15;
+      if (j < Tb) zp[s * SB_T + j] = red[j * SB_MS + s] + red[(SB_T + j) * SB_MS + s] + b2[d0 + j];
+    }
+    __syncthreads();
+
+    // ---------------- phase 2: units completing inside the block (wave w: samples 4w..4w+3)
+    {
+      const int s = 4 * wv + g;
+      float* zs = zp + s * SB_T;
+      float* ts = thr + s * SB_T;
+      int8_t* ss = sbk + s * SB_T;
+      float* as = st + s * LDA;
+      int i = 0;
+      while (i < Tb) {
+        const int cr = cb[i];
+        int ie = i + 1;
+        while (ie < Tb && cb[ie] == cr) ++ie;
+        const int cn = cb[ie];
+        for (int j = i + l16; j < ie; j += 16) {
+          const float z = zs[j];
+          const bool up = z > ts[j];
+          ss[j] = up ? (int8_t)1 : (int8_t)-1;
+          ts[j] = up ? z : -z;
+        }
+        if (cr < c1) {
+          wave_sync_lds();
+          for (int u = cr + l16; u < c1; u += 16) {
+            float a = as[u];
+            const int uu = u - c0;
+            for (int j = i; j < ie; ++j) {
+              const float w = fastpb ? pb[j * SB_UB + uu] : to_f32(P[(int64_t)(d0 + j) * ldh + u]);
+              a = fmaf((float)ss[j], w, a);
+            }
+            as[u] = a;
+          }
+          if (cn > cr) {
+            wave_sync_lds();
+            for (int j = ie + l16; j < Tb; j += 16) {
+              float z = zs[j];
+              for (int u = cr; u < cn; ++u) {
+                const float w = fastpb ? pb[j * SB_UB + (u - c0)] : to_f32(P[(int64_t)(d0 + j) * ldh + u]);
+                z = fmaf(w, fmaxf(as[u], 0.f), z);
+              }
+              zs[j] = z;
+            }
+          }
+          wave_sync_lds();
+        }
+        i = ie;
+      }
+    }
+    __syncthreads();
+
+    // ---------------- outputs of the block: spins and log sigma(s z)
+    {
+      const int s = t >> 4, q4 = t & 15;
+      if (4 * q4 < Tb && b0 + s < B) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * q4 + e < Tb) word |= ((uint32_t)(uint8_t)sbk[s * SB_T + 4 * q4 + e]) << (8 * e);
+        *(uint32_t*)(S + (b0 + s) * lds + d0 + 4 * q4) = word;
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int j = q4 + 16 * m;
+        if (j < Tb) lp_part += log_sigmoid(thr[s * SB_T + j]);
+      }
+    }
+
+    // ---------------- phase 3: A[:, c1:] += S_block P[block, c1:]
+    {
+      bf16x8_t sv[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int j = 32 * ks + 8 * g + e;
+          const int8_t v = (j < Tb) ? sbk[l16 * SB_T + j] : (int8_t)0;
+          sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
+        }
+      for (int k0 = (c1 & ~15) + 16 * wv; k0 < h; k0 += 64) {
+        float* cp = st + l16 * LDA + k0 + 4 * g;
+        const float4 cur = *(const float4*)cp;
+        floatx4_t acc = {cur.x, cur.y, cur.z, cur.w};
+        const int unit = k0 + l16;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const int dd = d0 + 32 * ks + 8 * g;
+          if constexpr (sizeof(WT) == 2) {
+            bf16x8_t a = __builtin_bit_cast(bf16x8_t, make_uint4(0, 0, 0, 0));
+            if (unit < h && dd + 8 <= ldn) a = load_bf16x8((const bf16_t*)Pt + (int64_t)unit * ldn + dd);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sv[ks], acc, 0, 0, 0);
+          } else {
+            float w[8];
+            if (unit < h && dd + 8 <= ldn) {
+              const float4 w0 = *(const float4*)((const float*)Pt + (int64_t)unit * ldn + dd);
+              const float4 w1 = *(const float4*)((const float*)Pt + (int64_t)unit * ldn + dd + 4);
+              w[0] = w0.x; w[1] = w0.y; w[2] = w0.z; w[3] = w0.w;
+              w[4] = w1.x; w[5] = w1.y; w[6] = w1.z; w[7] = w1.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) w[e] = 0.f;
+            }
+            bf16x8_t hi, mid, lo;
+            split3(w, hi, mid, lo);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, sv[ks], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, sv[ks], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, sv[ks], acc, 0, 0, 0);
+          }
+        }
+        // lane holds state rows (units) k0 + 4g + e for sample l16; units < c1 are
+        // owned by phase 2 and are left untouched
+        if (k0 + 4 * g >= c1) {
+          *(float4*)cp = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (k0 + 4 * g + e >= c1) cp[e] = acc[e];
+        }
+      }
+    }
+    __syncthreads();
+    d0 = d1;
+  }
+
+  // log pi: sum the 16 per-thread partials of each sample (one 16-lane DPP row)
+  float v = lp_part;
+  v += VQMC_DPP(v, 0xB1);
+  v += VQMC_DPP(v, 0x4E);
+  v += VQMC_DPP(v, 0x141);
+  v += VQMC_DPP(v, 0x140);
+  const int s = t >> 4;
+  if ((t & 15) == 0 && b0 + s < B) {
+    if (logp) logp[b0 + s] = v;
+    for (int64_t col = round_up(n, 4); col < lds; col += 4) *(uint32_t*)(S + (b0 + s) * lds + col) = 0u;
+  }
+}
+
+bool sample_blocked_supported(int n, int h) { return sb_smem_bytes(h) <= 160 * 1024; }
+
+template <typename WT>
+static hipError_t launch_blocked_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
+                                   uint32_t tag, int8_t* S, float* logp, hipStream_t st) {
+  const size_t smem = sb_smem_bytes(m.h);
+  hipError_t e = hipFuncSetAttribute((const void*)sample_blocked_kernel<WT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((B + SB_MS - 1) / SB_MS);
+  sample_blocked_kernel<WT><<<grid, 256, smem, st>>>((const WT*)m.P, (const WT*)m.Pt, round_up(m.h, kPad),
+                                                     round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h,
+                                                     sb_lda(m.h), B, seed, step, offset, tag, S,
+                                                     round_up(m.n, kPad), logp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_blocked(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
+                                 uint32_t tag, int8_t* S, float* logp, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return launch_blocked_t<bf16_t>(m, B, seed, step, offset, tag, S, logp, st);
+  return launch_blocked_t<float>(m, B, seed, step, offset, tag, S, logp, st);
+}
+
+}  // namespace vqmc

@@ -234,6 +234,39 @@ def test_sample_incremental_teacher_forced(n, h, B, wd):
     assert (np.abs(lpg - f["logp"]) <= logp_bound(f, S_np[idx], sc["z"], 1e-5)).all()
 
 
+def _degree_pattern(kind, n, h):
+    if kind == "default":
+        return inputs.made_degrees(n, h)
+    if kind == "all_first":      # every unit completes after site 1: one huge in-block set
+        return np.ones(h, np.int32)
+    if kind == "all_last":       # every unit completes after site n-1
+        return np.full(h, n - 1, np.int32)
+    if kind == "clustered":      # bursts of units completing at a few sites
+        rng = np.random.default_rng(4)
+        return np.sort(rng.choice(np.arange(1, n), size=h)).astype(np.int32)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("kind,n,h,B", [("all_first", 50, 90, 40), ("all_last", 70, 60, 33),
+                                        ("clustered", 301, 150, 48), ("default", 9, 700, 17),
+                                        ("default", 131, 2500, 20)])
+def test_sample_degree_patterns_teacher_forced(kind, n, h, B, wd):
+    _banner(f"sample degrees={kind} n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, _ = instance(n, h, seed=14, graph=None, scale=3.0)
+    p["degrees"] = _degree_pattern(kind, n, h)
+    M = build_made(p, wdtype)
+    S, lp = B_.sample(M, B, 6, 1)
+    S_np = spins_np(S, n)
+    q = oracle_params(p, wdtype)
+    U = oph.uniforms(6, 1, np.arange(B), n)
+    mism, amb, _ = osmp.teacher_forced_check(q, S_np, U, 1e-4)
+    assert mism == 0
+    f, sc = logit_scale(q, S_np)
+    assert (np.abs(lp.cpu().numpy() - f["logp"]) <= logp_bound(f, S_np, sc["z"], 1e-5)).all()
+
+
 def test_sample_free_running_equals_oracle_maxcut20():
     _banner("sample free running n=20")
     w = inputs.WORKLOADS["maxcut20"]
@@ -299,6 +332,38 @@ def test_sample_plain_matches_incremental(n, h, B):
     clean = (np.abs(U - pref) > 1e-4).all(axis=1)
     assert np.array_equal(spins_np(Si, n)[clean], Sp_np[clean])
     assert np.allclose(lpi.cpu().numpy()[clean], lpp.cpu().numpy()[clean], rtol=1e-5, atol=1e-4)
+
+
+@pytest.mark.parametrize("wd", ["bf16", "f32"])
+def test_gradient_error_full_size_subset(wd):
+    """n = 10^4, h = 2000, B = 2048: the score gradient of a 256-sample subset (with c_b
+    from the whole batch) against the FP64 oracle."""
+    _banner(f"gradient error n=10000 h=2000 subset=256 {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    w = inputs.WORKLOADS["maxcut10k_h2000"]
+    inst = inputs.make_instance(w)
+    M = build_made(inst, wdtype)
+    H = B_.Hamiltonian.from_edges(w.n, inst["edges"], inst["weights"], device=DEV)
+    bufs = B_.StepBuffers.allocate(M, H, w.B)
+    B_.step(M, H, w.B, 2, 0, bufs)
+    sub = np.arange(0, w.B, w.B // 256)
+    coef = bufs.coef.cpu().numpy()
+    mask = np.zeros(w.B, np.float32)
+    mask[sub] = 1
+    coef_sub = torch.from_numpy(coef * mask).to(DEV)
+    dP, db1, db2 = B_.logprob_backward(M, bufs.S, coef_sub)
+    dW1, dW2 = M.unpack(dP)
+    S_np = spins_np(bufs.S, w.n)
+    q = oracle_params(inst, wdtype)
+    g = oest.logp_grad(q, S_np[sub], coef[sub].astype(np.float64))
+    tol = 1e-4 if wd == "f32" else 3e-2
+    for k, got in (("W1", dW1), ("W2", dW2), ("b1", db1), ("b2", db2)):
+        got = got.cpu().numpy()
+        err = np.abs(got - g[k]).max()
+        rel = err / np.abs(g[k]).max()
+        fro = np.linalg.norm(got - g[k]) / np.linalg.norm(g[k])
+        print(f"  {k}: max abs err {err:.3e}, max-normalised {rel:.3e}, relative Frobenius {fro:.3e}")
+        assert rel <= tol, k
 
 
 # ---------------------------------------------------------------- the full step
