@@ -30,6 +30,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
+GRAPH_DESC = {"maxcut10k": "random 10-regular, integer weights 1..5, CSR",
+              "maxcut10k_h2000": "random 10-regular, unit weights, CSR",
+              "sk2000": "SK dense J ~ N(0,1/n), FP64 energy",
+              "maxcut500": "G(500, 0.02), unit weights, CSR"}
 METRIC = "samples/s per VQMC step (sample+energy+grad) at n=10k, BF16 vs FP32 at equal cut"
 PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "fp32_vector_tflops": 157.3,
         "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
@@ -132,13 +136,72 @@ def algorithmic_work(w, made, H):
         # sampler: n*h MACs per sample (dot over complete units + rank-1 update)
         "sample": {"flops": 2.0 * nh * B_, "bytes": nh * es + B_ * (n + 4)},
         # energy: read the spins once (+ the CSR, L2 resident) and write E
-        "energy": {"bytes": B_ * n + (H.nnz * 8 + (n + 1) * 8) + B_ * 8},
+        "energy": ({"bytes": B_ * n + (H.nnz * 8 + (n + 1) * 8) + B_ * 8} if H.J is None else
+                   # dense J: strict upper triangle, n^2/2 FP64 MACs per sample
+                   {"flops": float(n) * (n - 1) * B_, "bytes": B_ * n + 4 * n * n + B_ * 8}),
         # forward: first layer sum_d (h - c[d]) + second layer sum_d c[d] = n*h MACs
         "logprob": {"flops": 2.0 * nh * B_},
         # backward: forward recompute (n*h) + hidden adjoint (sum_c) + weight gradient (n*h)
         "logprob_backward": {"flops": 2.0 * (2 * nh + sum_c) * B_},
     }
     return work
+
+
+# kernels behind each library call of the step, the file that holds them, and their bound
+def _dominant_desc(call, made, H):
+    bf16 = made.wdtype == 2
+    mm = PEAK["bf16_mfma_tflops"] if bf16 else PEAK["fp32_mfma_tflops"]
+    if call == "sample":
+        if made.h <= 2048:
+            k = "sample_blocked_kernel<bf16>" if bf16 else "sample_blocked_kernel<float>"
+            return {"kernels": [k], "src": ["sample_blocked.hip"], "bound": "mfma", "peak": mm,
+                    "unit": "TFLOP/s", "metric": "tflops"}
+        return {"kernels": ["sample_incremental_kernel"], "src": ["sample.hip"], "bound": "alu",
+                "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s", "metric": "tflops"}
+    if call == "energy":
+        if H.J is not None:
+            return {"kernels": ["energy_dense_kernel", "sum_partials_kernel"], "src": ["energy.hip"],
+                    "bound": "mfma", "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s", "metric": "tflops"}
+        return {"kernels": ["energy_csr_kernel<int, long>"], "src": ["energy.hip"], "bound": "hbm",
+                "peak": PEAK["hbm_gbs"], "unit": "GB/s", "metric": "gbs"}
+    t = "bf16" if bf16 else "float"
+    return {"kernels": [f"fwd_hidden_kernel<{t}, true>", f"fwd_out_kernel<{t}, 1>", f"bwd_hidden_kernel<{t}>",
+                        f"bwd_weight_kernel<{t}, false>", f"bwd_weight_kernel<{t}, true>", "sum_rows_kernel"],
+            "src": ["gemm.hip"], "bound": "mfma", "peak": mm, "unit": "TFLOP/s", "metric": "tflops"}
+
+
+def _src_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(HERE, "paper_2106_13308_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def _traffic(desc, workload):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+    or None when they are missing or the kernels' source changed since they were taken."""
+    path = os.path.join(HERE, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256", {}).get(",".join(desc["src"])) != _src_sha(desc["src"]):
+        return None
+    tot = 0.0
+    for k in desc["kernels"]:
+        e = rec["kernels"].get(k)
+        if e is None or e.get("fetch_bytes") is None or e.get("write_bytes") is None:
+            return None
+        tot += (e["fetch_bytes"] + e["write_bytes"]) * e.get("launches_per_call", 1)
+    return tot
+
+
+def roofline(call, kernels, made, H, workload):
+    desc = _dominant_desc(call, made, H)
+    ach = kernels[call][desc["metric"]]
+    return {"kernel": "+".join(desc["kernels"]), "call": f"vqmc_{call}", "bound": desc["bound"],
+            "achieved": ach, "peak": desc["peak"], "unit": desc["unit"], "frac": ach / desc["peak"],
+            "traffic": _traffic(desc, workload)}
 
 
 def cpu_baseline(w, inst, nsamp):
@@ -157,7 +220,8 @@ def cpu_baseline(w, inst, nsamp):
     t0 = time.perf_counter()
     U = oph.uniforms(2, 0, np.arange(nsamp), w.n)
     S, lp = osmp.sample_plain(p, U)
-    E = oen.energy_edges(inst["edges"], inst["weights"], S)
+    E = (oen.energy_edges(inst["edges"], inst["weights"], S) if "edges" in inst
+         else oen.energy_dense(inst["J"], S))
     st = oest.batch_stats(E)
     oest.logp_grad(p, S, st["coef"])
     dt = time.perf_counter() - t0
@@ -222,20 +286,7 @@ def main():
         kernels[name] = d
     step_calls = {k: calls[k] for k in ("sample", "energy", "stats", "logprob_backward")}
     dom = max(step_calls, key=step_calls.get)
-    if dom == "sample":
-        ach = kernels["sample"]["tflops"]
-        roof = {"kernel": "sample_incremental_kernel", "bound": "alu", "achieved": ach,
-                "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s",
-                "frac": ach / PEAK["fp32_vector_tflops"], "traffic": None}
-    elif dom == "energy":
-        ach = kernels["energy"]["gbs"]
-        roof = {"kernel": "energy_csr_kernel", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"],
-                "unit": "GB/s", "frac": ach / PEAK["hbm_gbs"], "traffic": None}
-    else:
-        ach = kernels["logprob_backward"]["tflops"]
-        roof = {"kernel": "logprob_backward (4 MFMA kernels)", "bound": "mfma", "achieved": ach,
-                "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
-                "frac": ach / PEAK["bf16_mfma_tflops"], "traffic": None}
+    roof = roofline(dom, kernels, made, H, w.name)
     forms = {"bf16_incremental": {"ms_per_step": ms, "samples_per_s": value}}
     if not a.no_forms:
         made32 = B.Made(made.n, made.h, made.P32, made.b1, made.b2, made.c, wdtype=B.F32)
@@ -252,7 +303,7 @@ def main():
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "h": w.h, "global_batch": w.B,
-                   "graph": "random 10-regular, integer weights 1..5, CSR",
+                   "graph": GRAPH_DESC.get(w.name, w.description),
                    "sampler": "incremental", "weights": "bf16", "parallelism": "single GPU"},
         "roofline": roof, "kernels": kernels, "forms": forms,
         "step_stats": {"mean_E": st["mean"], "min_E": st["min"], "var_E": st["var"]},

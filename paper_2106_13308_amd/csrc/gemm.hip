@@ -16,8 +16,8 @@
 //
 // Tile engine: a BM x BN output tile per workgroup of 4 waves (2 x 2 waves of
 // BM/2 x BN/2, each a grid of MFMA 16x16 blocks).  Operands are staged through LDS as
-// [row][K] with K contiguous; the next K step is loaded into registers while the
-// current one is multiplied, with two LDS buffers and one barrier per K step.  T = bf16
+// [row][K] with K contiguous; the K step after next is loaded into registers while
+// the current one is multiplied, with two LDS buffers and one barrier per K step.  T = bf16
 // uses v_mfma_f32_16x16x32_bf16 (BK = 32); T = float uses v_mfma_f32_16x16x4_f32
 // (BK = 16).  Accumulation is always FP32.  Intermediates that a later product
 // contracts over the batch (R, G, S, D) are written batch-contiguous (transposed) by
@@ -107,49 +107,84 @@ __device__ inline int count_le(const int32_t* c, int n, int x) {
   return lo;
 }
 
-// spins S[b][d0 .. d0+VEC) -> T  (rows b beyond B and sites beyond n read as 0)
-template <typename T>
-__device__ inline Vec<T> load_spins(const int8_t* S, int64_t lds, int64_t b, int64_t B, int d0, int n) {
-  constexpr int VEC = 16 / sizeof(T);
-  Vec<T> out;
-  if (b < B && d0 + VEC <= n) {
-    int8_t tmp[VEC];
-    if constexpr (VEC == 8) *(uint2*)tmp = *(const uint2*)(S + b * lds + d0);
-    else *(uint32_t*)tmp = *(const uint32_t*)(S + b * lds + d0);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) out.v[e] = spin_val<T>(tmp[e]);
-  } else {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      out.v[e] = (b < B && d0 + e < n) ? spin_val<T>(S[b * lds + d0 + e]) : (T)0;
-  }
-  return out;
-}
-
-// row-major T matrix X[r][k0 .. k0+VEC), rows >= R or columns >= K read as 0
-template <typename T>
-__device__ inline Vec<T> load_rows(const T* X, int64_t ld, int64_t r, int64_t R, int k0, int K) {
-  constexpr int VEC = 16 / sizeof(T);
-  Vec<T> out;
-  if (r < R && k0 + VEC <= K) {
-    *(uint4*)&out = *(const uint4*)(X + r * ld + k0);
-  } else {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) out.v[e] = (r < R && k0 + e < K) ? X[r * ld + k0 + e] : (T)0;
-  }
-  return out;
-}
-
 template <typename T>
 __device__ inline void store4(T* p, const T (&v)[4]) {
   if constexpr (sizeof(T) == 2) *(uint2*)p = *(const uint2*)v;
   else *(uint4*)p = *(const uint4*)v;
 }
 
+// ---------------------------------------------------------------- operand loaders
+// A loader stages 16-byte vectors of one operand.  fetch() only issues the global
+// loads of vector v of the thread (row r0 + 64 v) at K index kq; finish() converts /
+// masks the raw bytes when the stage is written to LDS.  Keeping the loaded values
+// untouched until then lets the loads of later K steps stay in flight while the
+// current step is multiplied.
+
+// spins S[b][kq .. kq+VEC) (int8, rows = samples m0 + row) -> T
+template <typename T>
+struct SpinA {
+  static constexpr int VEC = 16 / sizeof(T);
+  struct Raw { int8_t s[VEC]; };
+  const int8_t* S;
+  int64_t lds, B, m0;
+  int n, r0;
+  __device__ Raw fetch(int v, int kq) const {
+    Raw raw;
+    const int64_t b = m0 + r0 + 64 * v;
+    if (b < B && kq + VEC <= n) {
+      if constexpr (VEC == 8) *(uint2*)raw.s = *(const uint2*)(S + b * lds + kq);
+      else *(uint32_t*)raw.s = *(const uint32_t*)(S + b * lds + kq);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) raw.s[e] = (b < B && kq + e < n) ? S[b * lds + kq + e] : (int8_t)0;
+    }
+    return raw;
+  }
+  __device__ Vec<T> finish(int, const Raw& raw, int) const {
+    Vec<T> out;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out.v[e] = spin_val<T>(raw.s[e]);
+    return out;
+  }
+};
+
+// row-major T matrix, rows R0 + row (< R), K index valid in [lo[v], hi[v]) and < K.
+// The MADE staircase masks are prefixes / suffixes of each row, so one (lo, hi) pair
+// per staged row expresses them.
+template <typename T, int NV>
+struct RowsA {
+  static constexpr int VEC = 16 / sizeof(T);
+  using Raw = uint4;
+  const T* X;
+  int64_t ld, R0, R;
+  int K, r0;
+  int lo[NV], hi[NV];
+  __device__ Raw fetch(int v, int kq) const {
+    uint4 raw = make_uint4(0, 0, 0, 0);
+    const int64_t r = R0 + r0 + 64 * v;
+    if (r < R && kq < hi[v] && kq + VEC > lo[v]) {
+      if (kq + VEC <= K) {
+        raw = *(const uint4*)(X + r * ld + kq);
+      } else {
+        T tmp[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) tmp[e] = (kq + e < K) ? X[r * ld + kq + e] : (T)0;
+        raw = *(const uint4*)tmp;
+      }
+    }
+    return raw;
+  }
+  __device__ Vec<T> finish(int v, const Raw& raw, int kq) const {
+    Vec<T> out = *(const Vec<T>*)&raw;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (kq + e < lo[v] || kq + e >= hi[v]) out.v[e] = (T)0;
+    return out;
+  }
+};
+
 // ---------------------------------------------------------------- tile engine
 // Thread t stages rows (t / 4) + 64 v, element chunk (t % 4) * VEC of each operand.
-// LA(row, kq, v) / LB(row, kq, v) return the 16-byte vector of tile row `row` at K
-// index kq (absolute); PRE(k0) runs once per stage before the loads (shared state).
 template <typename T, int BM, int BN>
 struct Engine {
   static constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
@@ -169,45 +204,80 @@ struct Engine {
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
     if (kbeg >= kend) return;
-    Vec<T> ra[AV], rb[BV];
+    // two raw register sets: the tile multiplied at step i was fetched at step i-2
+    typename LA::Raw ra0[AV], ra1[AV];
+    typename LB::Raw rb0[BV], rb1[BV];
+    auto fetch = [&](typename LA::Raw(&ra)[AV], typename LB::Raw(&rb)[BV], int k) {
 #pragma unroll
-    for (int v = 0; v < AV; ++v) ra[v] = la(r0 + 64 * v, kbeg + q);
+      for (int v = 0; v < AV; ++v) ra[v] = la.fetch(v, k + q);
 #pragma unroll
-    for (int v = 0; v < BV; ++v) rb[v] = lb(r0 + 64 * v, kbeg + q);
-    auto store = [&](uint8_t* st) {
-#pragma unroll
-      for (int v = 0; v < AV; ++v) *(uint4*)(st + (r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&ra[v];
-#pragma unroll
-      for (int v = 0; v < BV; ++v)
-        *(uint4*)(st + (BM + r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&rb[v];
+      for (int v = 0; v < BV; ++v) rb[v] = lb.fetch(v, k + q);
     };
-    store(smem);
+    auto store = [&](uint8_t* st, const typename LA::Raw(&ra)[AV], const typename LB::Raw(&rb)[BV], int k) {
+#pragma unroll
+      for (int v = 0; v < AV; ++v) {
+        const Vec<T> x = la.finish(v, ra[v], k + q);
+        *(uint4*)(st + (r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&x;
+      }
+#pragma unroll
+      for (int v = 0; v < BV; ++v) {
+        const Vec<T> x = lb.finish(v, rb[v], k + q);
+        *(uint4*)(st + (BM + r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&x;
+      }
+    };
+    fetch(ra0, rb0, kbeg);
+    if (kbeg + BK < kend) fetch(ra1, rb1, kbeg + BK);
+    store(smem, ra0, rb0, kbeg);
     __syncthreads();
     int cur = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-      const bool nxt = k0 + BK < kend;
-      if (nxt) {
-#pragma unroll
-        for (int v = 0; v < AV; ++v) ra[v] = la(r0 + 64 * v, k0 + BK + q);
-#pragma unroll
-        for (int v = 0; v < BV; ++v) rb[v] = lb(r0 + 64 * v, k0 + BK + q);
+    int k0 = kbeg;
+    while (true) {
+      // set 1 holds tile k0 + BK; set 0 is free
+      if (k0 + 2 * BK < kend) fetch(ra0, rb0, k0 + 2 * BK);
+      {
+        const uint8_t* st = smem + cur * STAGE;
+        Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
       }
-      const uint8_t* st = smem + cur * STAGE;
-      Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
-      if (nxt) store(smem + (cur ^ 1) * STAGE);
+      if (k0 + BK < kend) store(smem + (cur ^ 1) * STAGE, ra1, rb1, k0 + BK);
       __syncthreads();
       cur ^= 1;
+      k0 += BK;
+      if (k0 >= kend) break;
+      // set 0 holds tile k0 + BK; set 1 is free
+      if (k0 + 2 * BK < kend) fetch(ra1, rb1, k0 + 2 * BK);
+      {
+        const uint8_t* st = smem + cur * STAGE;
+        Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
+      }
+      if (k0 + BK < kend) store(smem + (cur ^ 1) * STAGE, ra0, rb0, k0 + BK);
+      __syncthreads();
+      cur ^= 1;
+      k0 += BK;
+      if (k0 >= kend) break;
     }
   }
 };
 
+template <typename T, int NV>
+__device__ inline RowsA<T, NV> rows_plain(const T* X, int64_t ld, int64_t R0, int64_t R, int K, int r0) {
+  RowsA<T, NV> L{X, ld, R0, R, K, r0, {}, {}};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    L.lo[v] = 0;
+    L.hi[v] = K;
+  }
+  return L;
+}
+
 // tile shapes of the four products
-constexpr int H_BM = 128, H_BN = 64;    // hidden-layer products (N = h)
+constexpr int H_BM = 64, H_BN = 64;     // hidden-layer products (N = h), many small tiles
 constexpr int O_BM = 128, O_BN = 128;   // output-layer product (N = n)
 constexpr int W_BM = 128, W_BN = 128;   // weight gradient (M = n, N = h)
 
 // ---------------------------------------------------------------- K1: first layer
 // A = S * P_upper + b1 ; writes R = relu(A) (B x ldh) and optionally Rt (h x ldB).
+// Unit k receives site d iff c[d] <= k, i.e. d < count_le(c, k): a prefix of Pt's row.
+// N tiles run in decreasing order of their K range (largest first).
 template <typename T, bool WRITE_T>
 __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restrict__ S, int64_t lds,
                                                           const T* __restrict__ Pt, int64_t ldn,
@@ -217,25 +287,20 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
                                                           T* __restrict__ Rt, int64_t ldB) {
   using E = Engine<T, H_BM, H_BN>;
   __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
-  __shared__ int kend_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (H_BM / 2), wn = (wv & 1) * (H_BN / 2);
-  const int64_t m0 = (int64_t)blockIdx.y * H_BM;  // samples
-  const int n0 = blockIdx.x * H_BN;               // units
-  if (t == 0) kend_s = count_le(c, n, n0 + H_BN - 1);
-  __syncthreads();
-  const int kend = kend_s;
-  auto la = [&](int row, int kq) { return load_spins<T>(S, lds, m0 + row, B, kq, n); };
-  auto lb = [&](int row, int kq) {
-    const int unit = n0 + row;
-    Vec<T> v = load_rows<T>(Pt, ldn, unit, h, kq, n);
+  const int r0 = t >> 2;
+  const int64_t m0 = (int64_t)blockIdx.y * H_BM;                   // samples
+  const int n0 = (gridDim.x - 1 - blockIdx.x) * H_BN;              // units
+  const int kend = count_le(c, n, n0 + H_BN - 1);
+  const SpinA<T> la{S, lds, B, m0, n, r0};
+  RowsA<T, E::BV> lb{Pt, ldn, n0, h, n, r0, {}, {}};
 #pragma unroll
-    for (int e = 0; e < E::VEC; ++e) {
-      const int d = kq + e;
-      if (d >= n || c[d] > unit) v.v[e] = (T)0;  // unit receives site d iff c[d] <= unit
-    }
-    return v;
-  };
+  for (int v = 0; v < E::BV; ++v) {
+    const int unit = n0 + r0 + 64 * v;
+    lb.lo[v] = 0;
+    lb.hi[v] = (unit < h) ? count_le(c, n, unit) : 0;
+  }
   floatx4_t acc[E::FM][E::FN];
   E::run(smem, 0, kend, la, lb, acc);
 #pragma unroll
@@ -259,6 +324,7 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
 // ---------------------------------------------------------------- K2: second layer
 // MODE 0: logp partials (+ optional Z).  MODE 1: also G, Gt, St and db2 partials for
 // the backward.  MODE 2: plain sampler: draw site `dsel` from the conditional.
+// Unit k feeds site d iff k < c[d]: a prefix of P's row d.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void fwd_out_kernel(
     const T* __restrict__ R, int64_t ldh, const T* __restrict__ P, const float* __restrict__ b2,
@@ -273,19 +339,19 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
   __shared__ float colacc[2][O_BN];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (O_BM / 2), wn = (wv & 1) * (O_BN / 2);
-  const int64_t m0 = (int64_t)blockIdx.y * O_BM;                         // samples
-  const int d0 = (MODE == 2) ? (dsel / O_BN) * O_BN : blockIdx.x * O_BN;  // sites
+  const int r0 = t >> 2;
+  const int64_t m0 = (int64_t)blockIdx.y * O_BM;  // samples
+  const int tile = (MODE == 2) ? dsel / O_BN : (int)(gridDim.x - 1 - blockIdx.x);
+  const int d0 = tile * O_BN;                     // sites
   const int kend = c[min(d0 + O_BN - 1, n - 1)];
-  auto la = [&](int row, int kq) { return load_rows<T>(R, ldh, m0 + row, B, kq, h); };
-  auto lb = [&](int row, int kq) {
-    const int d = d0 + row;
-    Vec<T> v = load_rows<T>(P, ldh, d, n, kq, h);
-    const int cd = (d < n) ? c[d] : 0;
+  const RowsA<T, E::AV> la = rows_plain<T, E::AV>(R, ldh, m0, B, h, r0);
+  RowsA<T, E::BV> lb{P, ldh, d0, n, h, r0, {}, {}};
 #pragma unroll
-    for (int e = 0; e < E::VEC; ++e)
-      if (kq + e >= cd) v.v[e] = (T)0;  // unit k feeds site d iff k < c[d]
-    return v;
-  };
+  for (int v = 0; v < E::BV; ++v) {
+    const int d = d0 + r0 + 64 * v;
+    lb.lo[v] = 0;
+    lb.hi[v] = (d < n) ? c[d] : 0;
+  }
   floatx4_t acc[E::FM][E::FN];
   E::run(smem, 0, kend, la, lb, acc);
   if constexpr (MODE == 2) {
@@ -390,7 +456,7 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
   __syncthreads();
   if (t < O_BM) {
     const int64_t b = m0 + t;
-    if (b < B) lp_part[(int64_t)blockIdx.x * B + b] = rowacc[0][t] + rowacc[1][t];
+    if (b < B) lp_part[(int64_t)tile * B + b] = rowacc[0][t] + rowacc[1][t];
   } else if (MODE == 1) {
     const int dl = t - O_BM;
     const int d = d0 + dl;
@@ -400,6 +466,8 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
 
 // ---------------------------------------------------------------- K3: hidden adjoint
 // D = [A > 0] (G * P_lower) ; writes Dt (h x ldB) and db1 partials.
+// Unit k feeds site d iff c[d] > k, i.e. d >= count_le(c, k): a suffix of Pt's row.
+// Tiles of small k have the longest K range and come first in the grid.
 template <typename T>
 __global__ __launch_bounds__(256) void bwd_hidden_kernel(const T* __restrict__ G, int64_t ldn,
                                                           const T* __restrict__ Pt,
@@ -410,25 +478,20 @@ __global__ __launch_bounds__(256) void bwd_hidden_kernel(const T* __restrict__ G
   using E = Engine<T, H_BM, H_BN>;
   __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
   __shared__ float colacc[2][H_BN];
-  __shared__ int kbeg_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (H_BM / 2), wn = (wv & 1) * (H_BN / 2);
+  const int r0 = t >> 2;
   const int64_t m0 = (int64_t)blockIdx.y * H_BM;  // samples
   const int n0 = blockIdx.x * H_BN;               // units
-  if (t == 0) kbeg_s = count_le(c, n, n0);        // first site with c[d] > n0
-  __syncthreads();
-  const int kbeg = (kbeg_s / E::BK) * E::BK;
-  auto la = [&](int row, int kq) { return load_rows<T>(G, ldn, m0 + row, B, kq, n); };
-  auto lb = [&](int row, int kq) {
-    const int unit = n0 + row;
-    Vec<T> v = load_rows<T>(Pt, ldn, unit, h, kq, n);
+  const int kbeg = (count_le(c, n, n0) / E::BK) * E::BK;
+  const RowsA<T, E::AV> la = rows_plain<T, E::AV>(G, ldn, m0, B, n, r0);
+  RowsA<T, E::BV> lb{Pt, ldn, n0, h, n, r0, {}, {}};
 #pragma unroll
-    for (int e = 0; e < E::VEC; ++e) {
-      const int d = kq + e;
-      if (d >= n || c[d] <= unit) v.v[e] = (T)0;  // unit feeds site d iff unit < c[d]
-    }
-    return v;
-  };
+  for (int v = 0; v < E::BV; ++v) {
+    const int unit = n0 + r0 + 64 * v;
+    lb.lo[v] = (unit < h) ? count_le(c, n, unit) : n;
+    lb.hi[v] = n;
+  }
   floatx4_t acc[E::FM][E::FN];
   E::run(smem, kbeg, n, la, lb, acc);
   float cs[E::FN];
@@ -484,13 +547,14 @@ __global__ __launch_bounds__(256) void bwd_weight_kernel(const T* __restrict__ X
   __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (W_BM / 2), wn = (wv & 1) * (W_BN / 2);
+  const int r0 = t >> 2;
   const int d0 = blockIdx.y * W_BM;   // sites
   const int k0u = blockIdx.x * W_BN;  // units
   const int dlast = min(d0 + W_BM - 1, n - 1);
   const bool any = UPPER ? (k0u + W_BN - 1 >= c[d0]) : (k0u < c[dlast]);
   if (!any) return;
-  auto la = [&](int row, int kq) { return load_rows<T>(X, ldB, d0 + row, n, kq, (int)ldB); };
-  auto lb = [&](int row, int kq) { return load_rows<T>(Y, ldB, k0u + row, h, kq, (int)ldB); };
+  const RowsA<T, E::AV> la = rows_plain<T, E::AV>(X, ldB, d0, n, (int)ldB, r0);
+  const RowsA<T, E::BV> lb = rows_plain<T, E::BV>(Y, ldB, k0u, h, (int)ldB, r0);
   floatx4_t acc[E::FM][E::FN];
   E::run(smem, 0, (int)ldB, la, lb, acc);
 #pragma unroll

@@ -79,37 +79,163 @@ __device__ inline void load_bf16x4x2(const bf16_t* p0, const bf16_t* p1, bf16x8_
   out = __builtin_bit_cast(bf16x8_t, make_uint4(a.x, a.y, b.x, b.y));
 }
 
+// Weight fragments of the two products, fetched ahead of their use.
+//  phase 1, chunk of K units at k0, the wave's two M tiles (rows = sites):
+//   BF16: units k0+4g..+3 and k0+16+4g..+3 of row d (the K order of the state operand)
+//   FP32: unit k0+g of row d
+//  phase 3, one 16-unit tile (rows = units), both 32-site halves of the block
+template <typename WT>
+struct Frags;
+template <>
+struct Frags<bf16_t> {
+  static constexpr int KC = 32;
+  struct P1 { uint2 a[2][2]; };
+  struct P3 { uint4 a[2]; };
+};
+template <>
+struct Frags<float> {
+  static constexpr int KC = 4;
+  struct P1 { float a[2]; };
+  struct P3 { uint4 a[2][2]; };
+};
+
 template <typename WT>
 __global__ __launch_bounds__(256) void sample_blocked_kernel(
     const WT* __restrict__ P, const WT* __restrict__ Pt, int64_t ldh, int64_t ldn,
     const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
     int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
     int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp) {
+  using F = Frags<WT>;
+  constexpr int KC = F::KC;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   float* st = (float*)smem;                 // [16][LDA]   state A
   float* red = st + SB_MS * LDA;            // [2][64][16] phase-1 partials
-  float* zp = red + 2 * SB_T * SB_MS;       // [16][64]    running logits of the block
-  float* thr = zp + SB_MS * SB_T;           // [16][64]    logit(u); then s*z
+  float* zp = red + 2 * SB_T * SB_MS;       // [16][64]    logits of the block before phase 2
+  float* thr = zp + SB_MS * SB_T;           // [16][64]    logit(u)
   float* pb = thr + SB_MS * SB_T;           // [64][UB]    P[d0+j][c0+u]
   int8_t* sbk = (int8_t*)(pb + SB_T * SB_UB);  // [16][64] spins of the block
   int* cb = (int*)(sbk + SB_MS * SB_T);     // [65]        c[d0+j], sentinel c1
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, g = lane >> 4;
+  const int kh = wv & 1, mh = wv >> 1;      // phase-1 split: K half, M (site) half
   const int64_t b0 = (int64_t)blockIdx.x * SB_MS;
+
+  // block [d0, d1): at most 64 sites, a multiple of 8 unless it ends at n, and as long
+  // as the in-block units c[d1-1] - c[d0] fit the LDS stage (at least 8 sites)
+  auto block_end = [&](int d0) {
+    const int c0 = c[d0];
+    int d1 = min(d0 + SB_T, n);
+    while (d1 - d0 > 8 && c[d1 - 1] - c0 > SB_UB) d1 = d0 + ((d1 - d0 - 1) >> 3) * 8;
+    return d1;
+  };
+  auto fetch_p1 = [&](typename F::P1& f, int dblk, int k0) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int d = dblk + 32 * mh + 16 * mt + l16;
+      if constexpr (sizeof(WT) == 2) {
+        if (d < n) {
+          const bf16_t* prow = (const bf16_t*)P + (int64_t)d * ldh + k0 + 4 * g;
+          f.a[mt][0] = *(const uint2*)prow;
+          f.a[mt][1] = *(const uint2*)(prow + 16);
+        } else {
+          f.a[mt][0] = f.a[mt][1] = make_uint2(0, 0);
+        }
+      } else {
+        f.a[mt] = (d < n) ? ((const float*)P)[(int64_t)d * ldh + k0 + g] : 0.f;
+      }
+    }
+  };
+  auto use_p1 = [&](const typename F::P1& f, int k0, int c0, floatx4_t(&acc)[2]) {
+    if constexpr (sizeof(WT) == 2) {
+      const float* srow = st + l16 * LDA + k0 + 4 * g;
+      const float4 ra = *(const float4*)srow;
+      const float4 rb = *(const float4*)(srow + 16);
+      float r[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int kk = k0 + 4 * g + (e & 3) + ((e >> 2) << 4);
+        r[e] = (kk < c0) ? fmaxf(r[e], 0.f) : 0.f;
+      }
+      bf16x8_t hi, mid, lo;
+      split3(r, hi, mid, lo);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const bf16x8_t a = __builtin_bit_cast(
+            bf16x8_t, make_uint4(f.a[mt][0].x, f.a[mt][0].y, f.a[mt][1].x, f.a[mt][1].y));
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, mid, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc[mt], 0, 0, 0);
+      }
+    } else {
+      const int k = k0 + g;
+      const float r = (k < c0) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[mt], r, acc[mt], 0, 0, 0);
+    }
+  };
+  auto fetch_p3 = [&](typename F::P3& f, int dblk, int k0) {
+    const int unit = k0 + l16;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int dd = dblk + 32 * ks + 8 * g;
+      const bool ok = unit < h && dd + 8 <= ldn;
+      if constexpr (sizeof(WT) == 2) {
+        f.a[ks] = ok ? *(const uint4*)((const bf16_t*)Pt + (int64_t)unit * ldn + dd) : make_uint4(0, 0, 0, 0);
+      } else {
+        const float* p = (const float*)Pt + (int64_t)unit * ldn + dd;
+        f.a[ks][0] = ok ? *(const uint4*)p : make_uint4(0, 0, 0, 0);
+        f.a[ks][1] = ok ? *(const uint4*)(p + 4) : make_uint4(0, 0, 0, 0);
+      }
+    }
+  };
+  // state rows (units) k0+4g..+3 of sample l16 += tile x block spins; units < c1 untouched
+  auto use_p3 = [&](const typename F::P3& f, int k0, int c1, const bf16x8_t(&sv)[2]) {
+    float* cp = st + l16 * LDA + k0 + 4 * g;
+    const float4 cur = *(const float4*)cp;
+    floatx4_t acc = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      if constexpr (sizeof(WT) == 2) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, f.a[ks]), sv[ks], acc, 0, 0, 0);
+      } else {
+        const float4 w0 = __builtin_bit_cast(float4, f.a[ks][0]);
+        const float4 w1 = __builtin_bit_cast(float4, f.a[ks][1]);
+        const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        bf16x8_t hi, mid, lo;
+        split3(w, hi, mid, lo);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, sv[ks], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, sv[ks], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, sv[ks], acc, 0, 0, 0);
+      }
+    }
+    if (k0 + 4 * g >= c1) {
+      *(float4*)cp = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (k0 + 4 * g + e >= c1) cp[e] = acc[e];
+    }
+  };
 
   for (int i = t; i < SB_MS * LDA; i += 256) {
     const int k = i % LDA;
     st[i] = (k < h) ? b1[k] : 0.f;
   }
   float lp_part = 0.f;
+  // phase-1 fragments of the first two chunks of the first block
+  typename F::P1 f0, f1;
+  {
+    const int nch = (c[0] + KC - 1) / KC;
+    if (kh < nch) fetch_p1(f0, 0, kh * KC);
+    if (kh + 2 < nch) fetch_p1(f1, 0, (kh + 2) * KC);
+  }
   __syncthreads();
 
   for (int d0 = 0; d0 < n;) {
     // ---------------- block bounds (uniform)
     const int c0 = c[d0];
-    int d1 = min(d0 + SB_T, n);
-    while (d1 - d0 > 8 && c[d1 - 1] - c0 > SB_UB) d1 = d0 + ((d1 - d0 - 1) >> 3) * 8;
+    const int d1 = block_end(d0);
     const int Tb = d1 - d0;
     const int c1 = c[d1 - 1];
     const int U = c1 - c0;
@@ -138,52 +264,18 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
       }
     }
 
-    // ---------------- phase 1: Zp = relu(A[:, :c0]) P[block, :c0]^T
+    // ---------------- phase 1: Zp = relu(A[:, :c0]) P[block, :c0]^T, fragments two chunks ahead
     {
-      const int kh = wv & 1, mh = wv >> 1;
       floatx4_t acc[2];
       acc[0] = acc[1] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-      if constexpr (sizeof(WT) == 2) {
-        const int nchunk = (c0 + 31) >> 5;
-        for (int ch = kh; ch < nchunk; ch += 2) {
-          const int k0 = ch * 32;
-          const float* srow = st + l16 * LDA + k0 + 4 * g;
-          const float4 ra = *(const float4*)srow;
-          const float4 rb = *(const float4*)(srow + 16);
-          float r[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int kk = k0 + 4 * g + (e & 3) + ((e >> 2) << 4);
-            r[e] = (kk < c0) ? fmaxf(r[e], 0.f) : 0.f;
-          }
-          bf16x8_t hi, mid, lo;
-          split3(r, hi, mid, lo);
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            const int d = d0 + 32 * mh + 16 * mt + l16;
-            bf16x8_t a;
-            if (d < n) {
-              const bf16_t* prow = (const bf16_t*)P + (int64_t)d * ldh + k0 + 4 * g;
-              load_bf16x4x2(prow, prow + 16, a);
-            } else {
-              a = __builtin_bit_cast(bf16x8_t, make_uint4(0, 0, 0, 0));
-            }
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc[mt], 0, 0, 0);
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, mid, acc[mt], 0, 0, 0);
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc[mt], 0, 0, 0);
-          }
-        }
-      } else {
-        const int nchunk = (c0 + 3) >> 2;
-        for (int ch = kh; ch < nchunk; ch += 2) {
-          const int k = ch * 4 + g;
-          const float r = (k < c0) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            const int d = d0 + 32 * mh + 16 * mt + l16;
-            const float a = (d < n && k < c0) ? ((const float*)P)[(int64_t)d * ldh + k] : 0.f;
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r, acc[mt], 0, 0, 0);
-          }
+      const int nch = (c0 + KC - 1) / KC;
+      const int cnt = (nch > kh) ? (nch - kh + 1) / 2 : 0;  // this wave's chunks kh, kh+2, ...
+      for (int it = 0; it < cnt; it += 2) {
+        use_p1(f0, (kh + 2 * it) * KC, c0, acc);
+        if (it + 2 < cnt) fetch_p1(f0, d0, (kh + 2 * (it + 2)) * KC);
+        if (it + 1 < cnt) {
+          use_p1(f1, (kh + 2 * (it + 1)) * KC, c0, acc);
+          if (it + 3 < cnt) fetch_p1(f1, d0, (kh + 2 * (it + 3)) * KC);
         }
       }
       // C layout: lane l holds rows (sites) 4*(l/16)+e, column (sample) l%16
@@ -194,6 +286,17 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
           const int j = 32 * mh + 16 * mt + 4 * g + e;
           red[(kh * SB_T + j) * SB_MS + l16] = acc[mt][e];
         }
+    }
+    // fragments for later: the first two phase-3 tiles of this block and the first two
+    // phase-1 chunks of the next block; their loads overlap the serial phase
+    typename F::P3 q0, q1;
+    const int p3base = (c1 & ~15) + 16 * wv;
+    if (p3base < h) fetch_p3(q0, d0, p3base);
+    if (p3base + 64 < h) fetch_p3(q1, d0, p3base + 64);
+    if (d1 < n) {
+      const int nch = (c[d1] + KC - 1) / KC;
+      if (kh < nch) fetch_p1(f0, d1, kh * KC);
+      if (kh + 2 < nch) fetch_p1(f1, d1, (kh + 2) * KC);
     }
     __syncthreads();
 #pragma unroll
@@ -207,52 +310,134 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
     // ---------------- phase 2: units completing inside the block (wave w: samples 4w..4w+3)
     {
       const int s = 4 * wv + g;
-      float* zs = zp + s * SB_T;
-      float* ts = thr + s * SB_T;
-      int8_t* ss = sbk + s * SB_T;
       float* as = st + s * LDA;
-      int i = 0;
-      while (i < Tb) {
-        const int cr = cb[i];
-        int ie = i + 1;
-        while (ie < Tb && cb[ie] == cr) ++ie;
-        const int cn = cb[ie];
-        for (int j = i + l16; j < ie; j += 16) {
-          const float z = zs[j];
-          const bool up = z > ts[j];
-          ss[j] = up ? (int8_t)1 : (int8_t)-1;
-          ts[j] = up ? z : -z;
+      if (fastpb) {
+        // lane (s, l16) owns sites l16 + 16m and in-block units c0 + l16 + 16mm in registers
+        float zr[4], th[4], ar[2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int j = l16 + 16 * m;
+          zr[m] = (j < Tb) ? zp[s * SB_T + j] : 0.f;
+          th[m] = (j < Tb) ? thr[s * SB_T + j] : 0.f;
         }
-        if (cr < c1) {
-          wave_sync_lds();
-          for (int u = cr + l16; u < c1; u += 16) {
-            float a = as[u];
-            const int uu = u - c0;
-            for (int j = i; j < ie; ++j) {
-              const float w = fastpb ? pb[j * SB_UB + uu] : to_f32(P[(int64_t)(d0 + j) * ldh + u]);
-              a = fmaf((float)ss[j], w, a);
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+          const int u = c0 + l16 + 16 * mm;
+          ar[mm] = (u < c1) ? as[u] : 0.f;
+        }
+        // run starts: site j starts a run when c[d0+j] differs from its predecessor
+        const int cbl = (lane < Tb) ? cb[lane] : c1;
+        const int cbp = (lane >= 1 && lane <= Tb) ? cb[lane - 1] : -1;
+        const uint64_t starts = __ballot(lane < Tb && cbl != cbp);
+        uint32_t dec = 0;
+        int i = 0;
+        while (i < Tb) {
+          const uint64_t later = (i < 63) ? (starts >> (i + 1)) : 0ull;
+          const int ie = later ? min(Tb, i + 1 + (int)__builtin_ctzll(later)) : Tb;
+          const int cr = __builtin_amdgcn_readlane(cbl, i);
+          const int cn = (ie < Tb) ? __builtin_amdgcn_readlane(cbl, ie) : c1;
+          // decide every site of the run at once
+          uint64_t bm[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int j = l16 + 16 * m;
+            const bool inrun = (j >= i) && (j < ie);
+            const bool up = zr[m] > th[m];
+            if (inrun) {
+              if (up) dec |= 1u << m;
+              else zr[m] = -zr[m];
+              lp_part += log_sigmoid(zr[m]);
             }
-            as[u] = a;
+            bm[m] = __ballot(inrun && up);
           }
-          if (cn > cr) {
-            wave_sync_lds();
-            for (int j = ie + l16; j < Tb; j += 16) {
-              float z = zs[j];
-              for (int u = cr; u < cn; ++u) {
-                const float w = fastpb ? pb[j * SB_UB + (u - c0)] : to_f32(P[(int64_t)(d0 + j) * ldh + u]);
-                z = fmaf(w, fmaxf(as[u], 0.f), z);
+          if (cr < c1) {
+            // in-block units not yet complete receive the run's spins
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm) {
+              const int u = c0 + l16 + 16 * mm;
+              if (u >= cr && u < c1) {
+                float a0 = ar[mm], a1 = 0.f;
+                for (int j = i; j < ie; ++j) {
+                  const uint64_t bj = (j < 16) ? bm[0] : (j < 32) ? bm[1] : (j < 48) ? bm[2] : bm[3];
+                  const float sg = ((bj >> (16 * g + (j & 15))) & 1ull) ? 1.f : -1.f;
+                  const float w = pb[j * SB_UB + (u - c0)];
+                  if (j & 1) a1 = fmaf(sg, w, a1); else a0 = fmaf(sg, w, a0);
+                }
+                ar[mm] = a0 + a1;
               }
-              zs[j] = z;
+            }
+            // units completing after the run feed every pending site of the block
+            for (int u = cr; u < cn; ++u) {
+              const int rel = u - c0;
+              const float v = (rel >= 16) ? ar[1] : ar[0];
+              const float r = fmaxf(__shfl(v, (lane & 48) | (rel & 15)), 0.f);
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                const int j = l16 + 16 * m;
+                if (j >= ie && j < Tb) zr[m] = fmaf(pb[j * SB_UB + rel], r, zr[m]);
+              }
             }
           }
-          wave_sync_lds();
+          i = ie;
         }
-        i = ie;
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+          const int u = c0 + l16 + 16 * mm;
+          if (u < c1) as[u] = ar[mm];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int j = l16 + 16 * m;
+          if (j < Tb) sbk[s * SB_T + j] = ((dec >> m) & 1u) ? (int8_t)1 : (int8_t)-1;
+        }
+      } else {
+        // many units complete inside the block: work through LDS, weights from global
+        float* zs = zp + s * SB_T;
+        float* ts = thr + s * SB_T;
+        int8_t* ss = sbk + s * SB_T;
+        int i = 0;
+        while (i < Tb) {
+          const int cr = cb[i];
+          int ie = i + 1;
+          while (ie < Tb && cb[ie] == cr) ++ie;
+          const int cn = cb[ie];
+          for (int j = i + l16; j < ie; j += 16) {
+            const float z = zs[j];
+            const bool up = z > ts[j];
+            ss[j] = up ? (int8_t)1 : (int8_t)-1;
+            ts[j] = up ? z : -z;
+          }
+          if (cr < c1) {
+            wave_sync_lds();
+            for (int u = cr + l16; u < c1; u += 16) {
+              float a = as[u];
+              for (int j = i; j < ie; ++j) a = fmaf((float)ss[j], to_f32(P[(int64_t)(d0 + j) * ldh + u]), a);
+              as[u] = a;
+            }
+            if (cn > cr) {
+              wave_sync_lds();
+              for (int j = ie + l16; j < Tb; j += 16) {
+                float z = zs[j];
+                for (int u = cr; u < cn; ++u)
+                  z = fmaf(to_f32(P[(int64_t)(d0 + j) * ldh + u]), fmaxf(as[u], 0.f), z);
+                zs[j] = z;
+              }
+            }
+            wave_sync_lds();
+          }
+          i = ie;
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int j = l16 + 16 * m;
+          if (j < Tb) lp_part += log_sigmoid(ts[j]);
+        }
       }
     }
     __syncthreads();
 
-    // ---------------- outputs of the block: spins and log sigma(s z)
+    // ---------------- spins of the block to global memory
     {
       const int s = t >> 4, q4 = t & 15;
       if (4 * q4 < Tb && b0 + s < B) {
@@ -262,14 +447,9 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
           if (4 * q4 + e < Tb) word |= ((uint32_t)(uint8_t)sbk[s * SB_T + 4 * q4 + e]) << (8 * e);
         *(uint32_t*)(S + (b0 + s) * lds + d0 + 4 * q4) = word;
       }
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int j = q4 + 16 * m;
-        if (j < Tb) lp_part += log_sigmoid(thr[s * SB_T + j]);
-      }
     }
 
-    // ---------------- phase 3: A[:, c1:] += S_block P[block, c1:]
+    // ---------------- phase 3: A[:, c1:] += S_block P[block, c1:], fragments two tiles ahead
     {
       bf16x8_t sv[2];
 #pragma unroll
@@ -280,44 +460,12 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
           const int8_t v = (j < Tb) ? sbk[l16 * SB_T + j] : (int8_t)0;
           sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
         }
-      for (int k0 = (c1 & ~15) + 16 * wv; k0 < h; k0 += 64) {
-        float* cp = st + l16 * LDA + k0 + 4 * g;
-        const float4 cur = *(const float4*)cp;
-        floatx4_t acc = {cur.x, cur.y, cur.z, cur.w};
-        const int unit = k0 + l16;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          const int dd = d0 + 32 * ks + 8 * g;
-          if constexpr (sizeof(WT) == 2) {
-            bf16x8_t a = __builtin_bit_cast(bf16x8_t, make_uint4(0, 0, 0, 0));
-            if (unit < h && dd + 8 <= ldn) a = load_bf16x8((const bf16_t*)Pt + (int64_t)unit * ldn + dd);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sv[ks], acc, 0, 0, 0);
-          } else {
-            float w[8];
-            if (unit < h && dd + 8 <= ldn) {
-              const float4 w0 = *(const float4*)((const float*)Pt + (int64_t)unit * ldn + dd);
-              const float4 w1 = *(const float4*)((const float*)Pt + (int64_t)unit * ldn + dd + 4);
-              w[0] = w0.x; w[1] = w0.y; w[2] = w0.z; w[3] = w0.w;
-              w[4] = w1.x; w[5] = w1.y; w[6] = w1.z; w[7] = w1.w;
-            } else {
-#pragma unroll
-              for (int e = 0; e < 8; ++e) w[e] = 0.f;
-            }
-            bf16x8_t hi, mid, lo;
-            split3(w, hi, mid, lo);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, sv[ks], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, sv[ks], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, sv[ks], acc, 0, 0, 0);
-          }
-        }
-        // lane holds state rows (units) k0 + 4g + e for sample l16; units < c1 are
-        // owned by phase 2 and are left untouched
-        if (k0 + 4 * g >= c1) {
-          *(float4*)cp = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (k0 + 4 * g + e >= c1) cp[e] = acc[e];
+      for (int k0 = p3base; k0 < h; k0 += 128) {
+        use_p3(q0, k0, c1, sv);
+        if (k0 + 128 < h) fetch_p3(q0, d0, k0 + 128);
+        if (k0 + 64 < h) {
+          use_p3(q1, k0 + 64, c1, sv);
+          if (k0 + 192 < h) fetch_p3(q1, d0, k0 + 192);
         }
       }
     }
