@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -28,6 +29,38 @@ int hip_status(hipError_t e, const char* where) {
 }
 
 constexpr int kMaxSamplerH = 4096;  // units held per thread: 16 x 256
+
+size_t step_energy_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  const size_t bw = logprob_ws_bytes(n, h, B, wdtype, true);
+  const size_t sp = sample_plain_ws_bytes(n, h, B, wdtype);
+  return (size_t)round_up((int64_t)std::max(bw, sp), 256);
+}
+
+// One auxiliary stream (default priority) and two events per device, created on first
+// use and kept for the life of the process: vqmc_step runs the energy and statistics
+// on it while the main stream starts the backward.
+struct StepAux {
+  hipStream_t stream = nullptr;
+  hipEvent_t sampled = nullptr, stats_done = nullptr;
+};
+std::mutex g_aux_mu;
+StepAux g_aux[64];
+
+hipError_t step_aux(StepAux** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  StepAux& a = g_aux[dev];
+  if (!a.stream) {
+    if ((e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.sampled, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.stats_done, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *out = &a;
+  return hipSuccess;
+}
 
 int check_made(const vqmc_made* m, bool need_pt) {
   if (!m) return fail(VQMC_EINVAL, "made is NULL");
@@ -65,11 +98,9 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_BACKWARD: return logprob_ws_bytes(n, h, B, wdtype, true);
     case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
     case VQMC_WS_STEP: {
-      // the step runs sample (plain form needs its own), energy and backward in order
-      const size_t bw = logprob_ws_bytes(n, h, B, wdtype, true);
-      const size_t sp = sample_plain_ws_bytes(n, h, B, wdtype);
-      const size_t en = (size_t)((n + 63) / 64) * (size_t)B * sizeof(double);
-      return std::max(bw, std::max(sp, en));
+      // sampling and the backward reuse one region; the energy (which overlaps the
+      // backward's first product) gets its own region after it
+      return step_energy_offset(n, h, B, wdtype) + (size_t)((n + 63) / 64) * (size_t)B * sizeof(double);
     }
     default: return 0;
   }
@@ -215,10 +246,18 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
                      ? launch_sample_incremental(*m, B, seed, step, sample_offset, 0, S, logp, st)
                      : launch_sample_plain(*m, B, seed, step, sample_offset, 0, S, logp, ws, st);
   if (e != hipSuccess) return hip_status(e, "vqmc_step sample");
-  if ((e = launch_energy(*H, S, B, E, ws, st)) != hipSuccess) return hip_status(e, "vqmc_step energy");
-  if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, st)) != hipSuccess)
+  // energy + statistics on the auxiliary stream, overlapping the first backward product
+  // (which only needs the spins); the main stream waits for them before reading coef
+  StepAux* aux = nullptr;
+  if ((e = step_aux(&aux)) != hipSuccess) return hip_status(e, "vqmc_step aux stream");
+  void* ws_energy = (uint8_t*)ws + step_energy_offset(m->n, m->h, B, m->wdtype);
+  if ((e = hipEventRecord(aux->sampled, st)) != hipSuccess) return hip_status(e, "vqmc_step record");
+  if ((e = hipStreamWaitEvent(aux->stream, aux->sampled, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
+  if ((e = launch_energy(*H, S, B, E, ws_energy, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step energy");
+  if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, aux->stream)) != hipSuccess)
     return hip_status(e, "vqmc_step stats");
-  if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st)) != hipSuccess)
+  if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
+  if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st, aux->stats_done)) != hipSuccess)
     return hip_status(e, "vqmc_step backward");
   return VQMC_OK;
 }

@@ -673,7 +673,7 @@ static hipError_t logprob_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
 
 template <typename T>
 static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                             float* dP, float* db1, float* db2, void* ws, hipStream_t st) {
+                             float* dP, float* db1, float* db2, void* ws, hipStream_t st, hipEvent_t coef_ready) {
   const Geom g = geom(m.n, m.h, B);
   const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
   uint8_t* w = (uint8_t*)ws;
@@ -690,6 +690,8 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
   fwd_hidden_kernel<T, true><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c,
                                                                     m.n, m.h, B, R, g.ldh, Rt, g.ldB);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the first product does not read coef; it may overlap the work that produces it
+  if (coef_ready && (e = hipStreamWaitEvent(st, coef_ready, 0)) != hipSuccess) return e;
   fwd_out_kernel<T, 1><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
       R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, nullptr, coef, G, Gt,
       St, g.ldB, db2_part, 0, 0, 0, 0, 0, nullptr);
@@ -744,9 +746,9 @@ hipError_t launch_logprob(const vqmc_made& m, const int8_t* S, int64_t B, float*
 }
 
 hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                           float* dP, float* db1, float* db2, void* ws, hipStream_t st) {
-  if (m.wdtype == VQMC_BF16) return backward_t<bf16_t>(m, S, B, coef, dP, db1, db2, ws, st);
-  return backward_t<float>(m, S, B, coef, dP, db1, db2, ws, st);
+                           float* dP, float* db1, float* db2, void* ws, hipStream_t st, hipEvent_t coef_ready) {
+  if (m.wdtype == VQMC_BF16) return backward_t<bf16_t>(m, S, B, coef, dP, db1, db2, ws, st, coef_ready);
+  return backward_t<float>(m, S, B, coef, dP, db1, db2, ws, st, coef_ready);
 }
 
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,

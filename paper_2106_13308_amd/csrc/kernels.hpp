@@ -36,8 +36,10 @@ struct FwdWorkspace;
 size_t logprob_ws_bytes(int n, int h, int64_t B, int dtype, bool backward);
 hipError_t launch_logprob(const vqmc_made& m, const int8_t* S, int64_t B, float* logp, float* Z,
                           void* ws, hipStream_t st);
+// coef_ready (nullable): event the output-layer product waits for before reading coef
 hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                           float* dP, float* db1, float* db2, void* ws, hipStream_t st);
+                           float* dP, float* db1, float* db2, void* ws, hipStream_t st,
+                           hipEvent_t coef_ready = nullptr);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,
