@@ -232,12 +232,10 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
   }
   __syncthreads();
 
+  // bounds of the current block; those of the next block are loaded during the current one
+  int d1 = block_end(0), c0 = c[0], c1 = c[d1 - 1];
   for (int d0 = 0; d0 < n;) {
-    // ---------------- block bounds (uniform)
-    const int c0 = c[d0];
-    const int d1 = block_end(d0);
     const int Tb = d1 - d0;
-    const int c1 = c[d1 - 1];
     const int U = c1 - c0;
     const bool fastpb = U <= SB_UB;
 
@@ -293,8 +291,12 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
     const int p3base = (c1 & ~15) + 16 * wv;
     if (p3base < h) fetch_p3(q0, d0, p3base);
     if (p3base + 64 < h) fetch_p3(q1, d0, p3base + 64);
+    int d1n = n, c0n = 0, c1n = 0;
     if (d1 < n) {
-      const int nch = (c[d1] + KC - 1) / KC;
+      c0n = c[d1];
+      d1n = block_end(d1);
+      c1n = c[d1n - 1];
+      const int nch = (c0n + KC - 1) / KC;
       if (kh < nch) fetch_p1(f0, d1, kh * KC);
       if (kh + 2 < nch) fetch_p1(f1, d1, (kh + 2) * KC);
     }
@@ -471,6 +473,9 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
     }
     __syncthreads();
     d0 = d1;
+    d1 = d1n;
+    c0 = c0n;
+    c1 = c1n;
   }
 
   // log pi: sum the 16 per-thread partials of each sample (one 16-lane DPP row)
