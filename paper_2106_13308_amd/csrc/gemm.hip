@@ -185,7 +185,7 @@ struct RowsA {
 
 // ---------------------------------------------------------------- tile engine
 // Thread t stages rows (t / 4) + 64 v, element chunk (t % 4) * VEC of each operand.
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int PD = 6>
 struct Engine {
   static constexpr int BK = Mfma<T>::BK, VEC = Mfma<T>::VEC;
   static constexpr int FM = BM / 32, FN = BN / 32;
@@ -204,56 +204,51 @@ struct Engine {
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
     if (kbeg >= kend) return;
-    // two raw register sets: the tile multiplied at step i was fetched at step i-2
-    typename LA::Raw ra0[AV], ra1[AV];
-    typename LB::Raw rb0[BV], rb1[BV];
-    auto fetch = [&](typename LA::Raw(&ra)[AV], typename LB::Raw(&rb)[BV], int k) {
+    // a ring of PD raw register sets: the stage multiplied at step i was fetched at step
+    // i - PD + 1, so PD - 1 steps of work cover the global-memory latency
+    typename LA::Raw ra[PD][AV];
+    typename LB::Raw rb[PD][BV];
+    const int nsteps = (kend - kbeg + BK - 1) / BK;
 #pragma unroll
-      for (int v = 0; v < AV; ++v) ra[v] = la.fetch(v, k + q);
+    for (int p = 0; p < PD; ++p)
+      if (p < nsteps) {
 #pragma unroll
-      for (int v = 0; v < BV; ++v) rb[v] = lb.fetch(v, k + q);
-    };
-    auto store = [&](uint8_t* st, const typename LA::Raw(&ra)[AV], const typename LB::Raw(&rb)[BV], int k) {
+        for (int v = 0; v < AV; ++v) ra[p][v] = la.fetch(v, kbeg + p * BK + q);
+#pragma unroll
+        for (int v = 0; v < BV; ++v) rb[p][v] = lb.fetch(v, kbeg + p * BK + q);
+      }
+    auto store = [&](uint8_t* st, int p, int k) {
 #pragma unroll
       for (int v = 0; v < AV; ++v) {
-        const Vec<T> x = la.finish(v, ra[v], k + q);
+        const Vec<T> x = la.finish(v, ra[p][v], k + q);
         *(uint4*)(st + (r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&x;
       }
 #pragma unroll
       for (int v = 0; v < BV; ++v) {
-        const Vec<T> x = lb.finish(v, rb[v], k + q);
+        const Vec<T> x = lb.finish(v, rb[p][v], k + q);
         *(uint4*)(st + (BM + r0 + 64 * v) * ROWB + (t & 3) * 16) = *(const uint4*)&x;
       }
     };
-    fetch(ra0, rb0, kbeg);
-    if (kbeg + BK < kend) fetch(ra1, rb1, kbeg + BK);
-    store(smem, ra0, rb0, kbeg);
+    store(smem, 0, kbeg);
     __syncthreads();
-    int cur = 0;
-    int k0 = kbeg;
-    while (true) {
-      // set 1 holds tile k0 + BK; set 0 is free
-      if (k0 + 2 * BK < kend) fetch(ra0, rb0, k0 + 2 * BK);
-      {
-        const uint8_t* st = smem + cur * STAGE;
-        Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
+    for (int base = 0; base < nsteps; base += PD) {
+#pragma unroll
+      for (int p = 0; p < PD; ++p) {
+        const int i = base + p;  // step being multiplied (its stage is in LDS buffer i & 1)
+        if (i < nsteps) {
+          // refill the ring slot of step i with step i + PD
+          if (i + PD < nsteps) {
+#pragma unroll
+            for (int v = 0; v < AV; ++v) ra[p][v] = la.fetch(v, kbeg + (i + PD) * BK + q);
+#pragma unroll
+            for (int v = 0; v < BV; ++v) rb[p][v] = lb.fetch(v, kbeg + (i + PD) * BK + q);
+          }
+          const uint8_t* st = smem + (i & 1) * STAGE;
+          Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
+          if (i + 1 < nsteps) store(smem + ((i + 1) & 1) * STAGE, (p + 1) % PD, kbeg + (i + 1) * BK);
+          __syncthreads();
+        }
       }
-      if (k0 + BK < kend) store(smem + (cur ^ 1) * STAGE, ra1, rb1, k0 + BK);
-      __syncthreads();
-      cur ^= 1;
-      k0 += BK;
-      if (k0 >= kend) break;
-      // set 0 holds tile k0 + BK; set 1 is free
-      if (k0 + 2 * BK < kend) fetch(ra1, rb1, k0 + 2 * BK);
-      {
-        const uint8_t* st = smem + cur * STAGE;
-        Mfma<T>::template tile<FM, FN>(st, st + BM * ROWB, wm, wn, lane, acc);
-      }
-      if (k0 + BK < kend) store(smem + (cur ^ 1) * STAGE, ra0, rb0, k0 + BK);
-      __syncthreads();
-      cur ^= 1;
-      k0 += BK;
-      if (k0 >= kend) break;
     }
   }
 };
@@ -270,9 +265,10 @@ __device__ inline RowsA<T, NV> rows_plain(const T* X, int64_t ld, int64_t R0, in
 }
 
 // tile shapes of the four products
-constexpr int H_BM = 64, H_BN = 64;     // hidden-layer products (N = h), many small tiles
-constexpr int O_BM = 128, O_BN = 128;   // output-layer product (N = n)
-constexpr int W_BM = 128, W_BN = 128;   // weight gradient (M = n, N = h)
+// 64 x 64 tiles everywhere: many workgroups per CU hide latency that one cannot
+constexpr int H_BM = 64, H_BN = 64;     // hidden-layer products (N = h)
+constexpr int O_BM = 64, O_BN = 64;     // output-layer product (N = n)
+constexpr int W_BM = 64, W_BN = 64;     // weight gradient (M = n, N = h)
 
 // ---------------------------------------------------------------- K1: first layer
 // A = S * P_upper + b1 ; writes R = relu(A) (B x ldh) and optionally Rt (h x ldB).
@@ -352,6 +348,24 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
     lb.lo[v] = 0;
     lb.hi[v] = (d < n) ? c[d] : 0;
   }
+  // the epilogue's spins and coefficients are loaded before the K loop so that their
+  // latency is hidden behind it
+  int8_t spre[E::FM][E::FN][4];
+  float cpre[E::FM][4];
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int i = 0; i < E::FM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t b = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+        cpre[i][e] = (MODE == 1 && b < B) ? coef[b] : 0.f;
+#pragma unroll
+        for (int j = 0; j < E::FN; ++j) {
+          const int d = d0 + wn + j * 16 + (lane & 15);
+          spre[i][j][e] = (b < B && d < n) ? S[b * lds + d] : (int8_t)0;
+        }
+      }
+  }
   floatx4_t acc[E::FM][E::FN];
   E::run(smem, 0, kend, la, lb, acc);
   if constexpr (MODE == 2) {
@@ -403,12 +417,12 @@ __global__ __launch_bounds__(256) void fwd_out_kernel(
         const int64_t b = bb + e;
         const bool ok = dv && b < B;
         const float z = acc[i][j][e] + bias;
-        const float s = ok ? (float)S[b * lds + d] : 0.f;
+        const float s = (float)spre[i][j][e];
         const float tt = s * z;
         if (ok) rs[i][e] += log_sigmoid(tt);
         if (Z && ok) Z[b * ldn + d] = z;
         if (MODE == 1) {
-          const float g = ok ? coef[b] * s * sigmoid(-tt) : 0.f;
+          const float g = ok ? cpre[i][e] * s * sigmoid(-tt) : 0.f;
           cs[j] += g;
           gv[e] = from_f32<T>(g);
           sv[e] = spin_val<T>((int8_t)s);

@@ -38,6 +38,8 @@ namespace vqmc {
 constexpr int SB_MS = 16;   // samples per workgroup
 constexpr int SB_T = 64;    // max sites per block
 constexpr int SB_UB = 32;   // in-block units whose weights are staged in LDS
+constexpr int PD1 = 6;      // phase-1 weight chunks in flight per wave
+constexpr int PD3 = 6;      // phase-3 weight tiles in flight per wave
 
 __host__ __device__ inline int sb_lda(int h) { return (int)round_up(h, 32) + 4; }
 
@@ -223,12 +225,18 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
     st[i] = (k < h) ? b1[k] : 0.f;
   }
   float lp_part = 0.f;
-  // phase-1 fragments of the first two chunks of the first block
-  typename F::P1 f0, f1;
+  // phase-1 fragment ring: slot p holds this wave's chunk it with it = p (mod PD1);
+  // the first PD1 chunks of a block are fetched during the previous block
+  typename F::P1 fr[PD1];
+  auto chunks_of = [&](int cc0) {  // this wave's chunks kh, kh+2, ... below cc0
+    const int nch = (cc0 + KC - 1) / KC;
+    return (nch > kh) ? (nch - kh + 1) / 2 : 0;
+  };
   {
-    const int nch = (c[0] + KC - 1) / KC;
-    if (kh < nch) fetch_p1(f0, 0, kh * KC);
-    if (kh + 2 < nch) fetch_p1(f1, 0, (kh + 2) * KC);
+    const int cnt = chunks_of(c[0]);
+#pragma unroll
+    for (int p = 0; p < PD1; ++p)
+      if (p < cnt) fetch_p1(fr[p], 0, (kh + 2 * p) * KC);
   }
   __syncthreads();
 
@@ -239,9 +247,14 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
     const int U = c1 - c0;
     const bool fastpb = U <= SB_UB;
 
-    // ---------------- staging (no conflict with phase 1)
-    if (t < Tb) cb[t] = c[d0 + t];
-    if (t == 0) cb[Tb] = c1;
+    // ---------------- staging: loads now, LDS stores after phase 1 (no wait here)
+    const int cbv = (t < Tb) ? c[d0 + t] : 0;
+    float pbv[SB_T * SB_UB / 256];
+#pragma unroll
+    for (int q = 0; q < SB_T * SB_UB / 256; ++q) {
+      const int i = t + 256 * q;
+      pbv[q] = (fastpb && i < Tb * U) ? to_f32(P[(int64_t)(d0 + i / U) * ldh + c0 + i % U]) : 0.f;
+    }
     {
       const int s = t >> 4, q4 = t & 15;  // 16 samples x 16 groups of 4 sites
       if (4 * q4 < Tb) {
@@ -255,25 +268,20 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
         }
       }
     }
-    if (fastpb) {
-      for (int i = t; i < Tb * U; i += 256) {
-        const int j = i / U, uu = i % U;
-        pb[j * SB_UB + uu] = to_f32(P[(int64_t)(d0 + j) * ldh + c0 + uu]);
-      }
-    }
 
-    // ---------------- phase 1: Zp = relu(A[:, :c0]) P[block, :c0]^T, fragments two chunks ahead
+    // ---------------- phase 1: Zp = relu(A[:, :c0]) P[block, :c0]^T, fragments PD1 chunks ahead
     {
       floatx4_t acc[2];
       acc[0] = acc[1] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-      const int nch = (c0 + KC - 1) / KC;
-      const int cnt = (nch > kh) ? (nch - kh + 1) / 2 : 0;  // this wave's chunks kh, kh+2, ...
-      for (int it = 0; it < cnt; it += 2) {
-        use_p1(f0, (kh + 2 * it) * KC, c0, acc);
-        if (it + 2 < cnt) fetch_p1(f0, d0, (kh + 2 * (it + 2)) * KC);
-        if (it + 1 < cnt) {
-          use_p1(f1, (kh + 2 * (it + 1)) * KC, c0, acc);
-          if (it + 3 < cnt) fetch_p1(f1, d0, (kh + 2 * (it + 3)) * KC);
+      const int cnt = chunks_of(c0);
+      for (int base = 0; base < cnt; base += PD1) {
+#pragma unroll
+        for (int p = 0; p < PD1; ++p) {
+          const int it = base + p;
+          if (it < cnt) {
+            use_p1(fr[p], (kh + 2 * it) * KC, c0, acc);
+            if (it + PD1 < cnt) fetch_p1(fr[p], d0, (kh + 2 * (it + PD1)) * KC);
+          }
         }
       }
       // C layout: lane l holds rows (sites) 4*(l/16)+e, column (sample) l%16
@@ -285,20 +293,31 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
           red[(kh * SB_T + j) * SB_MS + l16] = acc[mt][e];
         }
     }
-    // fragments for later: the first two phase-3 tiles of this block and the first two
+    // staged values of this block
+    if (t < Tb) cb[t] = cbv;
+    if (t == 0) cb[Tb] = c1;
+#pragma unroll
+    for (int q = 0; q < SB_T * SB_UB / 256; ++q) {
+      const int i = t + 256 * q;
+      if (fastpb && i < Tb * U) pb[(i / U) * SB_UB + i % U] = pbv[q];
+    }
+    // fragments for later: the first PD3 phase-3 tiles of this block and the first PD1
     // phase-1 chunks of the next block; their loads overlap the serial phase
-    typename F::P3 q0, q1;
+    typename F::P3 gr[PD3];
     const int p3base = (c1 & ~15) + 16 * wv;
-    if (p3base < h) fetch_p3(q0, d0, p3base);
-    if (p3base + 64 < h) fetch_p3(q1, d0, p3base + 64);
+    const int ntile = (p3base < h) ? (h - p3base + 63) / 64 : 0;
+#pragma unroll
+    for (int p = 0; p < PD3; ++p)
+      if (p < ntile) fetch_p3(gr[p], d0, p3base + 64 * p);
     int d1n = n, c0n = 0, c1n = 0;
     if (d1 < n) {
       c0n = c[d1];
       d1n = block_end(d1);
       c1n = c[d1n - 1];
-      const int nch = (c0n + KC - 1) / KC;
-      if (kh < nch) fetch_p1(f0, d1, kh * KC);
-      if (kh + 2 < nch) fetch_p1(f1, d1, (kh + 2) * KC);
+      const int cntn = chunks_of(c0n);
+#pragma unroll
+      for (int p = 0; p < PD1; ++p)
+        if (p < cntn) fetch_p1(fr[p], d1, (kh + 2 * p) * KC);
     }
     __syncthreads();
 #pragma unroll
@@ -348,7 +367,6 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
             if (inrun) {
               if (up) dec |= 1u << m;
               else zr[m] = -zr[m];
-              lp_part += log_sigmoid(zr[m]);
             }
             bm[m] = __ballot(inrun && up);
           }
@@ -359,11 +377,21 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
               const int u = c0 + l16 + 16 * mm;
               if (u >= cr && u < c1) {
                 float a0 = ar[mm], a1 = 0.f;
-                for (int j = i; j < ie; ++j) {
-                  const uint64_t bj = (j < 16) ? bm[0] : (j < 32) ? bm[1] : (j < 48) ? bm[2] : bm[3];
-                  const float sg = ((bj >> (16 * g + (j & 15))) & 1ull) ? 1.f : -1.f;
-                  const float w = pb[j * SB_UB + (u - c0)];
-                  if (j & 1) a1 = fmaf(sg, w, a1); else a0 = fmaf(sg, w, a0);
+                for (int jb = i; jb < ie; jb += 8) {
+                  // eight sites at a time: all LDS reads issued before the FMAs
+                  float w8[8], s8[8];
+#pragma unroll
+                  for (int q = 0; q < 8; ++q) {
+                    const int j = jb + q;
+                    const uint64_t bj = (j < 16) ? bm[0] : (j < 32) ? bm[1] : (j < 48) ? bm[2] : bm[3];
+                    s8[q] = ((bj >> (16 * g + (j & 15))) & 1ull) ? 1.f : -1.f;
+                    w8[q] = (j < ie) ? pb[j * SB_UB + (u - c0)] : 0.f;
+                  }
+#pragma unroll
+                  for (int q = 0; q < 8; q += 2) {
+                    a0 = fmaf(s8[q], w8[q], a0);
+                    a1 = fmaf(s8[q + 1], w8[q + 1], a1);
+                  }
                 }
                 ar[mm] = a0 + a1;
               }
@@ -390,7 +418,10 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int j = l16 + 16 * m;
-          if (j < Tb) sbk[s * SB_T + j] = ((dec >> m) & 1u) ? (int8_t)1 : (int8_t)-1;
+          if (j < Tb) {
+            sbk[s * SB_T + j] = ((dec >> m) & 1u) ? (int8_t)1 : (int8_t)-1;
+            lp_part += log_sigmoid(zr[m]);  // zr holds s_d z_d
+          }
         }
       } else {
         // many units complete inside the block: work through LDS, weights from global
@@ -451,7 +482,7 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
       }
     }
 
-    // ---------------- phase 3: A[:, c1:] += S_block P[block, c1:], fragments two tiles ahead
+    // ---------------- phase 3: A[:, c1:] += S_block P[block, c1:], fragments PD3 tiles ahead
     {
       bf16x8_t sv[2];
 #pragma unroll
@@ -462,12 +493,14 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
           const int8_t v = (j < Tb) ? sbk[l16 * SB_T + j] : (int8_t)0;
           sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
         }
-      for (int k0 = p3base; k0 < h; k0 += 128) {
-        use_p3(q0, k0, c1, sv);
-        if (k0 + 128 < h) fetch_p3(q0, d0, k0 + 128);
-        if (k0 + 64 < h) {
-          use_p3(q1, k0 + 64, c1, sv);
-          if (k0 + 192 < h) fetch_p3(q1, d0, k0 + 192);
+      for (int base = 0; base < ntile; base += PD3) {
+#pragma unroll
+        for (int p = 0; p < PD3; ++p) {
+          const int i = base + p;
+          if (i < ntile) {
+            use_p3(gr[p], p3base + 64 * i, c1, sv);
+            if (i + PD3 < ntile) fetch_p3(gr[p], d0, p3base + 64 * (i + PD3));
+          }
         }
       }
     }
