@@ -371,6 +371,9 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
             bm[m] = __ballot(inrun && up);
           }
           if (cr < c1) {
+            // this lane's sample: bit j = spin of site j is +1 (sites of the run only)
+            const uint64_t sm = ((bm[0] >> (16 * g)) & 0xFFFFull) | (((bm[1] >> (16 * g)) & 0xFFFFull) << 16) |
+                                (((bm[2] >> (16 * g)) & 0xFFFFull) << 32) | (((bm[3] >> (16 * g)) & 0xFFFFull) << 48);
             // in-block units not yet complete receive the run's spins
 #pragma unroll
             for (int mm = 0; mm < 2; ++mm) {
@@ -383,8 +386,7 @@ __global__ __launch_bounds__(256) void sample_blocked_kernel(
 #pragma unroll
                   for (int q = 0; q < 8; ++q) {
                     const int j = jb + q;
-                    const uint64_t bj = (j < 16) ? bm[0] : (j < 32) ? bm[1] : (j < 48) ? bm[2] : bm[3];
-                    s8[q] = ((bj >> (16 * g + (j & 15))) & 1ull) ? 1.f : -1.f;
+                    s8[q] = ((sm >> (j & 63)) & 1ull) ? 1.f : -1.f;
                     w8[q] = (j < ie) ? pb[j * SB_UB + (u - c0)] : 0.f;
                   }
 #pragma unroll
