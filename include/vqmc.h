@@ -62,7 +62,11 @@ typedef enum {
 /* MADE parameters in the kernels' working precision (produced by vqmc_cast).
  *   P  : n rows x vqmc_ld(h) columns, dtype wdtype, zero padding.
  *   Pt : h rows x vqmc_ld(n) columns, the transpose of P (same values), zero padding.
- *   b1 : h floats (hidden bias), b2 : n floats (output bias), c : n int32 (see above). */
+ *   b1 : h floats (hidden bias), b2 : n floats (output bias), c : n int32 (see above).
+ *   band (nullable): h records of VQMC_BAND_REC floats written by vqmc_band from P/Pt
+ *   and c.  When present, vqmc_sample runs its pipelined kernel; it must be rebuilt
+ *   whenever P changes. */
+#define VQMC_BAND_REC 132
 typedef struct {
   int32_t n, h;
   int32_t wdtype; /* VQMC_F32 or VQMC_BF16 */
@@ -71,6 +75,7 @@ typedef struct {
   const float* b1;
   const float* b2;
   const int32_t* c;
+  const float* band;
 } vqmc_made;
 
 typedef enum { VQMC_H_CSR_INT = 0, VQMC_H_CSR_F32 = 1, VQMC_H_DENSE_F32 = 2 } vqmc_hkind;
@@ -127,12 +132,26 @@ int vqmc_unpack(int32_t n, int32_t h, const float* P32, const int32_t* c, float*
 int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt,
               void* stream);
 
+/* The sampler's per-unit band (Algorithm 1, incremental form; the MADE masks of Sec. 2.3
+ * split each unit's weights by site).  Unit k completes inside the 64-site block
+ * [64q, 64q + 64), q = floor(m(k) / 64) (0-based block of site m(k)).  Its record holds,
+ * for the block's sites d = 64q + j (j < 64; entries with d >= n are 0):
+ *   rec[j]      = 2 W1[k][d] if d feeds k (k >= c[d]), else 0
+ *   rec[64 + j] = W2[d][k]   if k feeds d (k < c[d]),  else 0
+ *   rec[128..131] = -(sum over j of W1[k][d] for the sites feeding k), four copies
+ * with the values of P in its working precision, widened to float.  band: h *
+ * VQMC_BAND_REC floats (device, 16-byte aligned), overwritten.  Needs m->Pt and m->c;
+ * m->band is ignored. */
+int vqmc_band(const vqmc_made* m, float* band, void* stream);
+
 /* ------------------------------------------------------------------ the hot path */
 /* Algorithm 1 (autoregressive sampling), incremental form: each sample keeps its h
  * hidden pre-activations on chip; after drawing s_d it adds s_d * W1[k][d] to the
  * units that receive site d, and each logit is a dot product over the units already
  * complete.  Exactly the conditionals of n full forward passes, O(nh) per sample.
- * Writes S (B x ld(n) int8) and, if logp != NULL, log pi(S) (B floats). */
+ * Writes S (B x ld(n) int8, 8-byte aligned) and, if logp != NULL, log pi(S) (B floats).
+ * With m->band set (see vqmc_band) the draw runs the pipelined kernel, else the blocked
+ * one; both draw the same spins up to FP32 rounding of the logits. */
 int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
                 uint32_t tag, int8_t* S, float* logp, void* stream);
 

@@ -25,6 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
 WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP = 0, 1, 2, 3
+BAND_REC = 132
 TAG_TRAIN, TAG_EVAL = 0, 1
 
 _vp = ctypes.c_void_p
@@ -33,7 +34,7 @@ _i32, _i64, _u32, _u64, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, c
 
 class MadeC(ctypes.Structure):
     _fields_ = [("n", _i32), ("h", _i32), ("wdtype", _i32), ("P", _vp), ("Pt", _vp),
-                ("b1", _vp), ("b2", _vp), ("c", _vp)]
+                ("b1", _vp), ("b2", _vp), ("c", _vp), ("band", _vp)]
 
 
 class HamC(ctypes.Structure):
@@ -56,6 +57,7 @@ _SIGS = {
     "vqmc_pack": (ctypes.c_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vqmc_unpack": (ctypes.c_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "vqmc_band": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _vp]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
     "vqmc_sample_plain": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp,
                                          _vp, _sz, _vp]),
@@ -113,10 +115,11 @@ def _dev(t: torch.Tensor) -> torch.Tensor:
 # ---------------------------------------------------------------- parameters
 class Made:
     """MADE parameters: the FP32 master packed matrix P32 (n x h), biases, the
-    staircase index c, and the kernels' working copies (P, Pt) in ``wdtype``."""
+    staircase index c, and the kernels' working copies (P, Pt, and the sampler's band
+    unless ``band=False``) in ``wdtype``."""
 
     def __init__(self, n: int, h: int, P32: torch.Tensor, b1: torch.Tensor, b2: torch.Tensor,
-                 c: torch.Tensor, wdtype: int = F32):
+                 c: torch.Tensor, wdtype: int = F32, band: bool = True):
         self.n, self.h = int(n), int(h)
         self.P32, self.b1, self.b2, self.c = P32, b1, b2, c
         self.wdtype = wdtype
@@ -124,10 +127,11 @@ class Made:
         tdt = torch.bfloat16 if wdtype == BF16 else torch.float32
         self.P = torch.zeros((self.n, ld(self.h)), dtype=tdt, device=dev)
         self.Pt = torch.zeros((self.h, ld(self.n)), dtype=tdt, device=dev)
+        self.band = torch.zeros((self.h, BAND_REC), dtype=torch.float32, device=dev) if band else None
         self.refresh()
 
     @classmethod
-    def from_dense(cls, W1, b1, W2, b2, degrees, wdtype: int = F32, device="cuda"):
+    def from_dense(cls, W1, b1, W2, b2, degrees, wdtype: int = F32, device="cuda", band: bool = True):
         """Pack dense float32 weights (numpy or torch) on the device."""
         W1 = torch.as_tensor(np.asarray(W1, np.float32), device=device).contiguous()
         W2 = torch.as_tensor(np.asarray(W2, np.float32), device=device).contiguous()
@@ -139,16 +143,19 @@ class Made:
                                            deg.ctypes.data_as(_vp), P32.data_ptr(), c.data_ptr(), _stream()))
         b1t = torch.as_tensor(np.asarray(b1, np.float32), device=device).contiguous()
         b2t = torch.as_tensor(np.asarray(b2, np.float32), device=device).contiguous()
-        return cls(n, h, P32, b1t, b2t, c, wdtype)
+        return cls(n, h, P32, b1t, b2t, c, wdtype, band)
 
     def refresh(self):
         """Re-derive the working copies after P32 changed (e.g. after an optimiser step)."""
         _check("vqmc_cast", _lib.vqmc_cast(self.n, self.h, self.P32.data_ptr(), self.wdtype,
                                            self.P.data_ptr(), self.Pt.data_ptr(), _stream()))
+        if self.band is not None:
+            m = self.cstruct()
+            _check("vqmc_band", _lib.vqmc_band(ctypes.byref(m), self.band.data_ptr(), _stream()))
 
     def cstruct(self) -> MadeC:
         return MadeC(self.n, self.h, self.wdtype, self.P.data_ptr(), self.Pt.data_ptr(),
-                     self.b1.data_ptr(), self.b2.data_ptr(), self.c.data_ptr())
+                     self.b1.data_ptr(), self.b2.data_ptr(), self.c.data_ptr(), _ptr(self.band))
 
     def unpack(self, P32: torch.Tensor | None = None):
         """Dense (W1, W2) from a packed matrix (default: the master weights)."""

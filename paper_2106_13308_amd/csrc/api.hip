@@ -145,12 +145,22 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
   return hip_status(launch_cast(n, h, P32, dtype, P, Pt, (hipStream_t)stream), "vqmc_cast");
 }
 
+int vqmc_band(const vqmc_made* m, float* band, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (!band) return fail(VQMC_EINVAL, "band is NULL");
+  if ((uintptr_t)band & 15) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
+  return hip_status(launch_band(*m, band, (hipStream_t)stream), "vqmc_band");
+}
+
 int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
                 uint32_t tag, int8_t* S, float* logp, void* stream) {
   int r = check_made(m, false);
   if (r) return r;
   if (B < 1) return fail(VQMC_EINVAL, "B must be >= 1");
   if (!S) return fail(VQMC_EINVAL, "S is NULL");
+  if ((uintptr_t)S & 7) return fail(VQMC_EINVAL, "S must be 8-byte aligned");
+  if (m->band && ((uintptr_t)m->band & 15)) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
   if (sample_offset < 0) return fail(VQMC_EINVAL, "sample_offset < 0");
   if (m->h > kMaxSamplerH) return fail(VQMC_EINVAL, "h = %d exceeds the sampler limit %d", m->h, kMaxSamplerH);
   return hip_status(
@@ -239,6 +249,8 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
     return fail(VQMC_EINVAL, "bad step arguments");
   if (algo != 0 && algo != 1) return fail(VQMC_EINVAL, "algo must be 0 (incremental) or 1 (plain)");
   if (algo == 0 && m->h > kMaxSamplerH) return fail(VQMC_EINVAL, "h exceeds the sampler limit");
+  if ((uintptr_t)S & 7) return fail(VQMC_EINVAL, "S must be 8-byte aligned");
+  if (m->band && ((uintptr_t)m->band & 15)) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
   const size_t need = vqmc_workspace_bytes(VQMC_WS_STEP, m->n, m->h, B, m->wdtype);
   if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t st = (hipStream_t)stream;

@@ -28,6 +28,10 @@ hipError_t launch_sample_incremental(const vqmc_made& m, int64_t B, uint64_t see
 bool sample_blocked_supported(int n, int h);
 hipError_t launch_sample_blocked(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                  uint32_t tag, int8_t* S, float* logp, hipStream_t st);
+bool sample_pipe_supported(int n, int h);
+hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
+                              uint32_t tag, int8_t* S, float* logp, hipStream_t st);
+hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st);
 hipError_t launch_uniforms(int n, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
                            float* u, hipStream_t st);
 

@@ -177,6 +177,8 @@ hipError_t launch_sample_incremental(const vqmc_made& m, int64_t B, uint64_t see
                                      hipStream_t st) {
   // the blocked MFMA sampler keeps 16 samples' state in LDS; beyond its LDS budget the
   // register-resident kernel above takes over
+  if (m.Pt && m.band && sample_pipe_supported(m.n, m.h))
+    return launch_sample_pipe(m, B, seed, step, offset, tag, S, logp, st);
   if (m.Pt && sample_blocked_supported(m.n, m.h))
     return launch_sample_blocked(m, B, seed, step, offset, tag, S, logp, st);
   if (m.wdtype == VQMC_BF16) return launch_w<bf16_t>(m, B, seed, step, offset, tag, S, logp, st);

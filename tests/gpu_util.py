@@ -19,9 +19,11 @@ def oracle_params(p: dict, wdtype: int) -> dict:
     return q
 
 
-def build_made(p: dict, wdtype: int):
+def build_made(p: dict, wdtype: int, band: bool = True):
+    """band=True selects the pipelined sampler, band=False the blocked one."""
     from paper_2106_13308_amd import binding as B
-    return B.Made.from_dense(p["W1"], p["b1"], p["W2"], p["b2"], p["degrees"], wdtype=wdtype, device=DEV)
+    return B.Made.from_dense(p["W1"], p["b1"], p["W2"], p["b2"], p["degrees"], wdtype=wdtype, device=DEV,
+                             band=band)
 
 
 def spins_np(S: torch.Tensor, n: int) -> np.ndarray:

@@ -209,13 +209,14 @@ def test_logprob_backward(n, h, B, wd):
 SAMPLE_CASES = [(20, 40, 1024), (67, 33, 100), (500, 500, 4096), (200, 300, 257), (2, 1, 9), (10000, 1000, 2048)]
 
 
+@pytest.mark.parametrize("kernel", ["pipe", "blocked"])
 @pytest.mark.parametrize("wd", ["f32", "bf16"])
 @pytest.mark.parametrize("n,h,B", SAMPLE_CASES)
-def test_sample_incremental_teacher_forced(n, h, B, wd):
-    _banner(f"sample n={n} h={h} B={B} {wd}")
+def test_sample_incremental_teacher_forced(n, h, B, wd, kernel):
+    _banner(f"sample n={n} h={h} B={B} {wd} {kernel}")
     wdtype = B_.F32 if wd == "f32" else B_.BF16
     p, _ = instance(n, h, seed=10, graph=None, scale=3.0)
-    M = build_made(p, wdtype)
+    M = build_made(p, wdtype, band=kernel == "pipe")
     seed, step = 2, 3
     S, lp = B_.sample(M, B, seed, step)
     S_all = S.cpu().numpy()
@@ -247,16 +248,18 @@ def _degree_pattern(kind, n, h):
     raise ValueError(kind)
 
 
+@pytest.mark.parametrize("kernel", ["pipe", "blocked"])
 @pytest.mark.parametrize("wd", ["f32", "bf16"])
 @pytest.mark.parametrize("kind,n,h,B", [("all_first", 50, 90, 40), ("all_last", 70, 60, 33),
                                         ("clustered", 301, 150, 48), ("default", 9, 700, 17),
-                                        ("default", 131, 2500, 20)])
-def test_sample_degree_patterns_teacher_forced(kind, n, h, B, wd):
-    _banner(f"sample degrees={kind} n={n} h={h} B={B} {wd}")
+                                        ("default", 131, 2500, 20), ("default", 64, 64, 8),
+                                        ("clustered", 129, 40, 15)])
+def test_sample_degree_patterns_teacher_forced(kind, n, h, B, wd, kernel):
+    _banner(f"sample degrees={kind} n={n} h={h} B={B} {wd} {kernel}")
     wdtype = B_.F32 if wd == "f32" else B_.BF16
     p, _ = instance(n, h, seed=14, graph=None, scale=3.0)
     p["degrees"] = _degree_pattern(kind, n, h)
-    M = build_made(p, wdtype)
+    M = build_made(p, wdtype, band=kernel == "pipe")
     S, lp = B_.sample(M, B, 6, 1)
     S_np = spins_np(S, n)
     q = oracle_params(p, wdtype)
@@ -307,6 +310,51 @@ def test_sample_offset_shards_reproduce_full_batch():
     S, lp = B_.sample(M, 64, 5, 1)
     S2, lp2 = B_.sample(M, 24, 5, 1, offset=40)
     assert torch.equal(S[40:], S2) and torch.equal(lp[40:], lp2)
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+def test_sample_pipe_equals_blocked(wd):
+    """The two incremental kernels draw the same spins wherever the draw is not within
+    FP32 rounding of the boundary (same uniforms, same conditionals)."""
+    _banner(f"pipe vs blocked {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, _ = instance(700, 350, seed=21, graph=None, scale=3.0)
+    Mp = build_made(p, wdtype, band=True)
+    Mb = build_made(p, wdtype, band=False)
+    Sp, lpp = B_.sample(Mp, 96, 8, 5)
+    Sb, lpb = B_.sample(Mb, 96, 8, 5)
+    q = oracle_params(p, wdtype)
+    U = oph.uniforms(8, 5, np.arange(96), 700)
+    pref = omade.conditionals(q, spins_np(Sb, 700))
+    clean = (np.abs(U - pref) > 1e-4).all(axis=1)
+    assert clean.mean() > 0.9
+    assert np.array_equal(spins_np(Sp, 700)[clean], spins_np(Sb, 700)[clean])
+    assert np.allclose(lpp.cpu().numpy()[clean], lpb.cpu().numpy()[clean], rtol=1e-5, atol=1e-4)
+
+
+def test_band_layout():
+    """Band records against their definition, from the oracle's masks."""
+    _banner("band layout")
+    n, h = 150, 90
+    p, _ = instance(n, h, seed=5, graph=None)
+    M = build_made(p, B_.BF16)
+    band = M.band.cpu().numpy().astype(np.float64)
+    q = oracle_params(p, B_.BF16)
+    M1, M2 = omade.masks(n, p["degrees"])
+    W1 = M1 * np.asarray(q["W1"], np.float64)
+    W2 = M2 * np.asarray(q["W2"], np.float64)
+    deg = np.asarray(p["degrees"])
+    for k in range(h):
+        d0 = (deg[k] // 64) * 64
+        sites = np.arange(d0, d0 + 64)
+        ok = sites < n
+        w1 = np.zeros(64)
+        w2 = np.zeros(64)
+        w1[ok] = W1[k, sites[ok]]
+        w2[ok] = W2[sites[ok], k]
+        assert np.array_equal(band[k, :64], 2 * w1), k
+        assert np.array_equal(band[k, 64:128], w2), k
+        assert np.allclose(band[k, 128:], -w1.sum(), rtol=1e-6, atol=1e-6), k
 
 
 def test_sample_deterministic():
