@@ -152,6 +152,10 @@ def _dominant_desc(call, made, H):
     bf16 = made.wdtype == 2
     mm = PEAK["bf16_mfma_tflops"] if bf16 else PEAK["fp32_mfma_tflops"]
     if call == "sample":
+        if made.band is not None:
+            k = "sample_pipe_kernel<bf16>" if bf16 else "sample_pipe_kernel<float>"
+            return {"kernels": [k], "src": ["sample_pipe.hip"], "bound": "mfma", "peak": mm,
+                    "unit": "TFLOP/s", "metric": "tflops"}
         if made.h <= 2048:
             k = "sample_blocked_kernel<bf16>" if bf16 else "sample_blocked_kernel<float>"
             return {"kernels": [k], "src": ["sample_blocked.hip"], "bound": "mfma", "peak": mm,

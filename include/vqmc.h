@@ -66,7 +66,7 @@ typedef enum {
  *   band (nullable): h records of VQMC_BAND_REC floats written by vqmc_band from P/Pt
  *   and c.  When present, vqmc_sample runs its pipelined kernel; it must be rebuilt
  *   whenever P changes. */
-#define VQMC_BAND_REC 132
+#define VQMC_BAND_REC 260
 typedef struct {
   int32_t n, h;
   int32_t wdtype; /* VQMC_F32 or VQMC_BF16 */
@@ -135,10 +135,12 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
 /* The sampler's per-unit band (Algorithm 1, incremental form; the MADE masks of Sec. 2.3
  * split each unit's weights by site).  Unit k completes inside the 64-site block
  * [64q, 64q + 64), q = floor(m(k) / 64) (0-based block of site m(k)).  Its record holds,
- * for the block's sites d = 64q + j (j < 64; entries with d >= n are 0):
- *   rec[j]      = 2 W1[k][d] if d feeds k (k >= c[d]), else 0
- *   rec[64 + j] = W2[d][k]   if k feeds d (k < c[d]),  else 0
- *   rec[128..131] = -(sum over j of W1[k][d] for the sites feeding k), four copies
+ * for j < 64 (entries whose site is < 0 or >= n are 0):
+ *   rec[j]       = 2 W1[k][d] if site d = 64q + j feeds k (k >= c[d]), else 0
+ *   rec[64 + j]  = W2[d][k]   if k feeds site d = 64q + j (k < c[d]),  else 0
+ *   rec[128 + j] = 2 W1[k][d], d = 64(q-1) + j  (every site of the block before feeds k)
+ *   rec[192 + j] = W2[d][k],   d = 64(q+1) + j  (k feeds every site of the block after)
+ *   rec[256..259] = -(sum of the W1 entries above, halved back), four copies
  * with the values of P in its working precision, widened to float.  band: h *
  * VQMC_BAND_REC floats (device, 16-byte aligned), overwritten.  Needs m->Pt and m->c;
  * m->band is ignored. */

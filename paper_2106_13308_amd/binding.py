@@ -25,7 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
 WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP = 0, 1, 2, 3
-BAND_REC = 132
+BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
 _vp = ctypes.c_void_p

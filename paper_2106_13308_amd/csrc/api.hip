@@ -36,6 +36,13 @@ size_t step_energy_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
   return (size_t)round_up((int64_t)std::max(bw, sp), 256);
 }
 
+// Step workspace: [sampling / backward region][energy region][Zs: B x ld(n) floats, the
+// incremental sampler's s_d z_d, read by the backward]
+size_t step_zs_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  return step_energy_offset(n, h, B, wdtype) +
+         (size_t)round_up((int64_t)((n + 63) / 64) * B * (int64_t)sizeof(double), 256);
+}
+
 // One auxiliary stream (default priority) and two events per device, created on first
 // use and kept for the life of the process: vqmc_step runs the energy and statistics
 // on it while the main stream starts the backward.
@@ -97,11 +104,7 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_LOGPROB: return logprob_ws_bytes(n, h, B, wdtype, false);
     case VQMC_WS_BACKWARD: return logprob_ws_bytes(n, h, B, wdtype, true);
     case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
-    case VQMC_WS_STEP: {
-      // sampling and the backward reuse one region; the energy (which overlaps the
-      // backward's first product) gets its own region after it
-      return step_energy_offset(n, h, B, wdtype) + (size_t)((n + 63) / 64) * (size_t)B * sizeof(double);
-    }
+    case VQMC_WS_STEP: return step_zs_offset(n, h, B, wdtype) + (size_t)B * round_up(n, kPad) * sizeof(float);
     default: return 0;
   }
 }
@@ -254,9 +257,14 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
   const size_t need = vqmc_workspace_bytes(VQMC_WS_STEP, m->n, m->h, B, m->wdtype);
   if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = (algo == 0)
-                     ? launch_sample_incremental(*m, B, seed, step, sample_offset, 0, S, logp, st)
-                     : launch_sample_plain(*m, B, seed, step, sample_offset, 0, S, logp, ws, st);
+  // with the pipelined sampler the forward quantities of the backward (relu(A) and the
+  // logits) come out of the sampling itself
+  const bool fused = algo == 0 && m->Pt && m->band && sample_pipe_supported(m->n, m->h);
+  float* Zs = (float*)((uint8_t*)ws + step_zs_offset(m->n, m->h, B, m->wdtype));
+  hipError_t e = fused ? launch_sample_pipe(*m, B, seed, step, sample_offset, 0, S, logp, st, Zs,
+                                            backward_rt_slot(*m, B, ws))
+                 : (algo == 0) ? launch_sample_incremental(*m, B, seed, step, sample_offset, 0, S, logp, st)
+                               : launch_sample_plain(*m, B, seed, step, sample_offset, 0, S, logp, ws, st);
   if (e != hipSuccess) return hip_status(e, "vqmc_step sample");
   // energy + statistics on the auxiliary stream, overlapping the first backward product
   // (which only needs the spins); the main stream waits for them before reading coef
@@ -269,6 +277,12 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
   if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, aux->stream)) != hipSuccess)
     return hip_status(e, "vqmc_step stats");
   if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
+  if (fused) {
+    if ((e = hipStreamWaitEvent(st, aux->stats_done, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
+    if ((e = launch_backward_sampled(*m, S, B, coef, Zs, dP, db1, db2, ws, st)) != hipSuccess)
+      return hip_status(e, "vqmc_step backward");
+    return VQMC_OK;
+  }
   if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st, aux->stats_done)) != hipSuccess)
     return hip_status(e, "vqmc_step backward");
   return VQMC_OK;

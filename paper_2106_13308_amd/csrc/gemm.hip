@@ -584,6 +584,99 @@ __global__ __launch_bounds__(256) void bwd_weight_kernel(const T* __restrict__ X
     }
 }
 
+// ---------------------------------------------------------------- K2': output adjoint from
+// the sampler's logits.  The incremental sampler has already evaluated every logit; with
+// zs = s_d z_d it gives G = coef_b s_d sigma(-zs) directly (G, and batch-contiguous Gt, St,
+// and db2 partials, as K2 MODE 1 writes them).  64 samples x 64 sites per workgroup; the
+// transposed stores go through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void grad_out_kernel(const float* __restrict__ Zs, const int8_t* __restrict__ S,
+                                                        int64_t ldn, const float* __restrict__ coef, int n, int64_t B,
+                                                        T* __restrict__ G, T* __restrict__ Gt, T* __restrict__ St,
+                                                        int64_t ldB, float* __restrict__ db2_part) {
+  __shared__ float gs[64][65];
+  __shared__ int8_t sv[64][68];
+  const int t = threadIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.y * 64;  // samples
+  const int d0 = blockIdx.x * 64;               // sites
+  {
+    const int r = t >> 2, q = (t & 3) * 16;
+    const int64_t b = m0 + r;
+    float z[16];
+    int8_t s[16];
+    float cb = 0.f;
+    if (b < B) {
+      const float* zrow = Zs + b * ldn + d0 + q;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float4 x = *(const float4*)(zrow + 4 * v);
+        z[4 * v] = x.x; z[4 * v + 1] = x.y; z[4 * v + 2] = x.z; z[4 * v + 3] = x.w;
+      }
+      *(uint4*)s = *(const uint4*)(S + b * ldn + d0 + q);
+      cb = coef[b];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        z[e] = 0.f;
+        s[e] = 0;
+      }
+    }
+    T gv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const bool ok = b < B && d0 + q + e < n;
+      const float g = ok ? cb * (float)s[e] * sigmoid(-z[e]) : 0.f;
+      gv[e] = from_f32<T>(g);
+      gs[r][q + e] = g;
+      sv[r][q + e] = ok ? s[e] : (int8_t)0;
+    }
+    if (b < B) {
+      T* grow = G + b * ldn + d0 + q;
+      if constexpr (sizeof(T) == 2) {
+        *(uint4*)grow = *(const uint4*)gv;
+        *(uint4*)(grow + 8) = *(const uint4*)(gv + 8);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) *(uint4*)(grow + 4 * v) = *(const uint4*)(gv + 4 * v);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int dl = t >> 2, bq = (t & 3) * 16;
+    const int d = d0 + dl;
+    float colsum = 0.f;
+    T gv[16], svv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const float g = gs[bq + e][dl];
+      colsum += g;
+      gv[e] = from_f32<T>(g);
+      svv[e] = spin_val<T>(sv[bq + e][dl]);
+    }
+    if (d < n) {
+      T* go = Gt + (int64_t)d * ldB + m0 + bq;
+      T* so = St + (int64_t)d * ldB + m0 + bq;
+      if constexpr (sizeof(T) == 2) {
+        *(uint4*)go = *(const uint4*)gv;
+        *(uint4*)(go + 8) = *(const uint4*)(gv + 8);
+        *(uint4*)so = *(const uint4*)svv;
+        *(uint4*)(so + 8) = *(const uint4*)(svv + 8);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          *(uint4*)(go + 4 * v) = *(const uint4*)(gv + 4 * v);
+          *(uint4*)(so + 4 * v) = *(const uint4*)(svv + 4 * v);
+        }
+      }
+    }
+    // the 4 threads of a site are adjacent lanes: fixed-order butterfly
+    colsum += __shfl_xor(colsum, 1);
+    colsum += __shfl_xor(colsum, 2);
+    if ((t & 3) == 0 && d < ldn) db2_part[(int64_t)blockIdx.y * ldn + d] = colsum;
+  }
+}
+
 // ---------------------------------------------------------------- reductions
 __global__ void sum_rows_kernel(const float* __restrict__ part, int nparts, int64_t stride, int64_t len,
                                 float* __restrict__ out) {
@@ -721,6 +814,48 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
   if ((e = hipGetLastError()) != hipSuccess) return e;
   sum_rows_kernel<<<(unsigned)((m.h + 255) / 256), 256, 0, st>>>(db1_part, g.mt_h, g.ldh, m.h, db1);
   return hipGetLastError();
+}
+
+// Backward from the incremental sampler's byproducts: Rt (relu(A), batch-contiguous, in
+// the workspace's Rt slot) and Zs (s_d z_d): the two forward products are not recomputed.
+template <typename T>
+static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
+                                     const float* Zs, float* dP, float* db1, float* db2, void* ws,
+                                     hipStream_t st) {
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
+  uint8_t* w = (uint8_t*)ws;
+  T* Rt = (T*)(w + L.Rt);
+  T* G = (T*)(w + L.G);
+  T* Gt = (T*)(w + L.Gt);
+  T* St = (T*)(w + L.St);
+  T* Dt = (T*)(w + L.Dt);
+  float* db2_part = (float*)(w + L.db2_part);
+  float* db1_part = (float*)(w + L.db1_part);
+  hipError_t e;
+  grad_out_kernel<T><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(Zs, S, g.ldn, coef, m.n, B, G, Gt, St, g.ldB, db2_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_weight_kernel<T, false><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(Gt, Rt, g.ldB, m.c, m.n, m.h, dP);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_weight_kernel<T, true><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(St, Dt, g.ldB, m.c, m.n, m.h, dP);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  sum_rows_kernel<<<(unsigned)((m.n + 255) / 256), 256, 0, st>>>(db2_part, g.mt_o, g.ldn, m.n, db2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  sum_rows_kernel<<<(unsigned)((m.h + 255) / 256), 256, 0, st>>>(db1_part, g.mt_h, g.ldh, m.h, db1);
+  return hipGetLastError();
+}
+
+void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws) {
+  return (uint8_t*)ws + layout(m.n, m.h, B, m.wdtype, 1).Rt;
+}
+
+hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
+                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return backward_sampled_t<bf16_t>(m, S, B, coef, Zs, dP, db1, db2, ws, st);
+  return backward_sampled_t<float>(m, S, B, coef, Zs, dP, db1, db2, ws, st);
 }
 
 template <typename T>

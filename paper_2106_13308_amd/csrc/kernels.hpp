@@ -29,8 +29,10 @@ bool sample_blocked_supported(int n, int h);
 hipError_t launch_sample_blocked(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                  uint32_t tag, int8_t* S, float* logp, hipStream_t st);
 bool sample_pipe_supported(int n, int h);
+// Zs (nullable): B x ld(n) floats s_d z_d; Rt (nullable): h x ld(B) relu(A) in the weight dtype
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
-                              uint32_t tag, int8_t* S, float* logp, hipStream_t st);
+                              uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs = nullptr,
+                              void* Rt = nullptr);
 hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st);
 hipError_t launch_uniforms(int n, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
                            float* u, hipStream_t st);
@@ -44,6 +46,11 @@ hipError_t launch_logprob(const vqmc_made& m, const int8_t* S, int64_t B, float*
 hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
                            float* dP, float* db1, float* db2, void* ws, hipStream_t st,
                            hipEvent_t coef_ready = nullptr);
+// backward from the incremental sampler's Rt (written into the slot backward_rt_slot gives)
+// and Zs (s_d z_d, B x ld(n)); ws as for launch_backward
+void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws);
+hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
+                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, hipStream_t st);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,

@@ -10,27 +10,30 @@
 // its last input) inside block floor(m(k) / 64); with f_b = c[min(64b + 63, n - 1)] the
 // units completing in block b are [f_{b-1}, f_b) (f_{-1} = 0).  Only those units make the
 // block serial; everything else is a product:
-//   logits   z of block b+1 = b2 + relu(A[:, :f_b]) P[block b+1, :f_b]^T        (MFMA)
-//   push     A[:, k] += S_block P[block, k] for the units completing after the block
-//                                                                                (MFMA)
-//   serial   for each unit u in [f_{b-1}, f_b) in order:
-//              a_u = A_u + sum_{sites j of the block feeding u} s_j P[j][u]
-//              z_j += P[j][u] relu(a_u) for the sites j of the block that use u
+//   logits   z of block b+1 over the units complete before block b:
+//            b2 + relu(A[:, :f_{b-1}]) P[block b+1, :f_{b-1}]^T                  (MFMA)
+//   push     A[:, k] += S_{block b-1} P[block b-1, k] for the units k >= f_b      (MFMA)
+//   sweep    for each unit u in [f_{b-1}, f_b) in order:
+//              a_u = A_u + sum_{j in block b-1} s_j P[j][u]
+//                        + sum_{sites j of block b feeding u} s_j P[j][u]
+//              z_j += P[j][u] relu(a_u) for the sites j of block b that use u, and for
+//                     every site j of block b+1
 //            and s_j = +1 iff z_j > logit(u_j) once every unit site j uses has been added.
-// The serial sweep needs no per-site bookkeeping: the W1 half of a unit's column (sites
+// The sweep needs no per-site bookkeeping: the W1 half of a unit's column (sites
 // feeding it) is always decided when the unit is reached, and the W2 half (sites using it)
 // never is, so with the two halves stored apart (the band, see vqmc_band) the sweep reads
 // the sign of every site's current logit margin and multiplies by the W1 half, and adds the
 // W2 half to every logit; undecided sites meet zero W1 weights and decided ones zero W2
-// weights.
+// weights.  The band also holds each unit's weights to the block before (all feeding it)
+// and the block after (all using it), so the sweep itself finishes both products that
+// depend on the block it has just drawn, and one barrier per block suffices.
 //
-// Workgroup = 8 samples, 4 waves.  Wave 0 runs the serial sweep of block b with lane
-// (sample s, group g) holding sites 8g..8g+7 of sample s in registers; a unit's dot product
-// is an 8-lane DPP reduction.  Waves 1-3 meanwhile push block b-1's spins into the units
-// completing after block b, compute the part of block b+1's logits that only needs units
-// complete before block b, draw block b+1's uniforms, and write out block b-1's spins and
-// log-probabilities.  After the sweep all four waves push block b's spins into the units
-// of block b+1's sweep and add block b's completed units to block b+1's logits.
+// Workgroup = 8 samples, 4 waves.  Wave 0 sweeps block b with lane (sample s, group g)
+// holding sites 8g..8g+7 of sample s (and of the next block) in registers; a unit's dot
+// product is an 8-lane DPP reduction.  Waves 1-3 meanwhile push block b-1's spins into the
+// units completing after block b, compute the part of block b+1's logits that only needs
+// units complete before block b, draw block b+1's uniforms, and write out block b-1's
+// spins and log-probabilities.
 //
 // Arithmetic: FP32 state and logits.  BF16 weights: the products run on
 // v_mfma_f32_16x16x32_bf16, exact for the +-1 spins of the push and with every FP32
@@ -45,7 +48,7 @@ namespace vqmc {
 constexpr int SP_MS = 8;           // samples per workgroup
 constexpr int SP_T = 64;           // sites per block
 constexpr int SP_REC = VQMC_BAND_REC;
-constexpr int SP_PDS = 6;          // serial band records in flight
+constexpr int SP_PDS = 4;          // band records in flight in the sweep
 constexpr float SP_SCALE = 0x1p100f;
 
 __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; }
@@ -53,7 +56,7 @@ __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; 
 __host__ inline size_t sp_smem_bytes(int h) {
   const size_t st = (size_t)SP_MS * sp_lda(h) * 4;
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
-  return st + 2 * blk /*zp*/ + 2 * blk /*th*/ + 3 * blk /*red*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/;
+  return st + 6 * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/;
 }
 
 // exact 3-term BF16 split of 8 floats
@@ -79,16 +82,23 @@ struct SpFrag;
 template <>
 struct SpFrag<bf16_t> {
   static constexpr int KC = 32;
-  typedef uint4 Z1;
   struct Z { uint4 a[4]; };
   struct U { uint4 a[2]; };
 };
 template <>
 struct SpFrag<float> {
   static constexpr int KC = 4;
-  typedef float Z1;
   struct Z { float a[4]; };
   struct U { uint4 a[2][2]; };
+};
+
+// one band record of the sweep lane's 8 sites
+struct SpRec {
+  float4 w1a, w1b;  // 2 W1, this block
+  float4 w2a, w2b;  // W2, this block
+  float4 p1a, p1b;  // 2 W1, previous block
+  float4 n2a, n2b;  // W2, next block
+  float ns;         // minus the sum of the W1 halves
 };
 
 template <typename WT>
@@ -96,25 +106,26 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
     const WT* __restrict__ P, const WT* __restrict__ Pt, const float* __restrict__ band, int64_t ldh,
     int64_t ldn, const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
     int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
-    int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp) {
+    int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp, float* __restrict__ Zs, WT* __restrict__ Rt,
+    int64_t ldB) {
   using F = SpFrag<WT>;
   constexpr int KC = F::KC;
   constexpr int BLK = SP_MS * SP_T;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
-  float* zp = st + SP_MS * LDA;    // [2][8][64] logits of a block before its sweep
-  float* th = zp + 2 * BLK;        // [2][8][64] -logit(u) * 2^100
-  float* red = th + 2 * BLK;       // [3][64][8] helpers' partial logits of the next block
-  float* zs = red + 3 * BLK;       // [2][8][64] s_d z_d of a swept block
+  float* red = st + SP_MS * LDA;   // [2][3][8][64] helpers' partial logits of a block (+ b2)
+  float* th = red + 6 * BLK;       // [2][8][64] -logit(u) * 2^100
+  float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, g4 = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
-  auto fend = [&](int b) { return c[min(SP_T * b + SP_T - 1, n - 1)]; };
+  auto fend = [&](int b) { return (b < 0) ? 0 : c[min(SP_T * b + SP_T - 1, n - 1)]; };
 
-  // ---- fragment loaders
+  // ---- fragment loaders (indices clamped to valid memory, so that every path issues
+  // the same loads and each use waits only for its own fragment)
   auto fetch_z = [&](typename F::Z& f, int dblk, int k0) {
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
@@ -126,50 +137,6 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         f.a[tt] = ((const float*)P)[(int64_t)d * ldh + k0 + g4];
       }
     }
-  };
-  // activation operand of a K chunk at k0: relu(A[l16][k]) for k in [lo, hi), else 0
-  //   BF16: units k0+8g..k0+8g+7 split into three BF16 terms     FP32: unit k0+g
-  struct Act {
-    bf16x8_t xh, xm, xl;
-    float r;
-  };
-  auto act = [&](int k0, int lo, int hi) {
-    Act x;
-    if constexpr (sizeof(WT) == 2) {
-      float r[8];
-      const float* srow = st + l16 * LDA + k0 + 8 * g4;
-      if (l16 < SP_MS) {
-        const float4 ra = *(const float4*)srow, rb = *(const float4*)(srow + 4);
-        r[0] = ra.x; r[1] = ra.y; r[2] = ra.z; r[3] = ra.w;
-        r[4] = rb.x; r[5] = rb.y; r[6] = rb.z; r[7] = rb.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) r[e] = 0.f;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + 8 * g4 + e;
-        r[e] = (k >= lo && k < hi) ? fmaxf(r[e], 0.f) : 0.f;
-      }
-      sp_split3(r, x.xh, x.xm, x.xl);
-      x.r = 0.f;
-    } else {
-      const int k = k0 + g4;
-      x.r = (l16 < SP_MS && k >= lo && k < hi) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
-    }
-    return x;
-  };
-  // one site tile: acc += P[tile rows, chunk] x activation
-  auto mfma_z = [&](const Act& x, auto a, floatx4_t acc) {
-    if constexpr (sizeof(WT) == 2) {
-      const bf16x8_t w = __builtin_bit_cast(bf16x8_t, a);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x.xh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x.xm, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x.xl, acc, 0, 0, 0);
-    } else {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x.r, acc, 0, 0, 0);
-    }
-    return acc;
   };
   auto fetch_u = [&](typename F::U& f, int dblk, int k0) {
     // rows past h load row h-1: those state rows are never written back
@@ -251,37 +218,44 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
     *(float4*)(dst + s * SP_T + 4 * q4) = make_float4(v[0], v[1], v[2], v[3]);
   };
 
-  // ---- prologue: state = b1, block 0 logits = b2, block 0 thresholds
+  // ---- prologue: state = b1, block 0's logits = b2, block 0's thresholds
   for (int i = t; i < SP_MS * LDA; i += 256) {
     const int k = i % LDA;
     st[i] = (k < h) ? b1[k] : 0.f;
   }
-  for (int i = t; i < BLK; i += 256) {
+  for (int i = t; i < 3 * BLK; i += 256) {
     const int j = i % SP_T;
-    zp[i] = (j < n) ? b2[j] : 0.f;
+    red[i] = (i < BLK && j < n) ? b2[j] : 0.f;
   }
   if (t < 128) thresholds(0, th, t);
 
-  // serial lane roles (wave 0): sample ss, sites 8sg..8sg+7 of the block
+  // sweep lane roles (wave 0): sample ss, sites 8sg..8sg+7 of the block
   const int ss = lane >> 3, sg = lane & 7;
-  float4 rw1a[SP_PDS], rw1b[SP_PDS], rw2a[SP_PDS], rw2b[SP_PDS];
-  float rns[SP_PDS];
-  auto fetch_rec = [&](int p, int u) {
-    const float* r = band + (int64_t)u * SP_REC;
-    rw1a[p] = *(const float4*)(r + 8 * sg);
-    rw1b[p] = *(const float4*)(r + 8 * sg + 4);
-    rw2a[p] = *(const float4*)(r + 64 + 8 * sg);
-    rw2b[p] = *(const float4*)(r + 64 + 8 * sg + 4);
-    rns[p] = r[128 + (lane & 3)];  // the four copies keep this a per-lane (vector) load
+  SpRec ring[SP_PDS];
+  auto fetch_rec = [&](SpRec& r, int u) {
+    const float* q = band + (int64_t)u * SP_REC + 8 * sg;
+    r.w1a = *(const float4*)q;
+    r.w1b = *(const float4*)(q + 4);
+    r.w2a = *(const float4*)(q + 64);
+    r.w2b = *(const float4*)(q + 68);
+    r.p1a = *(const float4*)(q + 128);
+    r.p1b = *(const float4*)(q + 132);
+    r.n2a = *(const float4*)(q + 192);
+    r.n2b = *(const float4*)(q + 196);
+    // the four copies keep this a per-lane (vector) load
+    r.ns = band[(int64_t)u * SP_REC + 256 + (lane & 3)];
   };
+  float zn[8], cp[8];  // next block's logits from this block's units; previous block's draws
+#pragma unroll
+  for (int e = 0; e < 8; ++e) zn[e] = cp[e] = 0.f;
   if (wv == 0) {
 #pragma unroll
-    for (int p = 0; p < SP_PDS; ++p) fetch_rec(p, min(p, h - 1));
+    for (int p = 0; p < SP_PDS; ++p) fetch_rec(ring[p], min(p, h - 1));
   }
   float lp_part = 0.f;  // wave 1: log pi partial of sample lane>>3, sites 8(lane&7)..
   __syncthreads();
 
-  // spins out + log pi partial of a swept block (wave 1)
+  // spins, s*z and log pi partial of a swept block (wave 1)
   auto emit = [&](int blk, int buf) {
     const int s = lane >> 3, q = lane & 7;
     const int dblk = SP_T * blk;
@@ -291,27 +265,39 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       if (dblk + 8 * q + e < n) lp_part += log_sigmoid(zrow[e]);
+    if (Zs && b0 + s < B) {
+      float* zo = Zs + (b0 + s) * lds + dblk + 8 * q;
+      *(float4*)zo = *(const float4*)zrow;
+      *(float4*)(zo + 4) = *(const float4*)(zrow + 4);
+    }
   };
 
-  int fprev = 0, fcur = fend(0);
   for (int b = 0; b < nb; ++b) {
     const int d0 = SP_T * b, Tb = min(SP_T, n - d0);
     const bool has_next = b + 1 < nb;
-    const int fnext = has_next ? fend(b + 1) : h;
+    const int fprev = fend(b - 1), fcur = fend(b);
     const int cur = b & 1, nxt = cur ^ 1;
 
     if (wv == 0) {
-      // ================= serial sweep of block b over units [fprev, fcur)
+      // ================= sweep of block b over units [fprev, fcur)
       float zr[8], tz[8];
       {
-        const float* zrow = zp + cur * BLK + ss * SP_T + 8 * sg;
+        const float* r0 = red + cur * 3 * BLK + ss * SP_T + 8 * sg;
         const float* trow = th + cur * BLK + ss * SP_T + 8 * sg;
-        const float4 z0 = *(const float4*)zrow, z1 = *(const float4*)(zrow + 4);
+        const float4 x0 = *(const float4*)r0, x1 = *(const float4*)(r0 + 4);
+        const float4 y0 = *(const float4*)(r0 + BLK), y1 = *(const float4*)(r0 + BLK + 4);
+        const float4 v0 = *(const float4*)(r0 + 2 * BLK), v1 = *(const float4*)(r0 + 2 * BLK + 4);
         const float4 t0 = *(const float4*)trow, t1 = *(const float4*)(trow + 4);
-        zr[0] = z0.x; zr[1] = z0.y; zr[2] = z0.z; zr[3] = z0.w;
-        zr[4] = z1.x; zr[5] = z1.y; zr[6] = z1.z; zr[7] = z1.w;
-        tz[0] = t0.x; tz[1] = t0.y; tz[2] = t0.z; tz[3] = t0.w;
-        tz[4] = t1.x; tz[5] = t1.y; tz[6] = t1.z; tz[7] = t1.w;
+        const float px[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const float py[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+        const float pv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        const float pt[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          zr[e] = ((px[e] + py[e]) + pv[e]) + zn[e];
+          zn[e] = 0.f;
+          tz[e] = pt[e];
+        }
       }
       float* arow = st + ss * LDA;
       float a0n = arow[fprev];
@@ -320,26 +306,32 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         for (int p = 0; p < SP_PDS; ++p) {
           const int u = ub + p;
           if (u >= fprev && u < fcur) {
+            const SpRec& r = ring[p];
             const float a0 = a0n;
             a0n = arow[u + 1];
-            const float w1[8] = {rw1a[p].x, rw1a[p].y, rw1a[p].z, rw1a[p].w,
-                                 rw1b[p].x, rw1b[p].y, rw1b[p].z, rw1b[p].w};
-            const float w2[8] = {rw2a[p].x, rw2a[p].y, rw2a[p].z, rw2a[p].w,
-                                 rw2b[p].x, rw2b[p].y, rw2b[p].z, rw2b[p].w};
-            // c_e = 1 if site e is (or would be) drawn +1 now, else 0; w1 holds 2 W1
-            float acc = 0.f;
+            const float w1[8] = {r.w1a.x, r.w1a.y, r.w1a.z, r.w1a.w, r.w1b.x, r.w1b.y, r.w1b.z, r.w1b.w};
+            const float w2[8] = {r.w2a.x, r.w2a.y, r.w2a.z, r.w2a.w, r.w2b.x, r.w2b.y, r.w2b.z, r.w2b.w};
+            const float p1[8] = {r.p1a.x, r.p1a.y, r.p1a.z, r.p1a.w, r.p1b.x, r.p1b.y, r.p1b.z, r.p1b.w};
+            const float n2[8] = {r.n2a.x, r.n2a.y, r.n2a.z, r.n2a.w, r.n2b.x, r.n2b.y, r.n2b.z, r.n2b.w};
+            // c_e = 1 if site e is (or would be) drawn +1 now, else 0; w1 and p1 hold 2 W1
+            float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               const float ce = __builtin_amdgcn_fmed3f(fmaf(zr[e], SP_SCALE, tz[e]), 0.f, 1.f);
-              acc = fmaf(ce, w1[e], acc);
+              acc0 = fmaf(ce, w1[e], acc0);
+              acc1 = fmaf(cp[e], p1[e], acc1);
             }
+            float acc = acc0 + acc1;
             acc += VQMC_DPP(acc, 0xB1);   // quad_perm [1,0,3,2]
             acc += VQMC_DPP(acc, 0x4E);   // quad_perm [2,3,0,1]
             acc += VQMC_DPP(acc, 0x141);  // row_half_mirror: 8-lane total in every lane
-            const float a = (acc + rns[p]) + a0;
-            const float r = fmaxf(a, 0.f);
+            const float a = (acc + r.ns) + a0;
+            const float rl = fmaxf(a, 0.f);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) zr[e] = fmaf(w2[e], r, zr[e]);
+            for (int e = 0; e < 8; ++e) {
+              zr[e] = fmaf(w2[e], rl, zr[e]);
+              zn[e] = fmaf(n2[e], rl, zn[e]);
+            }
             arow[u] = a;
           }
           // Every step reloads its slot, so the number of loads in flight is the same on
@@ -349,7 +341,7 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
           // they hold.  The barrier keeps the loads after the slot's last use, so they go
           // straight into the slot's registers.
           __builtin_amdgcn_sched_barrier(0);
-          fetch_rec(p, min(u < fcur ? u + SP_PDS : u, h - 1));
+          fetch_rec(ring[p], min(u < fcur ? u + SP_PDS : u, h - 1));
         }
       }
       // decisions, spins and s*z of the block
@@ -364,6 +356,7 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         if (e < 4) lo |= byte << (8 * e);
         else hi |= byte << (8 * (e - 4));
         zsv[e] = up ? zr[e] : -zr[e];
+        cp[e] = (j < Tb && up) ? 1.f : 0.f;
       }
       *(uint2*)(sb + cur * BLK + ss * SP_T + 8 * sg) = make_uint2(lo, hi);
       float* zsr = zs + cur * BLK + ss * SP_T + 8 * sg;
@@ -373,8 +366,6 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
       // ================= helpers (waves 1-3)
       const int hw = wv - 1;
       // push of block b-1's spins into units [fcur, h): 16-unit tiles hw, hw+3, ...
-      // Ring loads are issued on every path (indices clamped to valid memory) so that each
-      // use waits only for its own fragment.
       constexpr int PDU = 4;
       typename F::U fu[PDU];
       const int ubase = fcur & ~15;
@@ -384,7 +375,8 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
       auto tile_u = [&](int it) { return ubase + 16 * (hw + 3 * min(it, max(cntu - 1, 0))); };
 #pragma unroll
       for (int p = 0; p < PDU; ++p) fetch_u(fu[p], dprev, tile_u(p));
-      // early logits of block b+1 over units [0, fprev): K chunks hw, hw+3, ...
+      // block b+1's logits over the units complete before block b, [0, fprev): K chunks
+      // hw, hw+3, ... (the units of block b are added by the sweep)
       constexpr int PDZ = (sizeof(WT) == 2) ? 4 : 8;
       typename F::Z fz[PDZ];
       const int nzc = has_next ? (fprev + KC - 1) / KC : 0;
@@ -414,17 +406,51 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         }
       }
       if (has_next) {
+        const int d0n = d0 + SP_T, Tbn = min(SP_T, n - d0n);
         floatx4_t acc[4];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) acc[tt] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+        for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int j = 16 * tt + 4 * g4 + e;
+            acc[tt][e] = (hw == 0 && j < Tbn) ? b2[d0n + j] : 0.f;
+          }
+        }
         for (int base = 0; base < cntz; base += PDZ) {
 #pragma unroll
           for (int p = 0; p < PDZ; ++p) {
             const int it = base + p;
             if (it < cntz) {
-              const Act x = act(KC * (hw + 3 * it), 0, fprev);
+              const int k0 = KC * (hw + 3 * it);
+              if constexpr (sizeof(WT) == 2) {
+                float rr[8];
+                const float* srow = st + l16 * LDA + k0 + 8 * g4;
+                if (l16 < SP_MS) {
+                  const float4 ra = *(const float4*)srow, rb = *(const float4*)(srow + 4);
+                  rr[0] = ra.x; rr[1] = ra.y; rr[2] = ra.z; rr[3] = ra.w;
+                  rr[4] = rb.x; rr[5] = rb.y; rr[6] = rb.z; rr[7] = rb.w;
+                } else {
 #pragma unroll
-              for (int tt = 0; tt < 4; ++tt) acc[tt] = mfma_z(x, fz[p].a[tt], acc[tt]);
+                  for (int e = 0; e < 8; ++e) rr[e] = 0.f;
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rr[e] = (k0 + 8 * g4 + e < fprev) ? fmaxf(rr[e], 0.f) : 0.f;
+                bf16x8_t xh, xm, xl;
+                sp_split3(rr, xh, xm, xl);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                  const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
+                }
+              } else {
+                const int k = k0 + g4;
+                const float rr = (l16 < SP_MS && k < fprev) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fz[p].a[tt], rr, acc[tt], 0, 0, 0);
+              }
             }
             __builtin_amdgcn_sched_barrier(0);
             fetch_z(fz[p], d0 + SP_T, chunk_z(it + PDZ));
@@ -432,68 +458,14 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         }
         // C layout: lane holds rows (sites) 16tt + 4g4 + e, column (sample) l16
         if (l16 < SP_MS) {
+          float* dst = red + nxt * 3 * BLK + hw * BLK + l16 * SP_T + 4 * g4;
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) red[(hw * SP_T + 16 * tt + 4 * g4 + e) * SP_MS + l16] = acc[tt][e];
+            *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
         }
       }
     }
     __syncthreads();
-
-    // ================= tail (all waves): block b+1's sweep needs block b's spins in its
-    // units and block b's completed units in its logits
-    if (has_next) {
-      const int d0n = d0 + SP_T, Tbn = min(SP_T, n - d0n);
-      // push block b's spins into units [fcur, fnext): tiles wv, wv+4, ...
-      {
-        const int ub0 = fcur & ~15;
-        bf16x8_t sv[2];
-        bool have_sv = false;
-        for (int k0 = ub0 + 16 * wv; k0 < fnext; k0 += 64) {
-          if (!have_sv) {
-            spin_operand(sb + cur * BLK, sv);
-            have_sv = true;
-          }
-          typename F::U f;
-          fetch_u(f, d0, k0);
-          use_u(f, k0, fcur, fnext, sv);
-        }
-      }
-      // logits of block b+1, site tile wv: + units [fprev, fcur) + helpers' partials + b2
-      {
-        floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = fprev & ~(KC - 1); k0 < fcur; k0 += KC) {
-          const int d = min(d0n + 16 * wv + l16, n - 1);  // rows past n: never read back
-          typename F::Z1 a;
-          if constexpr (sizeof(WT) == 2) {
-            a = *(const uint4*)((const bf16_t*)P + (int64_t)d * ldh + k0 + 8 * g4);
-          } else {
-            a = ((const float*)P)[(int64_t)d * ldh + k0 + g4];
-          }
-          const Act x = act(k0, fprev, fcur);
-          acc = mfma_z(x, a, acc);
-        }
-        if (l16 < SP_MS) {
-          float* zrow = zp + nxt * BLK + l16 * SP_T;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int j = 16 * wv + 4 * g4 + e;
-            float v = 0.f;
-            if (j < Tbn) {
-              const float r0 = red[(0 * SP_T + j) * SP_MS + l16];
-              const float r1 = red[(1 * SP_T + j) * SP_MS + l16];
-              const float r2 = red[(2 * SP_T + j) * SP_MS + l16];
-              v = b2[d0n + j] + ((r0 + r1) + r2) + acc[e];
-            }
-            zrow[j] = v;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    fprev = fcur;
-    fcur = fnext;
   }
 
   // last block's spins and log pi, then the 8-lane log pi sum of each sample
@@ -506,9 +478,31 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
     const int s = lane >> 3;
     if ((lane & 7) == 0 && b0 + s < B && logp) logp[b0 + s] = v;
   }
+  // every unit is complete: the hidden activations relu(A) of the forward pass,
+  // batch-contiguous (Rt[k][b], zero for b >= B up to ldB)
+  if (Rt) {
+    const int64_t bend = (blockIdx.x + 1 == gridDim.x) ? ldB : b0 + SP_MS;
+    for (int k = t; k < h; k += 256) {
+      WT v[SP_MS];
+#pragma unroll
+      for (int s = 0; s < SP_MS; ++s) {
+        const float a = (b0 + s < B) ? fmaxf(st[s * LDA + k], 0.f) : 0.f;
+        if constexpr (sizeof(WT) == 2) v[s] = f32_to_bf16(a);
+        else v[s] = a;
+      }
+      WT* out = Rt + (int64_t)k * ldB + b0;
+      if constexpr (sizeof(WT) == 2) {
+        *(uint4*)out = *(const uint4*)v;
+      } else {
+        *(uint4*)out = *(const uint4*)v;
+        *(uint4*)(out + 4) = *(const uint4*)(v + 4);
+      }
+      for (int64_t bb = b0 + SP_MS; bb < bend; ++bb) Rt[(int64_t)k * ldB + bb] = (WT)0;
+    }
+  }
 }
 
-// Band records (see vqmc_band): one wave per unit k.
+// Band records (see vqmc_band): one wave per unit k, lane j = site j of a block.
 template <typename WT>
 __global__ __launch_bounds__(256) void band_kernel(const WT* __restrict__ Pt, int64_t ldn, const int32_t* __restrict__ c,
                                                    int n, int h, float* __restrict__ band) {
@@ -521,21 +515,30 @@ __global__ __launch_bounds__(256) void band_kernel(const WT* __restrict__ Pt, in
     if (c[mid] > k) hi = mid;
     else lo = mid + 1;
   }
-  const int d = (lo / SP_T) * SP_T + j;
+  const int q = lo / SP_T;
+  float* r = band + (int64_t)k * SP_REC;
+  // this block: W1 (sites feeding k) doubled, W2 (sites using k)
+  const int d = q * SP_T + j;
   float w = 0.f;
   bool feeds = false;
   if (d < n) {
     w = to_f32(Pt[(int64_t)k * ldn + d]);
     feeds = k >= c[d];
   }
-  float* r = band + (int64_t)k * SP_REC;
   r[j] = feeds ? 2.f * w : 0.f;
   r[64 + j] = feeds ? 0.f : w;
-  // minus the W1 half's sum (fixed butterfly order, identical in every lane)
-  float s = feeds ? w : 0.f;
+  // previous block: every site feeds k
+  const int dp = (q - 1) * SP_T + j;
+  const float wp = (q > 0) ? to_f32(Pt[(int64_t)k * ldn + dp]) : 0.f;
+  r[128 + j] = 2.f * wp;
+  // next block: every site uses k
+  const int dn = (q + 1) * SP_T + j;
+  r[192 + j] = (dn < n) ? to_f32(Pt[(int64_t)k * ldn + dn]) : 0.f;
+  // minus the W1 halves' sum (fixed butterfly order, identical in every lane)
+  float s = (feeds ? w : 0.f) + wp;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o);
-  if (j < 4) r[128 + j] = -s;
+  if (j < 4) r[256 + j] = -s;
 }
 
 size_t band_floats(int h) { return (size_t)h * SP_REC; }
@@ -554,7 +557,8 @@ bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(h) <= 160 * 1024
 
 template <typename WT>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
-                                uint32_t tag, int8_t* S, float* logp, hipStream_t st) {
+                                uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, int64_t ldB,
+                                hipStream_t st) {
   const size_t smem = sp_smem_bytes(m.h);
   hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -562,14 +566,17 @@ static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, ui
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
   sample_pipe_kernel<WT><<<grid, 256, smem, st>>>((const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad),
                                                   round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h, sp_lda(m.h), B,
-                                                  seed, step, offset, tag, S, round_up(m.n, kPad), logp);
+                                                  seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs,
+                                                  (WT*)Rt, ldB);
   return hipGetLastError();
 }
 
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
-                              uint32_t tag, int8_t* S, float* logp, hipStream_t st) {
-  if (m.wdtype == VQMC_BF16) return launch_pipe_t<bf16_t>(m, B, seed, step, offset, tag, S, logp, st);
-  return launch_pipe_t<float>(m, B, seed, step, offset, tag, S, logp, st);
+                              uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs, void* Rt) {
+  const int64_t ldB = round_up(B, kPad);
+  if (m.wdtype == VQMC_BF16)
+    return launch_pipe_t<bf16_t>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
+  return launch_pipe_t<float>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
 }
 
 }  // namespace vqmc

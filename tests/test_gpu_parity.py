@@ -325,10 +325,16 @@ def test_sample_pipe_equals_blocked(wd):
     Sb, lpb = B_.sample(Mb, 96, 8, 5)
     q = oracle_params(p, wdtype)
     U = oph.uniforms(8, 5, np.arange(96), 700)
-    pref = omade.conditionals(q, spins_np(Sb, 700))
-    clean = (np.abs(U - pref) > 1e-4).all(axis=1)
-    assert clean.mean() > 0.9
-    assert np.array_equal(spins_np(Sp, 700)[clean], spins_np(Sb, 700)[clean])
+    Sb_np, Sp_np = spins_np(Sb, 700), spins_np(Sp, 700)
+    pref = omade.conditionals(q, Sb_np)
+    amb = np.abs(U - pref) <= 1e-4
+    # up to each sample's first near-boundary draw the two kernels see the same prefix
+    first = np.where(amb.any(axis=1), amb.argmax(axis=1), 700)
+    for b in range(96):
+        assert np.array_equal(Sp_np[b, :first[b]], Sb_np[b, :first[b]]), b
+    clean = first == 700
+    assert clean.mean() > 0.5
+    assert np.array_equal(Sp_np[clean], Sb_np[clean])
     assert np.allclose(lpp.cpu().numpy()[clean], lpb.cpu().numpy()[clean], rtol=1e-5, atol=1e-4)
 
 
@@ -344,17 +350,23 @@ def test_band_layout():
     W1 = M1 * np.asarray(q["W1"], np.float64)
     W2 = M2 * np.asarray(q["W2"], np.float64)
     deg = np.asarray(p["degrees"])
+
+    def part(W, k, d0, rows):
+        sites = np.arange(d0, d0 + 64)
+        ok = (sites >= 0) & (sites < n)
+        out = np.zeros(64)
+        out[ok] = W[k, sites[ok]] if rows else W[sites[ok], k]
+        return out
+
     for k in range(h):
         d0 = (deg[k] // 64) * 64
-        sites = np.arange(d0, d0 + 64)
-        ok = sites < n
-        w1 = np.zeros(64)
-        w2 = np.zeros(64)
-        w1[ok] = W1[k, sites[ok]]
-        w2[ok] = W2[sites[ok], k]
+        w1, w2 = part(W1, k, d0, True), part(W2, k, d0, False)
+        p1, n2 = part(W1, k, d0 - 64, True), part(W2, k, d0 + 64, False)
         assert np.array_equal(band[k, :64], 2 * w1), k
         assert np.array_equal(band[k, 64:128], w2), k
-        assert np.allclose(band[k, 128:], -w1.sum(), rtol=1e-6, atol=1e-6), k
+        assert np.array_equal(band[k, 128:192], 2 * p1), k
+        assert np.array_equal(band[k, 192:256], n2), k
+        assert np.allclose(band[k, 256:], -(w1.sum() + p1.sum()), rtol=1e-6, atol=1e-6), k
 
 
 def test_sample_deterministic():
@@ -439,3 +451,29 @@ def test_step_matches_oracle(algo):
     for k, got in (("W1", dW1), ("W2", dW2), ("b1", bufs.db1), ("b2", bufs.db2)):
         got = got.cpu().numpy()
         assert np.abs(got - g[k]).max() <= 2e-5 * np.abs(g[k]).max() + 1e-12, k
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(60, 90, 200), (700, 350, 130), (10000, 1000, 2048)])
+def test_step_fused_equals_recompute(n, h, B, wd):
+    """vqmc_step with the pipelined sampler takes relu(A) and the logits from the sampling;
+    its gradient must equal the recomputing backward on the same spins and coefficients."""
+    _banner(f"fused step n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, edges = instance(n, h, seed=17, graph="regular", deg=4, scale=2.0)
+    w = inputs.integer_weights(len(edges), 1, 5, 3)
+    M = build_made(p, wdtype)
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    bufs = B_.StepBuffers.allocate(M, H, B)
+    B_.step(M, H, B, 5, 2, bufs)
+    dP, db1, db2 = B_.logprob_backward(M, bufs.S, bufs.coef)
+    lp_ref = B_.logprob(M, bufs.S)
+    torch.cuda.synchronize()
+    tol = 1e-4 if wd == "f32" else 2e-2
+    for k, got, ref in (("dP", bufs.dP, dP), ("db1", bufs.db1, db1), ("db2", bufs.db2, db2)):
+        got, ref = got.cpu().numpy(), ref.cpu().numpy()
+        err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
+        print(f"  {k}: max err / max |ref| = {err:.2e}")
+        assert err <= tol, k
+    lp, lr = bufs.logp.cpu().numpy(), lp_ref.cpu().numpy()
+    assert np.abs(lp - lr).max() <= 1e-4 * np.abs(lr).max()
