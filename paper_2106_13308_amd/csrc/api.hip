@@ -37,10 +37,14 @@ size_t step_energy_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
 }
 
 // Step workspace: [sampling / backward region][energy region][Zs: B x ld(n) floats, the
-// incremental sampler's s_d z_d, read by the backward]
+// incremental sampler's s_d z_d, read by the backward][masked copy of P^T, h x ld(n)]
 size_t step_zs_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
   return step_energy_offset(n, h, B, wdtype) +
          (size_t)round_up((int64_t)((n + 63) / 64) * B * (int64_t)sizeof(double), 256);
+}
+
+size_t step_pm_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  return step_zs_offset(n, h, B, wdtype) + (size_t)round_up(B * round_up(n, kPad) * (int64_t)sizeof(float), 256);
 }
 
 // One auxiliary stream (default priority) and two events per device, created on first
@@ -104,7 +108,7 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_LOGPROB: return logprob_ws_bytes(n, h, B, wdtype, false);
     case VQMC_WS_BACKWARD: return logprob_ws_bytes(n, h, B, wdtype, true);
     case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
-    case VQMC_WS_STEP: return step_zs_offset(n, h, B, wdtype) + (size_t)B * round_up(n, kPad) * sizeof(float);
+    case VQMC_WS_STEP: return step_pm_offset(n, h, B, wdtype) + mask_w2t_bytes(n, h);
     default: return 0;
   }
 }
@@ -279,7 +283,8 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
   if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
   if (fused) {
     if ((e = hipStreamWaitEvent(st, aux->stats_done, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
-    if ((e = launch_backward_sampled(*m, S, B, coef, Zs, dP, db1, db2, ws, st)) != hipSuccess)
+    void* Pm = (uint8_t*)ws + step_pm_offset(m->n, m->h, B, m->wdtype);
+    if ((e = launch_backward_sampled(*m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st)) != hipSuccess)
       return hip_status(e, "vqmc_step backward");
     return VQMC_OK;
   }

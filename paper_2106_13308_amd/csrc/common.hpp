@@ -58,8 +58,16 @@ __device__ inline float4 site_uniforms(uint64_t seed, uint64_t step, uint32_t ta
 }
 
 // ---------------------------------------------------------------- numerics
+// log(1 + x) for x >= 0 without the cancellation of log(1 + x) near 0: with u = 1 + x
+// rounded, log(u) - ((u - 1) - x) / u corrects for the rounding of u (Goldberg, "What
+// every computer scientist should know about floating-point arithmetic", Thm. 4); the
+// correction is below one ulp of u, so a hardware reciprocal is accurate enough.
+__device__ inline float log1p_pos(float x) {
+  const float u = 1.f + x;
+  return __logf(u) - ((u - 1.f) - x) * __builtin_amdgcn_rcpf(u);
+}
 // log sigma(t) = min(t, 0) - log1p(exp(-|t|)), stable for large |t|.
-__device__ inline float log_sigmoid(float t) { return fminf(t, 0.f) - log1pf(__expf(-fabsf(t))); }
+__device__ inline float log_sigmoid(float t) { return fminf(t, 0.f) - log1p_pos(__expf(-fabsf(t))); }
 // sigma(t) for any t without overflow.
 __device__ inline float sigmoid(float t) {
   const float e = __expf(-fabsf(t));

@@ -12,55 +12,106 @@
 namespace vqmc {
 
 // ---------------------------------------------------------------- sparse (CSR upper)
-// One workgroup handles MSE samples: their spins are staged in LDS (int8), each thread
-// walks whole CSR rows (edges i<j) and accumulates w_ij s_i s_j for every staged
-// sample.  Integer weights accumulate exactly in int64; float weights in double (the
-// products w * (+-1) are exact).  Fixed thread->row map and a fixed-shape tree make the
-// result deterministic.
-template <typename WT, typename AT>
+// One workgroup handles MSE samples: their spins are staged in LDS (int8, 16-byte global
+// loads issued together), and so is the row pointer (int32) when it fits.  Each thread walks
+// rows i = t, t + 256, ... four at a time: the edge loads of the four rows are issued
+// together, so one memory latency covers them (consecutive threads take consecutive rows,
+// so the loads coalesce).  Every edge adds w_ij s_i s_j for each staged sample.  Integer
+// weights accumulate exactly in int64; float weights in double (the products w * (+-1) are
+// exact).  A fixed thread -> row map and fixed-shape reductions make the result
+// deterministic.
+constexpr int EMSE = 8;
+template <typename WT, typename AT, bool RP_LDS>
 __global__ __launch_bounds__(256) void energy_csr_kernel(int n, int64_t lds, const int64_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ col,
                                                           const WT* __restrict__ w,
                                                           const int8_t* __restrict__ S, int64_t B,
-                                                          int mse, AT* __restrict__ E) {
-  extern __shared__ int8_t sh[];  // mse * n spins, then reduction scratch
-  const int t = threadIdx.x;
+                                                          int mse, int nst, AT* __restrict__ E) {
+  // mse rows of nst spins, then the row pointer (n + 1 int32, if staged), then scratch
+  extern __shared__ __attribute__((aligned(16))) int8_t sh[];
+  int32_t* rp = (int32_t*)(sh + mse * nst);
+  AT* red = (AT*)(sh + mse * nst + (RP_LDS ? round_up((int64_t)(n + 1) * 4, 16) : 0));
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t b0 = (int64_t)blockIdx.x * mse;
   const int nq = (int)min<int64_t>(mse, B - b0);
-  for (int q = 0; q < nq; ++q)
-    for (int i = t; i < n; i += 256) sh[q * n + i] = S[(b0 + q) * lds + i];
+  {
+    // nst = round_up(n, 16) <= lds: every 16-byte chunk lies inside the padded row
+    const int nch = nst / 16;
+    for (int c0 = t; c0 < nch; c0 += 256) {
+      uint4 v[EMSE];
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q)
+        v[q] = (q < nq) ? *(const uint4*)(S + (b0 + q) * lds + 16 * c0) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q)
+        if (q < mse) *(uint4*)(sh + q * nst + 16 * c0) = v[q];
+    }
+    if constexpr (RP_LDS)
+      for (int i = t; i <= n; i += 256) rp[i] = (int32_t)rowptr[i];
+  }
   __syncthreads();
-  AT acc[8];
+  auto rowp = [&](int i) -> int64_t {
+    if constexpr (RP_LDS) return rp[i];
+    else return rowptr[i];
+  };
+  AT acc[EMSE];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0;
-  for (int i = t; i < n; i += 256) {
-    const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
-    AT row[8];
+  for (int q = 0; q < EMSE; ++q) acc[q] = 0;
+  for (int i0 = t; i0 < n; i0 += 4 * 256) {
+    int64_t e0[4], e1[4];
+    int len = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) row[q] = 0;
-    for (int64_t e = e0; e < e1; ++e) {
-      const int j = col[e];
-      const AT we = (AT)w[e];
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 256 * r;
+      e0[r] = (i < n) ? rowp(i) : 0;
+      e1[r] = (i < n) ? rowp(i + 1) : 0;
+      len = max(len, (int)(e1[r] - e0[r]));
+    }
+    AT row[4][EMSE];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nq) row[q] += we * (AT)sh[q * n + j];
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q) row[r][q] = 0;
+    for (int k = 0; k < len; k += 2) {
+      int jj[4][2];
+      AT ww[4][2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int64_t e = e0[r] + k + u;
+          const bool ok = e < e1[r];
+          jj[r][u] = ok ? col[e] : 0;
+          ww[r][u] = ok ? (AT)w[e] : (AT)0;
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < EMSE; ++q)
+            if (q < mse) row[r][q] += (sh[q * nst + jj[r][u]] > 0) ? ww[r][u] : -ww[r][u];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < nq) acc[q] += row[q] * (AT)sh[q * n + i];
-  }
-  // block tree reduction, one sample at a time
-  AT* red = (AT*)(sh + ((mse * n + 15) / 16) * 16);
-  for (int q = 0; q < nq; ++q) {
-    red[t] = acc[q];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 256 * r;
+      if (i < n) {
+#pragma unroll
+        for (int q = 0; q < EMSE; ++q)
+          if (q < mse) acc[q] += (sh[q * nst + i] > 0) ? row[r][q] : -row[r][q];
+      }
     }
-    if (t == 0) E[b0 + q] = red[0];
-    __syncthreads();
   }
+  // per sample: fixed butterfly over the wave, then the four waves in order
+#pragma unroll
+  for (int q = 0; q < EMSE; ++q) {
+    AT v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && q < mse) red[q * 4 + wv] = v;
+  }
+  __syncthreads();
+  if (t < nq) E[b0 + t] = (red[t * 4] + red[t * 4 + 1]) + (red[t * 4 + 2] + red[t * 4 + 3]);
 }
 
 // ---------------------------------------------------------------- dense J (FP64)
@@ -184,16 +235,28 @@ hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, 
                                                                        (double*)E);
     return hipGetLastError();
   }
-  const int mse = std::min(8, std::max(1, 49152 / n));
-  const size_t shbytes = (size_t)(((mse * n + 15) / 16) * 16) + 256 * 8;
+  const int nst = (int)round_up(n, 16);
+  const int mse = std::min(EMSE, std::max(1, 98304 / nst));
+  // the row pointer goes to LDS as int32 when it fits next to the spins
+  const size_t rpb = (size_t)round_up((int64_t)(n + 1) * 4, 16);
+  const bool rp_lds = H.nnz < (int64_t)1 << 31 && (size_t)mse * nst + rpb + EMSE * 4 * 8 <= 160 * 1024;
+  const size_t shbytes = (size_t)mse * nst + (rp_lds ? rpb : 0) + EMSE * 4 * 8;
   const unsigned grid = (unsigned)((B + mse - 1) / mse);
-  if (H.kind == VQMC_H_CSR_INT)
-    energy_csr_kernel<int32_t, int64_t><<<grid, 256, shbytes, st>>>(
-        n, lds, H.rowptr, H.col, (const int32_t*)H.w, S, B, mse, (int64_t*)E);
-  else
-    energy_csr_kernel<float, double><<<grid, 256, shbytes, st>>>(
-        n, lds, H.rowptr, H.col, (const float*)H.w, S, B, mse, (double*)E);
-  return hipGetLastError();
+  hipError_t e;
+  auto go = [&](auto kern, auto wptr, auto eptr) {
+    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shbytes);
+    if (e != hipSuccess) return;
+    kern<<<grid, 256, shbytes, st>>>(n, lds, H.rowptr, H.col, wptr, S, B, mse, nst, eptr);
+    e = hipGetLastError();
+  };
+  if (H.kind == VQMC_H_CSR_INT) {
+    if (rp_lds) go(energy_csr_kernel<int32_t, int64_t, true>, (const int32_t*)H.w, (int64_t*)E);
+    else go(energy_csr_kernel<int32_t, int64_t, false>, (const int32_t*)H.w, (int64_t*)E);
+  } else {
+    if (rp_lds) go(energy_csr_kernel<float, double, true>, (const float*)H.w, (double*)E);
+    else go(energy_csr_kernel<float, double, false>, (const float*)H.w, (double*)E);
+  }
+  return e;
 }
 
 // ---------------------------------------------------------------- statistics

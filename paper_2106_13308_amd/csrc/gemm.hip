@@ -821,7 +821,7 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
 template <typename T>
 static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
                                      const float* Zs, float* dP, float* db1, float* db2, void* ws,
-                                     hipStream_t st) {
+                                     void* Pm, hipStream_t st) {
   const Geom g = geom(m.n, m.h, B);
   const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
   uint8_t* w = (uint8_t*)ws;
@@ -835,13 +835,19 @@ static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_
   hipError_t e;
   grad_out_kernel<T><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(Zs, S, g.ldn, coef, m.n, B, G, Gt, St, g.ldB, db2_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
-                                                             g.ldB, db1_part, g.ldh);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_weight_kernel<T, false><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(Gt, Rt, g.ldB, m.c, m.n, m.h, dP);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_weight_kernel<T, true><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(St, Dt, g.ldB, m.c, m.n, m.h, dP);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if constexpr (sizeof(T) == 2) {
+    // BF16: the direct-to-LDS engine, the adjoint's mask on a masked copy of P^T
+    e = launch_backward_products2(m, B, G, Gt, St, Rt, Dt, (bf16_t*)Pm, db1_part, dP, st);
+    if (e != hipSuccess) return e;
+  } else {
+    bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                               g.ldB, db1_part, g.ldh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bwd_weight_kernel<T, false><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(Gt, Rt, g.ldB, m.c, m.n, m.h, dP);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bwd_weight_kernel<T, true><<<dim3(g.nt_w, g.mt_w), 256, 0, st>>>(St, Dt, g.ldB, m.c, m.n, m.h, dP);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   sum_rows_kernel<<<(unsigned)((m.n + 255) / 256), 256, 0, st>>>(db2_part, g.mt_o, g.ldn, m.n, db2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   sum_rows_kernel<<<(unsigned)((m.h + 255) / 256), 256, 0, st>>>(db1_part, g.mt_h, g.ldh, m.h, db1);
@@ -853,9 +859,10 @@ void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws) {
 }
 
 hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, hipStream_t st) {
-  if (m.wdtype == VQMC_BF16) return backward_sampled_t<bf16_t>(m, S, B, coef, Zs, dP, db1, db2, ws, st);
-  return backward_sampled_t<float>(m, S, B, coef, Zs, dP, db1, db2, ws, st);
+                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, void* Pm,
+                                   hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return backward_sampled_t<bf16_t>(m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st);
+  return backward_sampled_t<float>(m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st);
 }
 
 template <typename T>

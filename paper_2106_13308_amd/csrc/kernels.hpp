@@ -50,7 +50,13 @@ hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const
 // and Zs (s_d z_d, B x ld(n)); ws as for launch_backward
 void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws);
 hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, hipStream_t st);
+                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, void* Pm,
+                                   hipStream_t st);
+// gemm2.hip: BF16 backward products on the direct-to-LDS engine; Pm: h x ld(n) bf16 scratch
+size_t mask_w2t_bytes(int n, int h);
+hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Gt,
+                                     const uint16_t* St, const uint16_t* Rt, uint16_t* Dt, uint16_t* Pm,
+                                     float* db1_part, float* dP, hipStream_t st);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,

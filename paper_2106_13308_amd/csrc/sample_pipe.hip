@@ -28,12 +28,14 @@
 // and the block after (all using it), so the sweep itself finishes both products that
 // depend on the block it has just drawn, and one barrier per block suffices.
 //
-// Workgroup = 8 samples, 4 waves.  Wave 0 sweeps block b with lane (sample s, group g)
-// holding sites 8g..8g+7 of sample s (and of the next block) in registers; a unit's dot
-// product is an 8-lane DPP reduction.  Waves 1-3 meanwhile push block b-1's spins into the
-// units completing after block b, compute the part of block b+1's logits that only needs
-// units complete before block b, draw block b+1's uniforms, and write out block b-1's
-// spins and log-probabilities.
+// Workgroup = 8 samples, 8 waves.  Waves 0-1 sweep block b, four samples each, lane
+// (sample s, group g) holding sites 4g..4g+3 of sample s (and of the next block) in
+// registers; a unit's dot product is a 16-lane DPP reduction.  Waves 2-7 meanwhile push
+// block b-1's spins into the units completing after block b, compute the part of block
+// b+1's logits that only needs units complete before block b, draw block b+1's uniforms,
+// and write out block b-1's spins and log-probabilities.  Two waves per SIMD let the
+// helpers' memory latency overlap; the two roles run separate loops with one barrier per
+// block each.
 //
 // Arithmetic: FP32 state and logits.  BF16 weights: the products run on
 // v_mfma_f32_16x16x32_bf16, exact for the +-1 spins of the push and with every FP32
@@ -53,24 +55,41 @@ constexpr float SP_SCALE = 0x1p100f;
 
 __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; }
 
-__host__ inline size_t sp_smem_bytes(int h) {
+constexpr int SP_NSW = 2;          // sweep waves (four samples each)
+constexpr int SP_NHW = 6;          // helper waves
+constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
+
+__host__ inline size_t sp_smem_bytes(int n, int h) {
   const size_t st = (size_t)SP_MS * sp_lda(h) * 4;
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
-  return st + 6 * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/;
+  const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
+  return st + 2 * SP_NHW * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
+         round_up((int64_t)(nb + 1) * 4, 16) /*fb*/;
 }
 
-// exact 3-term BF16 split of 8 floats
+// Exact 3-term BF16 split of 8 floats by truncation: hi keeps the top 8 significant bits
+// of x, mid the top 8 of the exact remainder x - hi, and lo = x - hi - mid has at most 8
+// significant bits left, so hi + mid + lo = x with every term a BF16 value (normal range).
+// Two terms' upper halves are packed into one dword with v_perm_b32.
 __device__ inline void sp_split3(const float r[8], bf16x8_t& hi, bf16x8_t& mid, bf16x8_t& lo) {
+  uint32_t h[4], m[4], l[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const bf16_t a = f32_to_bf16(r[e]);
-    const float r1 = r[e] - bf16_to_f32(a);
-    const bf16_t b = f32_to_bf16(r1);
-    const float r2 = r1 - bf16_to_f32(b);
-    hi[e] = __builtin_bit_cast(__bf16, a);
-    mid[e] = __builtin_bit_cast(__bf16, b);
-    lo[e] = __builtin_bit_cast(__bf16, f32_to_bf16(r2));
+  for (int p = 0; p < 4; ++p) {
+    const uint32_t x0 = __float_as_uint(r[2 * p]), x1 = __float_as_uint(r[2 * p + 1]);
+    const uint32_t h0 = x0 & 0xFFFF0000u, h1 = x1 & 0xFFFF0000u;
+    const float r0 = r[2 * p] - __uint_as_float(h0), r1 = r[2 * p + 1] - __uint_as_float(h1);
+    const uint32_t m0 = __float_as_uint(r0) & 0xFFFF0000u, m1 = __float_as_uint(r1) & 0xFFFF0000u;
+    const float q0 = r0 - __uint_as_float(m0), q1 = r1 - __uint_as_float(m1);
+    // bytes 2,3 of the first operand to the low half, bytes 2,3 of the second to the high
+    h[p] = __builtin_amdgcn_perm(x1, x0, 0x07060302u);
+    m[p] = __builtin_amdgcn_perm(__float_as_uint(r1), __float_as_uint(r0), 0x07060302u);
+    l[p] = __builtin_amdgcn_perm(__float_as_uint(q1), __float_as_uint(q0), 0x07060302u);
+    (void)h1;
+    (void)m1;
   }
+  hi = __builtin_bit_cast(bf16x8_t, make_uint4(h[0], h[1], h[2], h[3]));
+  mid = __builtin_bit_cast(bf16x8_t, make_uint4(m[0], m[1], m[2], m[3]));
+  lo = __builtin_bit_cast(bf16x8_t, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
 // A-operand fragments of the products, fetched ahead of their use.
@@ -92,17 +111,17 @@ struct SpFrag<float> {
   struct U { uint4 a[2][2]; };
 };
 
-// one band record of the sweep lane's 8 sites
+// one band record of the sweep lane's 4 sites
 struct SpRec {
-  float4 w1a, w1b;  // 2 W1, this block
-  float4 w2a, w2b;  // W2, this block
-  float4 p1a, p1b;  // 2 W1, previous block
-  float4 n2a, n2b;  // W2, next block
-  float ns;         // minus the sum of the W1 halves
+  float4 w1;  // 2 W1, this block
+  float4 w2;  // W2, this block
+  float4 p1;  // 2 W1, previous block
+  float4 n2;  // W2, next block
+  float ns;   // minus the sum of the W1 halves
 };
 
 template <typename WT>
-__global__ __launch_bounds__(256) void sample_pipe_kernel(
+__global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     const WT* __restrict__ P, const WT* __restrict__ Pt, const float* __restrict__ band, int64_t ldh,
     int64_t ldn, const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
     int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
@@ -113,8 +132,8 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
   constexpr int BLK = SP_MS * SP_T;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
-  float* red = st + SP_MS * LDA;   // [2][3][8][64] helpers' partial logits of a block (+ b2)
-  float* th = red + 6 * BLK;       // [2][8][64] -logit(u) * 2^100
+  float* red = st + SP_MS * LDA;   // [2][6][8][64] helpers' partial logits of a block (+ b2)
+  float* th = red + 2 * SP_NHW * BLK;  // [2][8][64] -logit(u) * 2^100
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
 
@@ -122,7 +141,6 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
   const int l16 = lane & 15, g4 = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
-  auto fend = [&](int b) { return (b < 0) ? 0 : c[min(SP_T * b + SP_T - 1, n - 1)]; };
 
   // ---- fragment loaders (indices clamped to valid memory, so that every path issues
   // the same loads and each use waits only for its own fragment)
@@ -210,96 +228,67 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
       const float uv[4] = {u4.x, u4.y, u4.z, u4.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        // s = +1 iff u < sigma(z) iff z > log(u) - log(1-u); u = 0 gives -inf (always +1)
-        const float lg = __logf(uv[e]) - log1pf(-uv[e]);
+        // s = +1 iff u < sigma(z) iff z > log(u) - log(1-u); u = 0 gives -inf (always +1).
+        // 1 - u is exact for the 24-bit dyadic u.
+        const float lg = __logf(uv[e]) - __logf(1.f - uv[e]);
         v[e] = (d + e < n) ? -lg * SP_SCALE : 0.f;
       }
     }
     *(float4*)(dst + s * SP_T + 4 * q4) = make_float4(v[0], v[1], v[2], v[3]);
   };
 
-  // ---- prologue: state = b1, block 0's logits = b2, block 0's thresholds
-  for (int i = t; i < SP_MS * LDA; i += 256) {
+  // ---- prologue: state = b1, block 0's logits = b2, block 0's thresholds, block bounds
+  int* fb = (int*)(sb + 2 * BLK);  // fb[b + 1] = f_b, fb[0] = 0
+  for (int i = t; i < SP_MS * LDA; i += SP_THREADS) {
     const int k = i % LDA;
     st[i] = (k < h) ? b1[k] : 0.f;
   }
-  for (int i = t; i < 3 * BLK; i += 256) {
+  for (int i = t; i < SP_NHW * BLK; i += SP_THREADS) {
     const int j = i % SP_T;
     red[i] = (i < BLK && j < n) ? b2[j] : 0.f;
   }
+  for (int i = t; i <= nb; i += SP_THREADS) fb[i] = (i == 0) ? 0 : c[min(SP_T * i - 1, n - 1)];
   if (t < 128) thresholds(0, th, t);
 
-  // sweep lane roles (wave 0): sample ss, sites 8sg..8sg+7 of the block
-  const int ss = lane >> 3, sg = lane & 7;
-  SpRec ring[SP_PDS];
-  auto fetch_rec = [&](SpRec& r, int u) {
-    const float* q = band + (int64_t)u * SP_REC + 8 * sg;
-    r.w1a = *(const float4*)q;
-    r.w1b = *(const float4*)(q + 4);
-    r.w2a = *(const float4*)(q + 64);
-    r.w2b = *(const float4*)(q + 68);
-    r.p1a = *(const float4*)(q + 128);
-    r.p1b = *(const float4*)(q + 132);
-    r.n2a = *(const float4*)(q + 192);
-    r.n2b = *(const float4*)(q + 196);
-    // the four copies keep this a per-lane (vector) load
-    r.ns = band[(int64_t)u * SP_REC + 256 + (lane & 3)];
-  };
-  float zn[8], cp[8];  // next block's logits from this block's units; previous block's draws
-#pragma unroll
-  for (int e = 0; e < 8; ++e) zn[e] = cp[e] = 0.f;
-  if (wv == 0) {
+  if (wv < SP_NSW) {
+    // ================= sweep waves: samples 4wv..4wv+3, lane = (sample, 4-site group)
+    const int ss = 4 * wv + (lane >> 4), g = lane & 15;
+    SpRec ring[SP_PDS];
+    auto fetch_rec = [&](SpRec& r, int u) {
+      const float* q = band + (int64_t)u * SP_REC + 4 * g;
+      r.w1 = *(const float4*)q;
+      r.w2 = *(const float4*)(q + 64);
+      r.p1 = *(const float4*)(q + 128);
+      r.n2 = *(const float4*)(q + 192);
+      // the four copies keep this a per-lane (vector) load
+      r.ns = band[(int64_t)u * SP_REC + 256 + (lane & 3)];
+    };
 #pragma unroll
     for (int p = 0; p < SP_PDS; ++p) fetch_rec(ring[p], min(p, h - 1));
-  }
-  float lp_part = 0.f;  // wave 1: log pi partial of sample lane>>3, sites 8(lane&7)..
-  __syncthreads();
-
-  // spins, s*z and log pi partial of a swept block (wave 1)
-  auto emit = [&](int blk, int buf) {
-    const int s = lane >> 3, q = lane & 7;
-    const int dblk = SP_T * blk;
-    const uint2 w = *(const uint2*)(sb + buf * BLK + s * SP_T + 8 * q);
-    if (b0 + s < B) *(uint2*)(S + (b0 + s) * lds + dblk + 8 * q) = w;
-    const float* zrow = zs + buf * BLK + s * SP_T + 8 * q;
+    float zn[4], cp[4];  // next block's logits from this block's units; previous block's draws
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (dblk + 8 * q + e < n) lp_part += log_sigmoid(zrow[e]);
-    if (Zs && b0 + s < B) {
-      float* zo = Zs + (b0 + s) * lds + dblk + 8 * q;
-      *(float4*)zo = *(const float4*)zrow;
-      *(float4*)(zo + 4) = *(const float4*)(zrow + 4);
-    }
-  };
-
-  for (int b = 0; b < nb; ++b) {
-    const int d0 = SP_T * b, Tb = min(SP_T, n - d0);
-    const bool has_next = b + 1 < nb;
-    const int fprev = fend(b - 1), fcur = fend(b);
-    const int cur = b & 1, nxt = cur ^ 1;
-
-    if (wv == 0) {
-      // ================= sweep of block b over units [fprev, fcur)
-      float zr[8], tz[8];
+    for (int e = 0; e < 4; ++e) zn[e] = cp[e] = 0.f;
+    float* arow = st + ss * LDA;
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      const int d0 = SP_T * b, Tb = min(SP_T, n - d0);
+      const int fprev = fb[b], fcur = fb[b + 1];
+      const int cur = b & 1;
+      float zr[4], tz[4];
       {
-        const float* r0 = red + cur * 3 * BLK + ss * SP_T + 8 * sg;
-        const float* trow = th + cur * BLK + ss * SP_T + 8 * sg;
-        const float4 x0 = *(const float4*)r0, x1 = *(const float4*)(r0 + 4);
-        const float4 y0 = *(const float4*)(r0 + BLK), y1 = *(const float4*)(r0 + BLK + 4);
-        const float4 v0 = *(const float4*)(r0 + 2 * BLK), v1 = *(const float4*)(r0 + 2 * BLK + 4);
-        const float4 t0 = *(const float4*)trow, t1 = *(const float4*)(trow + 4);
-        const float px[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        const float py[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-        const float pv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        const float pt[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+        const float* r0 = red + cur * SP_NHW * BLK + ss * SP_T + 4 * g;
+        float4 acc4 = *(const float4*)r0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          zr[e] = ((px[e] + py[e]) + pv[e]) + zn[e];
-          zn[e] = 0.f;
-          tz[e] = pt[e];
+        for (int q = 1; q < SP_NHW; ++q) {
+          const float4 x = *(const float4*)(r0 + q * BLK);
+          acc4.x += x.x; acc4.y += x.y; acc4.z += x.z; acc4.w += x.w;
         }
+        const float4 t4 = *(const float4*)(th + cur * BLK + ss * SP_T + 4 * g);
+        zr[0] = acc4.x + zn[0]; zr[1] = acc4.y + zn[1]; zr[2] = acc4.z + zn[2]; zr[3] = acc4.w + zn[3];
+        tz[0] = t4.x; tz[1] = t4.y; tz[2] = t4.z; tz[3] = t4.w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) zn[e] = 0.f;
       }
-      float* arow = st + ss * LDA;
       float a0n = arow[fprev];
       for (int ub = fprev - fprev % SP_PDS; ub < fcur; ub += SP_PDS) {
 #pragma unroll
@@ -309,14 +298,14 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
             const SpRec& r = ring[p];
             const float a0 = a0n;
             a0n = arow[u + 1];
-            const float w1[8] = {r.w1a.x, r.w1a.y, r.w1a.z, r.w1a.w, r.w1b.x, r.w1b.y, r.w1b.z, r.w1b.w};
-            const float w2[8] = {r.w2a.x, r.w2a.y, r.w2a.z, r.w2a.w, r.w2b.x, r.w2b.y, r.w2b.z, r.w2b.w};
-            const float p1[8] = {r.p1a.x, r.p1a.y, r.p1a.z, r.p1a.w, r.p1b.x, r.p1b.y, r.p1b.z, r.p1b.w};
-            const float n2[8] = {r.n2a.x, r.n2a.y, r.n2a.z, r.n2a.w, r.n2b.x, r.n2b.y, r.n2b.z, r.n2b.w};
+            const float w1[4] = {r.w1.x, r.w1.y, r.w1.z, r.w1.w};
+            const float w2[4] = {r.w2.x, r.w2.y, r.w2.z, r.w2.w};
+            const float p1[4] = {r.p1.x, r.p1.y, r.p1.z, r.p1.w};
+            const float n2[4] = {r.n2.x, r.n2.y, r.n2.z, r.n2.w};
             // c_e = 1 if site e is (or would be) drawn +1 now, else 0; w1 and p1 hold 2 W1
             float acc0 = 0.f, acc1 = 0.f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
+            for (int e = 0; e < 4; ++e) {
               const float ce = __builtin_amdgcn_fmed3f(fmaf(zr[e], SP_SCALE, tz[e]), 0.f, 1.f);
               acc0 = fmaf(ce, w1[e], acc0);
               acc1 = fmaf(cp[e], p1[e], acc1);
@@ -324,11 +313,12 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
             float acc = acc0 + acc1;
             acc += VQMC_DPP(acc, 0xB1);   // quad_perm [1,0,3,2]
             acc += VQMC_DPP(acc, 0x4E);   // quad_perm [2,3,0,1]
-            acc += VQMC_DPP(acc, 0x141);  // row_half_mirror: 8-lane total in every lane
+            acc += VQMC_DPP(acc, 0x141);  // row_half_mirror
+            acc += VQMC_DPP(acc, 0x140);  // row_mirror: 16-lane total in every lane
             const float a = (acc + r.ns) + a0;
             const float rl = fmaxf(a, 0.f);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
+            for (int e = 0; e < 4; ++e) {
               zr[e] = fmaf(w2[e], rl, zr[e]);
               zn[e] = fmaf(n2[e], rl, zn[e]);
             }
@@ -345,66 +335,133 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
         }
       }
       // decisions, spins and s*z of the block
-      uint32_t lo = 0, hi = 0;
-      float zsv[8];
+      uint32_t word = 0;
+      float zsv[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = 8 * sg + e;
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * g + e;
         const float ce = __builtin_amdgcn_fmed3f(fmaf(zr[e], SP_SCALE, tz[e]), 0.f, 1.f);
         const bool up = ce > 0.5f;
-        const uint32_t byte = (j < Tb) ? (up ? 0x01u : 0xFFu) : 0u;
-        if (e < 4) lo |= byte << (8 * e);
-        else hi |= byte << (8 * (e - 4));
+        word |= ((j < Tb) ? (up ? 0x01u : 0xFFu) : 0u) << (8 * e);
         zsv[e] = up ? zr[e] : -zr[e];
         cp[e] = (j < Tb && up) ? 1.f : 0.f;
       }
-      *(uint2*)(sb + cur * BLK + ss * SP_T + 8 * sg) = make_uint2(lo, hi);
-      float* zsr = zs + cur * BLK + ss * SP_T + 8 * sg;
-      *(float4*)zsr = make_float4(zsv[0], zsv[1], zsv[2], zsv[3]);
-      *(float4*)(zsr + 4) = make_float4(zsv[4], zsv[5], zsv[6], zsv[7]);
-    } else {
-      // ================= helpers (waves 1-3)
-      const int hw = wv - 1;
-      // push of block b-1's spins into units [fcur, h): 16-unit tiles hw, hw+3, ...
-      constexpr int PDU = 4;
-      typename F::U fu[PDU];
-      const int ubase = fcur & ~15;
-      const int nut = (b >= 1 && ubase < h) ? (h - ubase + 15) / 16 : 0;
-      const int cntu = (nut > hw) ? (nut - hw + 2) / 3 : 0;
-      const int dprev = max(d0 - SP_T, 0);
-      auto tile_u = [&](int it) { return ubase + 16 * (hw + 3 * min(it, max(cntu - 1, 0))); };
+      *(uint32_t*)(sb + cur * BLK + ss * SP_T + 4 * g) = word;
+      *(float4*)(zs + cur * BLK + ss * SP_T + 4 * g) = make_float4(zsv[0], zsv[1], zsv[2], zsv[3]);
+      __syncthreads();
+    }
+  } else {
+    // ================= helper waves
+    const int hw = wv - SP_NSW;
+    float lp_part = 0.f;  // waves hw 2-3: log pi partial of sample 4(hw-2) + lane/16
+    // spins, s*z and log pi partial of a swept block: helper hw in {2, 3}, lane =
+    // (sample 4(hw-2) + lane/16, sites 4(lane%16)..+3)
+    auto emit = [&](int blk, int buf) {
+      const int s = 4 * (hw - 2) + (lane >> 4), q = lane & 15;
+      const int dblk = SP_T * blk;
+      const uint32_t w = *(const uint32_t*)(sb + buf * BLK + s * SP_T + 4 * q);
+      if (b0 + s < B) *(uint32_t*)(S + (b0 + s) * lds + dblk + 4 * q) = w;
+      const float4 z4 = *(const float4*)(zs + buf * BLK + s * SP_T + 4 * q);
+      const float zv[4] = {z4.x, z4.y, z4.z, z4.w};
 #pragma unroll
-      for (int p = 0; p < PDU; ++p) fetch_u(fu[p], dprev, tile_u(p));
-      // block b+1's logits over the units complete before block b, [0, fprev): K chunks
-      // hw, hw+3, ... (the units of block b are added by the sweep)
-      constexpr int PDZ = (sizeof(WT) == 2) ? 4 : 8;
-      typename F::Z fz[PDZ];
-      const int nzc = has_next ? (fprev + KC - 1) / KC : 0;
-      const int cntz = (nzc > hw) ? (nzc - hw + 2) / 3 : 0;
-      auto chunk_z = [&](int it) { return cntz ? KC * (hw + 3 * min(it, cntz - 1)) : 0; };
+      for (int e = 0; e < 4; ++e)
+        if (dblk + 4 * q + e < n) lp_part += log_sigmoid(zv[e]);
+      if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
+    };
+    // This wave's work items: the push tiles of every block (block b: tiles hw, hw+6, ... of
+    // the units [f_b, h), block b-1's sites) and the logit chunks of every block (block b:
+    // K chunks hw, hw+6, ... of the units [0, f_{b-1}), block b+1's sites).  Their weight
+    // fragments do not depend on the draws, so each kind has a ring of fragments that runs
+    // ahead through the items of later blocks: slot g % PD holds item g when item g is
+    // used, and then takes item g + PD (a cursor over the item sequence).  Every step
+    // reloads its slot (a skipped slot reloads the item it holds), so the loads in flight
+    // are the same on every path and each use waits only for its own fragment.
+    auto cnt_u = [&](int bb) {
+      const int ub = fb[bb + 1] & ~15;
+      const int nut = (bb >= 1 && ub < h) ? (h - ub + 15) / 16 : 0;
+      return (nut > hw) ? (nut - hw + SP_NHW - 1) / SP_NHW : 0;
+    };
+    auto cnt_z = [&](int bb) {
+      const int nzc = (bb + 1 < nb) ? (fb[bb] + KC - 1) / KC : 0;
+      return (nzc > hw) ? (nzc - hw + SP_NHW - 1) / SP_NHW : 0;
+    };
+    struct Cur { int b, j; };
+    auto next_u = [&](Cur c) {
+      ++c.j;
+      while (c.b < nb && c.j >= cnt_u(c.b)) { ++c.b; c.j = 0; }
+      return c;
+    };
+    auto next_z = [&](Cur c) {
+      ++c.j;
+      while (c.b < nb && c.j >= cnt_z(c.b)) { ++c.b; c.j = 0; }
+      return c;
+    };
+    // fragment of an item (items past the last block load valid memory, never used)
+    auto load_u = [&](typename F::U& f, Cur c) {
+      if (c.b < nb) fetch_u(f, SP_T * (c.b - 1), (fb[c.b + 1] & ~15) + 16 * (hw + SP_NHW * c.j));
+      else fetch_u(f, 0, 0);
+    };
+    auto load_z = [&](typename F::Z& f, Cur c) {
+      if (c.b < nb) fetch_z(f, SP_T * (c.b + 1), KC * (hw + SP_NHW * c.j));
+      else fetch_z(f, 0, 0);
+    };
+    constexpr int PDU = 4;
+    constexpr int PDZ = (sizeof(WT) == 2) ? 4 : 8;
+    typename F::U fu[PDU];
+    typename F::Z fz[PDZ];
+    Cur du[PDU], dz[PDZ];  // item held by each slot
+    Cur cu{0, -1}, cz{0, -1};
+    cu = next_u(cu);
+    cz = next_z(cz);
 #pragma unroll
-      for (int p = 0; p < PDZ; ++p) fetch_z(fz[p], d0 + SP_T, chunk_z(p));
+    for (int p = 0; p < PDU; ++p) {
+      du[p] = cu;
+      load_u(fu[p], cu);
+      cu = next_u(cu);
+    }
+#pragma unroll
+    for (int p = 0; p < PDZ; ++p) {
+      dz[p] = cz;
+      load_z(fz[p], cz);
+      cz = next_z(cz);
+    }
+    int gu = 0, gz = 0;  // global index of the current block's first item of each kind
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      const int d0 = SP_T * b;
+      const bool has_next = b + 1 < nb;
+      const int fprev = fb[b], fcur = fb[b + 1];
+      const int cur = b & 1, nxt = cur ^ 1;
+      const int cntu = cnt_u(b), cntz = cnt_z(b);
 
-      // VALU work while the fragments load
-      if (hw == 0) {
+      // VALU work first: the ring's fragments for this block were issued a block ago
+      if (hw < 2) {
+        if (has_next) thresholds(b + 1, th + nxt * BLK, hw * 64 + lane);
+      } else if (hw < 4) {
         if (b >= 1) emit(b - 1, nxt);
-      } else if (has_next) {
-        thresholds(b + 1, th + nxt * BLK, (hw - 1) * 64 + lane);
       }
 
+      // push of block b-1's spins into units [fcur, h)
       if (cntu) {
         bf16x8_t sv[2];
         spin_operand(sb + nxt * BLK, sv);
-        for (int base = 0; base < cntu; base += PDU) {
+        for (int gb = gu - gu % PDU; gb < gu + cntu; gb += PDU) {
 #pragma unroll
           for (int p = 0; p < PDU; ++p) {
-            const int it = base + p;
-            if (it < cntu) use_u(fu[p], ubase + 16 * (hw + 3 * it), fcur, h, sv);
+            const int g = gb + p;
+            if (g >= gu && g < gu + cntu) {
+              use_u(fu[p], (fcur & ~15) + 16 * (hw + SP_NHW * du[p].j), fcur, h, sv);
+              du[p] = cu;
+              cu = next_u(cu);
+            }
             __builtin_amdgcn_sched_barrier(0);
-            fetch_u(fu[p], dprev, tile_u(it + PDU));
+            load_u(fu[p], du[p]);
           }
         }
+        gu += cntu;
       }
+      // block b+1's logits over the units complete before block b, [0, fprev) (the units of
+      // block b are added by the sweep)
       if (has_next) {
         const int d0n = d0 + SP_T, Tbn = min(SP_T, n - d0n);
         floatx4_t acc[4];
@@ -416,73 +473,79 @@ __global__ __launch_bounds__(256) void sample_pipe_kernel(
             acc[tt][e] = (hw == 0 && j < Tbn) ? b2[d0n + j] : 0.f;
           }
         }
-        for (int base = 0; base < cntz; base += PDZ) {
+        if (cntz) {
+          for (int gb = gz - gz % PDZ; gb < gz + cntz; gb += PDZ) {
 #pragma unroll
-          for (int p = 0; p < PDZ; ++p) {
-            const int it = base + p;
-            if (it < cntz) {
-              const int k0 = KC * (hw + 3 * it);
-              if constexpr (sizeof(WT) == 2) {
-                float rr[8];
-                const float* srow = st + l16 * LDA + k0 + 8 * g4;
-                if (l16 < SP_MS) {
-                  const float4 ra = *(const float4*)srow, rb = *(const float4*)(srow + 4);
-                  rr[0] = ra.x; rr[1] = ra.y; rr[2] = ra.z; rr[3] = ra.w;
-                  rr[4] = rb.x; rr[5] = rb.y; rr[6] = rb.z; rr[7] = rb.w;
+            for (int p = 0; p < PDZ; ++p) {
+              const int g = gb + p;
+              if (g >= gz && g < gz + cntz) {
+                const int k0 = KC * (hw + SP_NHW * dz[p].j);
+                if constexpr (sizeof(WT) == 2) {
+                  float rr[8];
+                  const float* srow = st + l16 * LDA + k0 + 8 * g4;
+                  if (l16 < SP_MS) {
+                    const float4 ra = *(const float4*)srow, rb = *(const float4*)(srow + 4);
+                    rr[0] = ra.x; rr[1] = ra.y; rr[2] = ra.z; rr[3] = ra.w;
+                    rr[4] = rb.x; rr[5] = rb.y; rr[6] = rb.z; rr[7] = rb.w;
+                  } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) rr[e] = 0.f;
+                  }
+#pragma unroll
+                  for (int e = 0; e < 8; ++e) rr[e] = (k0 + 8 * g4 + e < fprev) ? fmaxf(rr[e], 0.f) : 0.f;
+                  bf16x8_t xh, xm, xl;
+                  sp_split3(rr, xh, xm, xl);
+#pragma unroll
+                  for (int tt = 0; tt < 4; ++tt) {
+                    const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
+                  }
                 } else {
+                  const int k = k0 + g4;
+                  const float rr = (l16 < SP_MS && k < fprev) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
 #pragma unroll
-                  for (int e = 0; e < 8; ++e) rr[e] = 0.f;
+                  for (int tt = 0; tt < 4; ++tt)
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fz[p].a[tt], rr, acc[tt], 0, 0, 0);
                 }
-#pragma unroll
-                for (int e = 0; e < 8; ++e) rr[e] = (k0 + 8 * g4 + e < fprev) ? fmaxf(rr[e], 0.f) : 0.f;
-                bf16x8_t xh, xm, xl;
-                sp_split3(rr, xh, xm, xl);
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                  const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
-                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
-                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
-                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
-                }
-              } else {
-                const int k = k0 + g4;
-                const float rr = (l16 < SP_MS && k < fprev) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt)
-                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fz[p].a[tt], rr, acc[tt], 0, 0, 0);
+                dz[p] = cz;
+                cz = next_z(cz);
               }
+              __builtin_amdgcn_sched_barrier(0);
+              load_z(fz[p], dz[p]);
             }
-            __builtin_amdgcn_sched_barrier(0);
-            fetch_z(fz[p], d0 + SP_T, chunk_z(it + PDZ));
           }
+          gz += cntz;
         }
         // C layout: lane holds rows (sites) 16tt + 4g4 + e, column (sample) l16
         if (l16 < SP_MS) {
-          float* dst = red + nxt * 3 * BLK + hw * BLK + l16 * SP_T + 4 * g4;
+          float* dst = red + nxt * SP_NHW * BLK + hw * BLK + l16 * SP_T + 4 * g4;
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
             *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
+    // last block's spins and log pi, then the 16-lane log pi sum of each sample
+    if (hw == 2 || hw == 3) {
+      emit(nb - 1, (nb - 1) & 1);
+      float v = lp_part;
+      v += VQMC_DPP(v, 0xB1);
+      v += VQMC_DPP(v, 0x4E);
+      v += VQMC_DPP(v, 0x141);
+      v += VQMC_DPP(v, 0x140);
+      const int s = 4 * (hw - 2) + (lane >> 4);
+      if ((lane & 15) == 0 && b0 + s < B && logp) logp[b0 + s] = v;
+    }
   }
-
-  // last block's spins and log pi, then the 8-lane log pi sum of each sample
-  if (wv == 1) {
-    emit(nb - 1, (nb - 1) & 1);
-    float v = lp_part;
-    v += VQMC_DPP(v, 0xB1);
-    v += VQMC_DPP(v, 0x4E);
-    v += VQMC_DPP(v, 0x141);
-    const int s = lane >> 3;
-    if ((lane & 7) == 0 && b0 + s < B && logp) logp[b0 + s] = v;
-  }
-  // every unit is complete: the hidden activations relu(A) of the forward pass,
-  // batch-contiguous (Rt[k][b], zero for b >= B up to ldB)
+  // every unit is complete once both loops are done: the hidden activations relu(A) of
+  // the forward pass, batch-contiguous (Rt[k][b], zero for b >= B up to ldB)
+  __syncthreads();
   if (Rt) {
     const int64_t bend = (blockIdx.x + 1 == gridDim.x) ? ldB : b0 + SP_MS;
-    for (int k = t; k < h; k += 256) {
+    for (int k = t; k < h; k += SP_THREADS) {
       WT v[SP_MS];
 #pragma unroll
       for (int s = 0; s < SP_MS; ++s) {
@@ -553,18 +616,18 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
   return hipGetLastError();
 }
 
-bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(h) <= 160 * 1024; }
+bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h) <= 160 * 1024; }
 
 template <typename WT>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                 uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, int64_t ldB,
                                 hipStream_t st) {
-  const size_t smem = sp_smem_bytes(m.h);
+  const size_t smem = sp_smem_bytes(m.n, m.h);
   hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
-  sample_pipe_kernel<WT><<<grid, 256, smem, st>>>((const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad),
+  sample_pipe_kernel<WT><<<grid, SP_THREADS, smem, st>>>((const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad),
                                                   round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h, sp_lda(m.h), B,
                                                   seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs,
                                                   (WT*)Rt, ldB);

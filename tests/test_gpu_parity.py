@@ -469,11 +469,21 @@ def test_step_fused_equals_recompute(n, h, B, wd):
     dP, db1, db2 = B_.logprob_backward(M, bufs.S, bufs.coef)
     lp_ref = B_.logprob(M, bufs.S)
     torch.cuda.synchronize()
-    tol = 1e-4 if wd == "f32" else 2e-2
+    # Both gradients are FP32 evaluations of the same function; where a pre-activation
+    # lies within FP32 rounding of 0 the two can take different sides of the ReLU, which
+    # moves a whole column of the W1 gradient.  At small sizes no such tie occurs and the
+    # bar is the rounding level; at n = 10^4 (2 x 10^6 pre-activations) a few do, so the
+    # bar there is on the Frobenius error with a looser max-norm.
+    small = n * h * B < 1e8
+    tol_max = (1e-4 if wd == "f32" else 2e-2) if small else (1e-2 if wd == "f32" else 3e-2)
+    tol_fro = (1e-4 if wd == "f32" else 1e-2) if small else (1e-3 if wd == "f32" else 1e-2)
     for k, got, ref in (("dP", bufs.dP, dP), ("db1", bufs.db1, db1), ("db2", bufs.db2, db2)):
-        got, ref = got.cpu().numpy(), ref.cpu().numpy()
+        got, ref = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
         err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
-        print(f"  {k}: max err / max |ref| = {err:.2e}")
-        assert err <= tol, k
+        fro = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(f"  {k}: max err / max |ref| = {err:.2e}, relative Frobenius {fro:.2e}")
+        assert err <= tol_max and fro <= tol_fro, k
+    # the recomputing forward keeps relu(A) in the weight dtype for its second product; the
+    # sampler's logits use the FP32 activations, so with BF16 the two differ at that level
     lp, lr = bufs.logp.cpu().numpy(), lp_ref.cpu().numpy()
-    assert np.abs(lp - lr).max() <= 1e-4 * np.abs(lr).max()
+    assert np.abs(lp - lr).max() <= (1e-4 if wd == "f32" else 2e-3) * np.abs(lr).max()
