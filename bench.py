@@ -104,13 +104,22 @@ def time_calls(made, H, B_, reps=10, seed=2):
     bufs = B.StepBuffers.allocate(made, H, B_)
     B.step(made, H, B_, seed, 0, bufs)
     ws_bw = B.workspace(B.WS_BACKWARD, made, B_)
-    calls = {
-        "sample": lambda: B.sample(made, B_, seed, 1, S=bufs.S, logp=bufs.logp),
+    calls = {}
+    if made.band is not None:
+        # the calls vqmc_step makes: sampling with the forward byproducts, energy, statistics,
+        # and the backward from those byproducts
+        S, lp, Zs, Rt = B.sample_fwd(made, B_, seed, 1)
+        ws_bs = B.workspace(B.WS_BACKWARD_SAMPLED, made, B_)
+        calls["sample"] = lambda: B.sample_fwd(made, B_, seed, 1, S=S, logp=lp, Zs=Zs, Rt=Rt)
+        calls["backward_sampled"] = lambda: B.backward_sampled(made, S, bufs.coef, Zs, Rt, ws=ws_bs)
+    else:
+        calls["sample"] = lambda: B.sample(made, B_, seed, 1, S=bufs.S, logp=bufs.logp)
+    calls.update({
         "energy": lambda: B.energy(H, bufs.S, B_),
         "stats": lambda: B.batch_stats(bufs.E),
         "logprob_backward": lambda: B.logprob_backward(made, bufs.S, bufs.coef, ws=ws_bw),
         "logprob": lambda: B.logprob(made, bufs.S),
-    }
+    })
     out = {}
     for name, fn in calls.items():
         fn()
@@ -143,6 +152,8 @@ def algorithmic_work(w, made, H):
         "logprob": {"flops": 2.0 * nh * B_},
         # backward: forward recompute (n*h) + hidden adjoint (sum_c) + weight gradient (n*h)
         "logprob_backward": {"flops": 2.0 * (2 * nh + sum_c) * B_},
+        # backward from the sampler's byproducts: hidden adjoint (sum_c) + weight gradient (n*h)
+        "backward_sampled": {"flops": 2.0 * (nh + sum_c) * B_},
     }
     return work
 
@@ -153,7 +164,7 @@ def _dominant_desc(call, made, H):
     mm = PEAK["bf16_mfma_tflops"] if bf16 else PEAK["fp32_mfma_tflops"]
     if call == "sample":
         if made.band is not None:
-            k = "sample_pipe_kernel<bf16>" if bf16 else "sample_pipe_kernel<float>"
+            k = "sample_pipe_kernel<bf16" if bf16 else "sample_pipe_kernel<float"  # prefix: <T, planes>
             return {"kernels": [k], "src": ["sample_pipe.hip"], "bound": "mfma", "peak": mm,
                     "unit": "TFLOP/s", "metric": "tflops"}
         if made.h <= 2048:
@@ -169,6 +180,14 @@ def _dominant_desc(call, made, H):
         return {"kernels": ["energy_csr_kernel<int, long>"], "src": ["energy.hip"], "bound": "hbm",
                 "peak": PEAK["hbm_gbs"], "unit": "GB/s", "metric": "gbs"}
     t = "bf16" if bf16 else "float"
+    if call == "backward_sampled" and bf16:
+        return {"kernels": ["grad_out_kernel<bf16>", "mask_w2t_kernel", "bwd_hidden2_kernel", "bwd_weight2_kernel",
+                            "sum_rows_kernel"],
+                "src": ["gemm.hip", "gemm2.hip"], "bound": "mfma", "peak": mm, "unit": "TFLOP/s", "metric": "tflops"}
+    if call == "backward_sampled":
+        return {"kernels": [f"grad_out_kernel<{t}>", f"bwd_hidden_kernel<{t}>", f"bwd_weight_kernel<{t}, false>",
+                            f"bwd_weight_kernel<{t}, true>", "sum_rows_kernel"],
+                "src": ["gemm.hip"], "bound": "mfma", "peak": mm, "unit": "TFLOP/s", "metric": "tflops"}
     return {"kernels": [f"fwd_hidden_kernel<{t}, true>", f"fwd_out_kernel<{t}, 1>", f"bwd_hidden_kernel<{t}>",
                         f"bwd_weight_kernel<{t}, false>", f"bwd_weight_kernel<{t}, true>", "sum_rows_kernel"],
             "src": ["gemm.hip"], "bound": "mfma", "peak": mm, "unit": "TFLOP/s", "metric": "tflops"}
@@ -194,6 +213,8 @@ def _traffic(desc, workload):
     tot = 0.0
     for k in desc["kernels"]:
         e = rec["kernels"].get(k)
+        if e is None:  # a name prefix (template arguments chosen at launch)
+            e = next((v for name, v in rec["kernels"].items() if name.startswith(k)), None)
         if e is None or e.get("fetch_bytes") is None or e.get("write_bytes") is None:
             return None
         tot += (e["fetch_bytes"] + e["write_bytes"]) * e.get("launches_per_call", 1)
@@ -288,7 +309,8 @@ def main():
         if "bytes" in wk:
             d["gbs"] = wk["bytes"] / (t / 1e3) / 1e9
         kernels[name] = d
-    step_calls = {k: calls[k] for k in ("sample", "energy", "stats", "logprob_backward")}
+    grad_call = "backward_sampled" if "backward_sampled" in calls else "logprob_backward"
+    step_calls = {k: calls[k] for k in ("sample", "energy", "stats", grad_call)}
     dom = max(step_calls, key=step_calls.get)
     roof = roofline(dom, kernels, made, H, w.name)
     forms = {"bf16_incremental": {"ms_per_step": ms, "samples_per_s": value}}

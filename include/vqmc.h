@@ -110,7 +110,13 @@ int64_t vqmc_ld(int64_t x);
 const char* vqmc_error_string(int status);
 const char* vqmc_last_error(void);
 
-enum { VQMC_WS_LOGPROB = 0, VQMC_WS_BACKWARD = 1, VQMC_WS_SAMPLE_PLAIN = 2, VQMC_WS_STEP = 3 };
+enum {
+  VQMC_WS_LOGPROB = 0,
+  VQMC_WS_BACKWARD = 1,
+  VQMC_WS_SAMPLE_PLAIN = 2,
+  VQMC_WS_STEP = 3,
+  VQMC_WS_BACKWARD_SAMPLED = 4
+};
 /* Workspace bytes needed by a call (host function, no device access). */
 size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
 
@@ -157,6 +163,25 @@ int vqmc_band(const vqmc_made* m, float* band, void* stream);
 int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
                 uint32_t tag, int8_t* S, float* logp, void* stream);
 
+/* vqmc_sample (pipelined kernel; needs m->band) that also returns the forward quantities the
+ * gradient needs, so that vqmc_backward_sampled does not recompute the forward pass
+ * (Sec. 5.1 MaskedFC1 -> ReLU -> MaskedFC2 evaluated along the way by Algorithm 1):
+ *   Zs (nullable): B x ld(n) floats, Zs[b][d] = s_d z_d, the drawn spin times its logit
+ *                  (columns >= n are 0); log pi(s_b) = sum_d log sigma(Zs[b][d]).
+ *   Rt (nullable): h x ld(B) values of type m->wdtype, Rt[k][b] = relu(A_k(s_b)), the hidden
+ *                  activations, batch-contiguous (columns >= B are 0).
+ * Zs and Rt 16-byte aligned.  EINVAL without a band or when h is too large for the kernel. */
+int vqmc_sample_fwd(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                    uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, void* stream);
+
+/* Gradient of F = sum_b coef_b log pi(s_b) (as vqmc_logprob_backward) from the Zs and Rt that
+ * vqmc_sample_fwd wrote for S: G = coef_b s sigma(-s z) directly from Zs, then the hidden
+ * adjoint and the two weight-gradient halves.  Outputs overwritten.  Needs
+ * VQMC_WS_BACKWARD_SAMPLED workspace. */
+int vqmc_backward_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, const float* Zs,
+                          const void* Rt, float* dP, float* db1, float* db2, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* Algorithm 1 as the paper runs it: n forward passes of the masked network over the
  * partially drawn batch, drawing site d after pass d (O(n^2 h) per sample).  Same
  * draws as vqmc_sample up to rounding.  Needs VQMC_WS_SAMPLE_PLAIN workspace. */
@@ -194,7 +219,10 @@ int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const 
 
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,
- * E, stats, coef and the gradient (dP, db1, db2). */
+ * E, stats, coef and the gradient (dP, db1, db2).  With algo 0 and a band this is
+ * vqmc_sample_fwd, then the energy and statistics on a library-owned auxiliary stream
+ * (default priority), then vqmc_backward_sampled; otherwise the gradient recomputes the
+ * forward pass as vqmc_logprob_backward does. */
 int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed,
               uint64_t step, int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E,
               vqmc_stats* stats, float* coef, float* dP, float* db1, float* db2, void* ws,

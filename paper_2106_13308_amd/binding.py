@@ -24,7 +24,7 @@ PAD = 64
 F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
-WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP = 0, 1, 2, 3
+WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED = 0, 1, 2, 3, 4
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
@@ -59,6 +59,10 @@ _SIGS = {
     "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "vqmc_band": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _vp]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
+    "vqmc_sample_fwd": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp, _vp,
+                                       _vp]),
+    "vqmc_backward_sampled": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _sz, _vp]),
     "vqmc_sample_plain": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp,
                                          _vp, _sz, _vp]),
     "vqmc_energy": (ctypes.c_int, [ctypes.POINTER(HamC), _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -279,6 +283,39 @@ def stats_to_dict(st: torch.Tensor) -> dict:
     raw = st.cpu().numpy().tobytes()
     s = StatsC.from_buffer_copy(raw)
     return {"mean": s.mean_E, "var": s.var_E, "min": s.min_E, "argmin": int(s.argmin), "sum": s.sum_E}
+
+
+def sample_fwd(made: Made, B: int, seed: int, step: int, offset: int = 0, tag: int = TAG_TRAIN,
+               S: torch.Tensor | None = None, logp: torch.Tensor | None = None, Zs: torch.Tensor | None = None,
+               Rt: torch.Tensor | None = None):
+    """Pipelined sampling that also returns Zs (s_d z_d, B x ld(n)) and Rt (relu(A), h x ld(B))."""
+    dev = made.P.device
+    S = empty_spins(B, made.n, dev) if S is None else S
+    logp = torch.empty(B, dtype=torch.float32, device=dev) if logp is None else logp
+    Zs = torch.empty((B, ld(made.n)), dtype=torch.float32, device=dev) if Zs is None else Zs
+    if Rt is None:
+        Rt = torch.empty((made.h, ld(B)), dtype=torch.bfloat16 if made.wdtype == BF16 else torch.float32, device=dev)
+    m = made.cstruct()
+    _check("vqmc_sample_fwd", _lib.vqmc_sample_fwd(ctypes.byref(m), B, seed, step, offset, tag, _dev(S).data_ptr(),
+                                                   _dev(logp).data_ptr(), _dev(Zs).data_ptr(), _dev(Rt).data_ptr(),
+                                                   _stream()))
+    return S, logp, Zs, Rt
+
+
+def backward_sampled(made: Made, S: torch.Tensor, coef: torch.Tensor, Zs: torch.Tensor, Rt: torch.Tensor,
+                     B: int | None = None, ws: torch.Tensor | None = None):
+    """Gradient of sum_b coef_b log pi(s_b) from sample_fwd's Zs and Rt (no forward recompute)."""
+    B = S.shape[0] if B is None else B
+    dev = S.device
+    dP = torch.empty((made.n, made.h), dtype=torch.float32, device=dev)
+    db1 = torch.empty(made.h, dtype=torch.float32, device=dev)
+    db2 = torch.empty(made.n, dtype=torch.float32, device=dev)
+    ws = workspace(WS_BACKWARD_SAMPLED, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_backward_sampled", _lib.vqmc_backward_sampled(
+        ctypes.byref(m), _dev(S).data_ptr(), B, _dev(coef).data_ptr(), _dev(Zs).data_ptr(), _dev(Rt).data_ptr(),
+        dP.data_ptr(), db1.data_ptr(), db2.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return dP, db1, db2
 
 
 def logprob(made: Made, S: torch.Tensor, B: int | None = None, want_z: bool = False,

@@ -109,6 +109,8 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_BACKWARD: return logprob_ws_bytes(n, h, B, wdtype, true);
     case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
     case VQMC_WS_STEP: return step_pm_offset(n, h, B, wdtype) + mask_w2t_bytes(n, h);
+    case VQMC_WS_BACKWARD_SAMPLED:
+      return (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256) + mask_w2t_bytes(n, h);
     default: return 0;
   }
 }
@@ -173,6 +175,38 @@ int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int
   return hip_status(
       launch_sample_incremental(*m, B, seed, step, sample_offset, tag, S, logp, (hipStream_t)stream),
       "vqmc_sample");
+}
+
+int vqmc_sample_fwd(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
+                    uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1) return fail(VQMC_EINVAL, "B must be >= 1");
+  if (!S) return fail(VQMC_EINVAL, "S is NULL");
+  if ((uintptr_t)S & 7) return fail(VQMC_EINVAL, "S must be 8-byte aligned");
+  if (!m->band) return fail(VQMC_EINVAL, "vqmc_sample_fwd needs the band (vqmc_band)");
+  if ((uintptr_t)m->band & 15) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
+  if ((Zs && ((uintptr_t)Zs & 15)) || (Rt && ((uintptr_t)Rt & 15)))
+    return fail(VQMC_EINVAL, "Zs and Rt must be 16-byte aligned");
+  if (sample_offset < 0) return fail(VQMC_EINVAL, "sample_offset < 0");
+  if (!sample_pipe_supported(m->n, m->h))
+    return fail(VQMC_EINVAL, "h = %d too large for the pipelined sampler", m->h);
+  return hip_status(launch_sample_pipe(*m, B, seed, step, sample_offset, tag, S, logp, (hipStream_t)stream, Zs, Rt),
+                    "vqmc_sample_fwd");
+}
+
+int vqmc_backward_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, const float* Zs,
+                          const void* Rt, float* dP, float* db1, float* db2, void* ws, size_t ws_bytes,
+                          void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !coef || !Zs || !Rt || !dP || !db1 || !db2 || !ws)
+    return fail(VQMC_EINVAL, "bad backward arguments");
+  const size_t need = vqmc_workspace_bytes(VQMC_WS_BACKWARD_SAMPLED, m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  void* Pm = (uint8_t*)ws + round_up((int64_t)logprob_ws_bytes(m->n, m->h, B, m->wdtype, true), 256);
+  return hip_status(launch_backward_sampled(*m, S, B, coef, Zs, Rt, dP, db1, db2, ws, Pm, (hipStream_t)stream),
+                    "vqmc_backward_sampled");
 }
 
 int vqmc_sample_plain(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
@@ -284,7 +318,8 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
   if (fused) {
     if ((e = hipStreamWaitEvent(st, aux->stats_done, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
     void* Pm = (uint8_t*)ws + step_pm_offset(m->n, m->h, B, m->wdtype);
-    if ((e = launch_backward_sampled(*m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st)) != hipSuccess)
+    if ((e = launch_backward_sampled(*m, S, B, coef, Zs, backward_rt_slot(*m, B, ws), dP, db1, db2, ws, Pm, st)) !=
+        hipSuccess)
       return hip_status(e, "vqmc_step backward");
     return VQMC_OK;
   }

@@ -75,6 +75,15 @@ __device__ inline float sigmoid(float t) {
   return t >= 0.f ? r : e * r;
 }
 
+// ---------------------------------------------------------------- workgroup barrier
+// Barrier whose fences order LDS only: global loads a wave has in flight stay in flight
+// across it.  For kernels whose waves exchange data through LDS alone.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- wave reductions (wave64)
 #define VQMC_DPP(v, ctrl) \
   __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false))

@@ -820,12 +820,11 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
 // the workspace's Rt slot) and Zs (s_d z_d): the two forward products are not recomputed.
 template <typename T>
 static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                                     const float* Zs, float* dP, float* db1, float* db2, void* ws,
+                                     const float* Zs, const T* Rt, float* dP, float* db1, float* db2, void* ws,
                                      void* Pm, hipStream_t st) {
   const Geom g = geom(m.n, m.h, B);
   const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
   uint8_t* w = (uint8_t*)ws;
-  T* Rt = (T*)(w + L.Rt);
   T* G = (T*)(w + L.G);
   T* Gt = (T*)(w + L.Gt);
   T* St = (T*)(w + L.St);
@@ -859,10 +858,11 @@ void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws) {
 }
 
 hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, void* Pm,
-                                   hipStream_t st) {
-  if (m.wdtype == VQMC_BF16) return backward_sampled_t<bf16_t>(m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st);
-  return backward_sampled_t<float>(m, S, B, coef, Zs, dP, db1, db2, ws, Pm, st);
+                                   const float* Zs, const void* Rt, float* dP, float* db1, float* db2, void* ws,
+                                   void* Pm, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16)
+    return backward_sampled_t<bf16_t>(m, S, B, coef, Zs, (const bf16_t*)Rt, dP, db1, db2, ws, Pm, st);
+  return backward_sampled_t<float>(m, S, B, coef, Zs, (const float*)Rt, dP, db1, db2, ws, Pm, st);
 }
 
 template <typename T>

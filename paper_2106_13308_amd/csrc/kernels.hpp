@@ -50,8 +50,8 @@ hipError_t launch_backward(const vqmc_made& m, const int8_t* S, int64_t B, const
 // and Zs (s_d z_d, B x ld(n)); ws as for launch_backward
 void* backward_rt_slot(const vqmc_made& m, int64_t B, void* ws);
 hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* coef,
-                                   const float* Zs, float* dP, float* db1, float* db2, void* ws, void* Pm,
-                                   hipStream_t st);
+                                   const float* Zs, const void* Rt, float* dP, float* db1, float* db2, void* ws,
+                                   void* Pm, hipStream_t st);
 // gemm2.hip: BF16 backward products on the direct-to-LDS engine; Pm: h x ld(n) bf16 scratch
 size_t mask_w2t_bytes(int n, int h);
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Gt,

@@ -54,17 +54,24 @@ constexpr int SP_PDS = 4;          // band records in flight in the sweep
 constexpr float SP_SCALE = 0x1p100f;
 
 __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; }
+// row stride of the BF16 split planes: a multiple of 8 elements, so 8-unit reads are 16-byte aligned
+__host__ __device__ inline int sp_plda(int h) { return (int)round_up(h, 32) + 8; }
 
 constexpr int SP_NSW = 2;          // sweep waves (four samples each)
 constexpr int SP_NHW = 6;          // helper waves
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
-__host__ inline size_t sp_smem_bytes(int n, int h) {
+__host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
   const size_t st = (size_t)SP_MS * sp_lda(h) * 4;
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
   return st + 2 * SP_NHW * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
-         round_up((int64_t)(nb + 1) * 4, 16) /*fb*/;
+         round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? 3 * (size_t)SP_MS * sp_plda(h) * 2 : 0);
+}
+constexpr size_t SP_LDS_MAX = 160 * 1024;
+// BF16 weights keep the three-term split of every completed activation in LDS when it fits
+__host__ inline bool sp_planes(int n, int h, int wdtype) {
+  return wdtype == VQMC_BF16 && sp_smem_bytes(n, h, true) <= SP_LDS_MAX;
 }
 
 // Exact 3-term BF16 split of 8 floats by truncation: hi keeps the top 8 significant bits
@@ -120,7 +127,7 @@ struct SpRec {
   float ns;   // minus the sum of the W1 halves
 };
 
-template <typename WT>
+template <typename WT, bool PLANES>
 __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     const WT* __restrict__ P, const WT* __restrict__ Pt, const float* __restrict__ band, int64_t ldh,
     int64_t ldn, const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
@@ -137,7 +144,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
 
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index, uniform
   const int l16 = lane & 15, g4 = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
@@ -239,6 +247,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 
   // ---- prologue: state = b1, block 0's logits = b2, block 0's thresholds, block bounds
   int* fb = (int*)(sb + 2 * BLK);  // fb[b + 1] = f_b, fb[0] = 0
+  // the bounds are the same for every lane: read them into scalar registers so that all
+  // loop control and addressing derived from them stays scalar
+  auto fbs = [&](int i) { return __builtin_amdgcn_readfirstlane(fb[i]); };
+  // [3][8][PLDA] BF16: hi, mid, lo of relu(A) of every completed unit (PLANES only)
+  bf16_t* pl = (bf16_t*)((uint8_t*)fb + round_up((int64_t)(nb + 1) * 4, 16));
+  const int PLDA = sp_plda(h);
   for (int i = t; i < SP_MS * LDA; i += SP_THREADS) {
     const int k = i % LDA;
     st[i] = (k < h) ? b1[k] : 0.f;
@@ -272,7 +286,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
       const int d0 = SP_T * b, Tb = min(SP_T, n - d0);
-      const int fprev = fb[b], fcur = fb[b + 1];
+      const int fprev = fbs(b), fcur = fbs(b + 1);
       const int cur = b & 1;
       float zr[4], tz[4];
       {
@@ -323,6 +337,17 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
               zn[e] = fmaf(n2[e], rl, zn[e]);
             }
             arow[u] = a;
+            if constexpr (PLANES) {
+              // exact three-term split of relu(a) by truncation (see sp_split3)
+              const uint32_t x = __float_as_uint(rl);
+              const float r1 = rl - __uint_as_float(x & 0xFFFF0000u);
+              const uint32_t y = __float_as_uint(r1);
+              const float r2 = r1 - __uint_as_float(y & 0xFFFF0000u);
+              bf16_t* q = pl + ss * PLDA + u;
+              q[0] = (bf16_t)(x >> 16);
+              q[SP_MS * PLDA] = (bf16_t)(y >> 16);
+              q[2 * SP_MS * PLDA] = (bf16_t)(__float_as_uint(r2) >> 16);
+            }
           }
           // Every step reloads its slot, so the number of loads in flight is the same on
           // every path and each use waits only for its own slot.  A slot that was used
@@ -343,12 +368,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         const float ce = __builtin_amdgcn_fmed3f(fmaf(zr[e], SP_SCALE, tz[e]), 0.f, 1.f);
         const bool up = ce > 0.5f;
         word |= ((j < Tb) ? (up ? 0x01u : 0xFFu) : 0u) << (8 * e);
-        zsv[e] = up ? zr[e] : -zr[e];
+        zsv[e] = (j < Tb) ? (up ? zr[e] : -zr[e]) : 0.f;
         cp[e] = (j < Tb && up) ? 1.f : 0.f;
       }
       *(uint32_t*)(sb + cur * BLK + ss * SP_T + 4 * g) = word;
       *(float4*)(zs + cur * BLK + ss * SP_T + 4 * g) = make_float4(zsv[0], zsv[1], zsv[2], zsv[3]);
-      __syncthreads();
+      lds_barrier();
     }
   } else {
     // ================= helper waves
@@ -377,12 +402,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     // reloads its slot (a skipped slot reloads the item it holds), so the loads in flight
     // are the same on every path and each use waits only for its own fragment.
     auto cnt_u = [&](int bb) {
-      const int ub = fb[bb + 1] & ~15;
+      const int ub = fbs(bb + 1) & ~15;
       const int nut = (bb >= 1 && ub < h) ? (h - ub + 15) / 16 : 0;
       return (nut > hw) ? (nut - hw + SP_NHW - 1) / SP_NHW : 0;
     };
     auto cnt_z = [&](int bb) {
-      const int nzc = (bb + 1 < nb) ? (fb[bb] + KC - 1) / KC : 0;
+      const int nzc = (bb + 1 < nb) ? (fbs(bb) + KC - 1) / KC : 0;
       return (nzc > hw) ? (nzc - hw + SP_NHW - 1) / SP_NHW : 0;
     };
     struct Cur { int b, j; };
@@ -398,7 +423,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     };
     // fragment of an item (items past the last block load valid memory, never used)
     auto load_u = [&](typename F::U& f, Cur c) {
-      if (c.b < nb) fetch_u(f, SP_T * (c.b - 1), (fb[c.b + 1] & ~15) + 16 * (hw + SP_NHW * c.j));
+      if (c.b < nb) fetch_u(f, SP_T * (c.b - 1), (fbs(c.b + 1) & ~15) + 16 * (hw + SP_NHW * c.j));
       else fetch_u(f, 0, 0);
     };
     auto load_z = [&](typename F::Z& f, Cur c) {
@@ -410,6 +435,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     typename F::U fu[PDU];
     typename F::Z fz[PDZ];
     Cur du[PDU], dz[PDZ];  // item held by each slot
+    __syncthreads();       // the block bounds fb[] are written by every thread
     Cur cu{0, -1}, cz{0, -1};
     cu = next_u(cu);
     cz = next_z(cz);
@@ -426,11 +452,10 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       cz = next_z(cz);
     }
     int gu = 0, gz = 0;  // global index of the current block's first item of each kind
-    __syncthreads();
     for (int b = 0; b < nb; ++b) {
       const int d0 = SP_T * b;
       const bool has_next = b + 1 < nb;
-      const int fprev = fb[b], fcur = fb[b + 1];
+      const int fprev = fbs(b), fcur = fbs(b + 1);
       const int cur = b & 1, nxt = cur ^ 1;
       const int cntu = cnt_u(b), cntz = cnt_z(b);
 
@@ -446,16 +471,24 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         bf16x8_t sv[2];
         spin_operand(sb + nxt * BLK, sv);
         for (int gb = gu - gu % PDU; gb < gu + cntu; gb += PDU) {
+          // two tiles per step: their LDS -> MFMA -> LDS chains overlap
 #pragma unroll
-          for (int p = 0; p < PDU; ++p) {
+          for (int p = 0; p < PDU; p += 2) {
             const int g = gb + p;
-            if (g >= gu && g < gu + cntu) {
-              use_u(fu[p], (fcur & ~15) + 16 * (hw + SP_NHW * du[p].j), fcur, h, sv);
+            const bool in0 = g >= gu && g < gu + cntu, in1 = g + 1 >= gu && g + 1 < gu + cntu;
+            if (in0) use_u(fu[p], (fcur & ~15) + 16 * (hw + SP_NHW * du[p].j), fcur, h, sv);
+            if (in1) use_u(fu[p + 1], (fcur & ~15) + 16 * (hw + SP_NHW * du[p + 1].j), fcur, h, sv);
+            if (in0) {
               du[p] = cu;
+              cu = next_u(cu);
+            }
+            if (in1) {
+              du[p + 1] = cu;
               cu = next_u(cu);
             }
             __builtin_amdgcn_sched_barrier(0);
             load_u(fu[p], du[p]);
+            load_u(fu[p + 1], du[p + 1]);
           }
         }
         gu += cntu;
@@ -480,7 +513,35 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
               const int g = gb + p;
               if (g >= gz && g < gz + cntz) {
                 const int k0 = KC * (hw + SP_NHW * dz[p].j);
-                if constexpr (sizeof(WT) == 2) {
+                if constexpr (PLANES) {
+                  // the split of the complete units, from the planes the sweep wrote;
+                  // units >= fprev (only in the last chunk) are not complete: zero them
+                  uint4 xv[3] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+                  if (l16 < SP_MS) {
+                    const bf16_t* q = pl + l16 * PLDA + k0 + 8 * g4;
+#pragma unroll
+                    for (int c3 = 0; c3 < 3; ++c3) xv[c3] = *(const uint4*)(q + c3 * SP_MS * PLDA);
+                  }
+                  if (k0 + KC > fprev) {
+#pragma unroll
+                    for (int c3 = 0; c3 < 3; ++c3) {
+                      bf16_t* e16 = (bf16_t*)&xv[c3];
+#pragma unroll
+                      for (int e = 0; e < 8; ++e)
+                        if (k0 + 8 * g4 + e >= fprev) e16[e] = 0;
+                    }
+                  }
+                  const bf16x8_t xh = __builtin_bit_cast(bf16x8_t, xv[0]);
+                  const bf16x8_t xm = __builtin_bit_cast(bf16x8_t, xv[1]);
+                  const bf16x8_t xl = __builtin_bit_cast(bf16x8_t, xv[2]);
+#pragma unroll
+                  for (int tt = 0; tt < 4; ++tt) {
+                    const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
+                  }
+                } else if constexpr (sizeof(WT) == 2) {
                   float rr[8];
                   const float* srow = st + l16 * LDA + k0 + 8 * g4;
                   if (l16 < SP_MS) {
@@ -526,7 +587,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     // last block's spins and log pi, then the 16-lane log pi sum of each sample
     if (hw == 2 || hw == 3) {
@@ -616,30 +677,32 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
   return hipGetLastError();
 }
 
-bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h) <= 160 * 1024; }
+bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h, false) <= SP_LDS_MAX; }
 
-template <typename WT>
+template <typename WT, bool PLANES>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                 uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, int64_t ldB,
                                 hipStream_t st) {
-  const size_t smem = sp_smem_bytes(m.n, m.h);
-  hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT>,
+  const size_t smem = sp_smem_bytes(m.n, m.h, PLANES);
+  hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT, PLANES>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
-  sample_pipe_kernel<WT><<<grid, SP_THREADS, smem, st>>>((const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad),
-                                                  round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h, sp_lda(m.h), B,
-                                                  seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs,
-                                                  (WT*)Rt, ldB);
+  sample_pipe_kernel<WT, PLANES><<<grid, SP_THREADS, smem, st>>>(
+      (const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad), round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h,
+      sp_lda(m.h), B, seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs, (WT*)Rt, ldB);
   return hipGetLastError();
 }
 
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                               uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs, void* Rt) {
   const int64_t ldB = round_up(B, kPad);
-  if (m.wdtype == VQMC_BF16)
-    return launch_pipe_t<bf16_t>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
-  return launch_pipe_t<float>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
+  if (m.wdtype == VQMC_BF16) {
+    if (sp_planes(m.n, m.h, m.wdtype))
+      return launch_pipe_t<bf16_t, true>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
+    return launch_pipe_t<bf16_t, false>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
+  }
+  return launch_pipe_t<float, false>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
 }
 
 }  // namespace vqmc

@@ -206,7 +206,8 @@ def test_logprob_backward(n, h, B, wd):
 
 
 # ---------------------------------------------------------------- sampling
-SAMPLE_CASES = [(20, 40, 1024), (67, 33, 100), (500, 500, 4096), (200, 300, 257), (2, 1, 9), (10000, 1000, 2048)]
+SAMPLE_CASES = [(20, 40, 1024), (67, 33, 100), (500, 500, 4096), (200, 300, 257), (2, 1, 9), (1000, 2000, 96),
+                (10000, 1000, 2048)]
 
 
 @pytest.mark.parametrize("kernel", ["pipe", "blocked"])
@@ -487,3 +488,51 @@ def test_step_fused_equals_recompute(n, h, B, wd):
     # sampler's logits use the FP32 activations, so with BF16 the two differ at that level
     lp, lr = bufs.logp.cpu().numpy(), lp_ref.cpu().numpy()
     assert np.abs(lp - lr).max() <= (1e-4 if wd == "f32" else 2e-3) * np.abs(lr).max()
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(67, 33, 100), (300, 200, 70)])
+def test_sample_fwd_outputs(n, h, B, wd):
+    """vqmc_sample_fwd's byproducts: Zs = s_d z_d with z the oracle's logits on the drawn prefix,
+    Rt = relu(A) of the oracle's forward pass, and log pi = sum log sigma(Zs)."""
+    _banner(f"sample_fwd n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, _ = instance(n, h, seed=23, graph=None, scale=2.0)
+    M = build_made(p, wdtype)
+    S, lp, Zs, Rt = B_.sample_fwd(M, B, 3, 4)
+    S2, lp2 = B_.sample(M, B, 3, 4)
+    assert torch.equal(S, S2) and torch.equal(lp, lp2)
+    S_np = spins_np(S, n)
+    q = oracle_params(p, wdtype)
+    f, sc = logit_scale(q, S_np)
+    Zs_np = Zs.cpu().numpy().astype(np.float64)
+    assert (Zs_np[:, n:] == 0).all()
+    zref = S_np * f["Z"]
+    assert (np.abs(Zs_np[:, :n] - zref) <= 1e-5 * (sc["z"] + 1e-30) + 1e-6).all()
+    Rt_np = Rt.float().cpu().numpy().astype(np.float64)
+    assert (Rt_np[:, B:] == 0).all()
+    Rref = f["R"].T
+    rtol = 1e-5 if wd == "f32" else 2 ** -8
+    assert (np.abs(Rt_np[:, :B] - Rref) <= rtol * (sc["a"].T + np.abs(Rref)) + 1e-6).all()
+    lpz = torch.nn.functional.logsigmoid(Zs[:, :n].double()).sum(dim=1).cpu().numpy()
+    assert np.abs(lp.cpu().numpy() - lpz).max() <= 1e-4 * np.abs(lpz).max()
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+def test_backward_sampled_equals_step(wd):
+    """vqmc_backward_sampled on vqmc_sample_fwd's outputs reproduces vqmc_step's gradient."""
+    _banner(f"backward_sampled {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    n, h, B = 500, 400, 300
+    p, edges = instance(n, h, seed=29, graph="regular", deg=4, scale=2.0)
+    w = inputs.integer_weights(len(edges), 1, 5, 4)
+    M = build_made(p, wdtype)
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    bufs = B_.StepBuffers.allocate(M, H, B)
+    B_.step(M, H, B, 6, 8, bufs)
+    S, lp, Zs, Rt = B_.sample_fwd(M, B, 6, 8)
+    assert torch.equal(S, bufs.S)
+    dP, db1, db2 = B_.backward_sampled(M, S, bufs.coef, Zs, Rt)
+    torch.cuda.synchronize()
+    for got, ref in ((dP, bufs.dP), (db1, bufs.db1), (db2, bufs.db2)):
+        assert torch.equal(got, ref)
