@@ -150,32 +150,32 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
 
-  // ---- fragment loaders (indices clamped to valid memory, so that every path issues
-  // the same loads and each use waits only for its own fragment)
-  auto fetch_z = [&](typename F::Z& f, int dblk, int k0) {
+  // ---- fragment loaders.  One straight-line sequence of loads for every item (rows past
+  // the end clamp to the last row inside the 32-bit per-lane offset; those rows are never
+  // read back), so the count of loads in flight is the same on every path and each use
+  // waits only for its own fragment.
+  constexpr int ES = sizeof(WT);
+  auto fetch_z = [&](typename F::Z& f, int dblk, int k0) {  // dblk <= n - 1
+    const uint8_t* base = (const uint8_t*)P + ((int64_t)dblk * ldh + k0) * ES;
+    const int lim = n - 1 - dblk;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
-      // rows past n load row n-1: their logits are never read back
-      const int d = min(dblk + 16 * tt + l16, n - 1);
-      if constexpr (sizeof(WT) == 2) {
-        f.a[tt] = *(const uint4*)((const bf16_t*)P + (int64_t)d * ldh + k0 + 8 * g4);
-      } else {
-        f.a[tt] = ((const float*)P)[(int64_t)d * ldh + k0 + g4];
-      }
+      const uint32_t off = (uint32_t)((min(16 * tt + l16, lim) * (int)ldh + (ES == 2 ? 8 * g4 : g4)) * ES);
+      if constexpr (ES == 2) f.a[tt] = *(const uint4*)(base + off);
+      else f.a[tt] = *(const float*)(base + off);
     }
   };
-  auto fetch_u = [&](typename F::U& f, int dblk, int k0) {
-    // rows past h load row h-1: those state rows are never written back
-    const int unit = min(k0 + l16, h - 1);
+  auto fetch_u = [&](typename F::U& f, int dblk, int k0) {  // k0 <= h - 1
+    const uint8_t* base = (const uint8_t*)Pt + ((int64_t)k0 * ldn + dblk) * ES;
+    const int r = min(l16, h - 1 - k0);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const int dd = dblk + 32 * ks + 8 * g4;  // dblk + 64 <= ldn (blocks are 64-aligned)
-      if constexpr (sizeof(WT) == 2) {
-        f.a[ks] = *(const uint4*)((const bf16_t*)Pt + (int64_t)unit * ldn + dd);
+      const uint32_t off = (uint32_t)((r * (int)ldn + 32 * ks + 8 * g4) * ES);  // dblk + 64 <= ldn
+      if constexpr (ES == 2) {
+        f.a[ks] = *(const uint4*)(base + off);
       } else {
-        const float* p = (const float*)Pt + (int64_t)unit * ldn + dd;
-        f.a[ks][0] = *(const uint4*)p;
-        f.a[ks][1] = *(const uint4*)(p + 4);
+        f.a[ks][0] = *(const uint4*)(base + off);
+        f.a[ks][1] = *(const uint4*)(base + off + 16);
       }
     }
   };
@@ -410,25 +410,35 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       const int nzc = (bb + 1 < nb) ? (fbs(bb) + KC - 1) / KC : 0;
       return (nzc > hw) ? (nzc - hw + SP_NHW - 1) / SP_NHW : 0;
     };
-    struct Cur { int b, j; };
+    // cursor: block, index in the block, the block's item count and (push) first tile
+    struct Cur { int b, j, cnt, base; };
     auto next_u = [&](Cur c) {
-      ++c.j;
-      while (c.b < nb && c.j >= cnt_u(c.b)) { ++c.b; c.j = 0; }
+      if (++c.j < c.cnt) return c;
+      c.j = 0;
+      do {
+        if (++c.b >= nb) return c;
+        c.cnt = cnt_u(c.b);
+      } while (c.cnt == 0);
+      c.base = fbs(c.b + 1) & ~15;
       return c;
     };
     auto next_z = [&](Cur c) {
-      ++c.j;
-      while (c.b < nb && c.j >= cnt_z(c.b)) { ++c.b; c.j = 0; }
+      if (++c.j < c.cnt) return c;
+      c.j = 0;
+      do {
+        if (++c.b >= nb) return c;
+        c.cnt = cnt_z(c.b);
+      } while (c.cnt == 0);
       return c;
     };
     // fragment of an item (items past the last block load valid memory, never used)
-    auto load_u = [&](typename F::U& f, Cur c) {
-      if (c.b < nb) fetch_u(f, SP_T * (c.b - 1), (fbs(c.b + 1) & ~15) + 16 * (hw + SP_NHW * c.j));
-      else fetch_u(f, 0, 0);
+    auto load_u = [&](typename F::U& f, const Cur& c) {
+      const bool v = c.b < nb;
+      fetch_u(f, v ? SP_T * (c.b - 1) : 0, v ? c.base + 16 * (hw + SP_NHW * c.j) : 0);
     };
-    auto load_z = [&](typename F::Z& f, Cur c) {
-      if (c.b < nb) fetch_z(f, SP_T * (c.b + 1), KC * (hw + SP_NHW * c.j));
-      else fetch_z(f, 0, 0);
+    auto load_z = [&](typename F::Z& f, const Cur& c) {
+      const bool v = c.b < nb;
+      fetch_z(f, v ? SP_T * (c.b + 1) : 0, v ? KC * (hw + SP_NHW * c.j) : 0);
     };
     constexpr int PDU = 4;
     constexpr int PDZ = (sizeof(WT) == 2) ? 4 : 8;
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     typename F::Z fz[PDZ];
     Cur du[PDU], dz[PDZ];  // item held by each slot
     __syncthreads();       // the block bounds fb[] are written by every thread
-    Cur cu{0, -1}, cz{0, -1};
+    Cur cu{-1, 0, 0, 0}, cz{-1, 0, 0, 0};
     cu = next_u(cu);
     cz = next_z(cz);
 #pragma unroll
@@ -496,14 +506,28 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       // block b+1's logits over the units complete before block b, [0, fprev) (the units of
       // block b are added by the sweep)
       if (has_next) {
-        const int d0n = d0 + SP_T, Tbn = min(SP_T, n - d0n);
+        const int d0n = d0 + SP_T;
+        // b2 of the block's sites 16hw..16hw+15 (helpers hw < 4) through scalar loads: they
+        // are waited for on the scalar/LDS counter, while a vector load here could be the
+        // youngest in flight on some path and make every later fragment wait drain all loads
+        typedef const __attribute__((address_space(4))) float cfloat;
+        const cfloat* b2c = (const cfloat*)b2;
+        const int r0 = d0n + 16 * hw;
+        float bq[16];
+        if (hw < 4 && r0 + 16 <= n) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) bq[i] = b2c[r0 + i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) bq[i] = (hw < 4 && r0 + i < n) ? b2c[min(r0 + i, n - 1)] : 0.f;
+        }
         floatx4_t acc[4];
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int j = 16 * tt + 4 * g4 + e;
-            acc[tt][e] = (hw == 0 && j < Tbn) ? b2[d0n + j] : 0.f;
+            const float v = (g4 == 0) ? bq[e] : (g4 == 1) ? bq[4 + e] : (g4 == 2) ? bq[8 + e] : bq[12 + e];
+            acc[tt][e] = (tt == hw) ? v : 0.f;
           }
         }
         if (cntz) {
