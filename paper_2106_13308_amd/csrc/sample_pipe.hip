@@ -62,11 +62,11 @@ constexpr int SP_NHW = 6;          // helper waves
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
 __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
-  const size_t st = (size_t)SP_MS * sp_lda(h) * 4;
+  const size_t st = (size_t)(SP_MS + 1) * sp_lda(h) * 4;   // + a spare row of zeros
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
   return st + 2 * SP_NHW * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
-         round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? 3 * (size_t)SP_MS * sp_plda(h) * 2 : 0);
+         round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? (3 * (size_t)SP_MS + 1) * sp_plda(h) * 2 : 0);
 }
 constexpr size_t SP_LDS_MAX = 160 * 1024;
 // BF16 weights keep the three-term split of every completed activation in LDS when it fits
@@ -118,6 +118,18 @@ struct SpFrag<float> {
   struct U { uint4 a[2][2]; };
 };
 
+// Raw buffer loads (range-checked: bytes at or past num_records read as zero).
+typedef __amdgpu_buffer_rsrc_t sp_rsrc_t;
+__device__ inline sp_rsrc_t sp_rsrc(const void* base, uint32_t off, uint32_t size) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((const uint8_t*)base + off), 0, (int)(size - off), 0x00020000);
+}
+__device__ inline uint4 sp_ld16(sp_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+}
+__device__ inline float sp_ld4(sp_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+
 // one band record of the sweep lane's 4 sites
 struct SpRec {
   float4 w1;  // 2 W1, this block
@@ -139,7 +151,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   constexpr int BLK = SP_MS * SP_T;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
-  float* red = st + SP_MS * LDA;   // [2][6][8][64] helpers' partial logits of a block (+ b2)
+                                   // row 8: zeros, the rows of the products' unused columns
+  float* red = st + (SP_MS + 1) * LDA;  // [2][6][8][64] helpers' partial logits of a block (+ b2)
   float* th = red + 2 * SP_NHW * BLK;  // [2][8][64] -logit(u) * 2^100
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
@@ -150,82 +163,6 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
 
-  // ---- fragment loaders.  One straight-line sequence of loads for every item (rows past
-  // the end clamp to the last row inside the 32-bit per-lane offset; those rows are never
-  // read back), so the count of loads in flight is the same on every path and each use
-  // waits only for its own fragment.
-  constexpr int ES = sizeof(WT);
-  auto fetch_z = [&](typename F::Z& f, int dblk, int k0) {  // dblk <= n - 1
-    const uint8_t* base = (const uint8_t*)P + ((int64_t)dblk * ldh + k0) * ES;
-    const int lim = n - 1 - dblk;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const uint32_t off = (uint32_t)((min(16 * tt + l16, lim) * (int)ldh + (ES == 2 ? 8 * g4 : g4)) * ES);
-      if constexpr (ES == 2) f.a[tt] = *(const uint4*)(base + off);
-      else f.a[tt] = *(const float*)(base + off);
-    }
-  };
-  auto fetch_u = [&](typename F::U& f, int dblk, int k0) {  // k0 <= h - 1
-    const uint8_t* base = (const uint8_t*)Pt + ((int64_t)k0 * ldn + dblk) * ES;
-    const int r = min(l16, h - 1 - k0);
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const uint32_t off = (uint32_t)((r * (int)ldn + 32 * ks + 8 * g4) * ES);  // dblk + 64 <= ldn
-      if constexpr (ES == 2) {
-        f.a[ks] = *(const uint4*)(base + off);
-      } else {
-        f.a[ks][0] = *(const uint4*)(base + off);
-        f.a[ks][1] = *(const uint4*)(base + off + 16);
-      }
-    }
-  };
-  // state rows (units) k0+4g..+3 of sample l16 += tile x block spins, rows outside [lo, hi) kept
-  auto use_u = [&](const typename F::U& f, int k0, int lo, int hi, const bf16x8_t (&sv)[2]) {
-    float* cp = st + l16 * LDA + k0 + 4 * g4;
-    floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
-    if (l16 < SP_MS) {
-      const float4 cur = *(const float4*)cp;
-      acc = (floatx4_t){cur.x, cur.y, cur.z, cur.w};
-    }
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      if constexpr (sizeof(WT) == 2) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, f.a[ks]), sv[ks], acc, 0, 0, 0);
-      } else {
-        const float4 w0 = __builtin_bit_cast(float4, f.a[ks][0]);
-        const float4 w1 = __builtin_bit_cast(float4, f.a[ks][1]);
-        const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-        bf16x8_t wh, wm, wl;
-        sp_split3(w, wh, wm, wl);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, sv[ks], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, sv[ks], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, sv[ks], acc, 0, 0, 0);
-      }
-    }
-    if (l16 < SP_MS) {
-      const int k = k0 + 4 * g4;
-      if (k >= lo && k + 3 < hi) {
-        *(float4*)cp = make_float4(acc[0], acc[1], acc[2], acc[3]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (k + e >= lo && k + e < hi) cp[e] = acc[e];
-      }
-    }
-  };
-  // spins of a swept block as the B operand of the push (+-1 / 0 in BF16), sample column l16
-  auto spin_operand = [&](const int8_t* sblk, bf16x8_t (&sv)[2]) {
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      uint2 raw = make_uint2(0, 0);
-      if (l16 < SP_MS) raw = *(const uint2*)(sblk + l16 * SP_T + 32 * ks + 8 * g4);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int8_t v = (int8_t)(((e < 4 ? raw.x : raw.y) >> (8 * (e & 3))) & 0xFF);
-        sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
-      }
-    }
-  };
   // -logit(u) * 2^100 for a block: thread tt < 128 draws sites 4(tt&15)..+3 of sample tt>>4
   auto thresholds = [&](int blk, float* dst, int tt) {
     const int s = tt >> 4, q4 = tt & 15;
@@ -250,12 +187,16 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   // the bounds are the same for every lane: read them into scalar registers so that all
   // loop control and addressing derived from them stays scalar
   auto fbs = [&](int i) { return __builtin_amdgcn_readfirstlane(fb[i]); };
-  // [3][8][PLDA] BF16: hi, mid, lo of relu(A) of every completed unit (PLANES only)
+  // [3][8][PLDA] BF16: hi, mid, lo of relu(A) of every completed unit, then a row of zeros
+  // (PLANES only)
   bf16_t* pl = (bf16_t*)((uint8_t*)fb + round_up((int64_t)(nb + 1) * 4, 16));
   const int PLDA = sp_plda(h);
-  for (int i = t; i < SP_MS * LDA; i += SP_THREADS) {
+  for (int i = t; i < (SP_MS + 1) * LDA; i += SP_THREADS) {
     const int k = i % LDA;
-    st[i] = (k < h) ? b1[k] : 0.f;
+    st[i] = (k < h && i < SP_MS * LDA) ? b1[k] : 0.f;
+  }
+  if constexpr (PLANES) {
+    for (int i = t; i < PLDA; i += SP_THREADS) pl[3 * SP_MS * PLDA + i] = 0;
   }
   for (int i = t; i < SP_NHW * BLK; i += SP_THREADS) {
     const int j = i % SP_T;
@@ -393,81 +334,152 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         if (dblk + 4 * q + e < n) lp_part += log_sigmoid(zv[e]);
       if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
     };
-    // This wave's work items: the push tiles of every block (block b: tiles hw, hw+6, ... of
-    // the units [f_b, h), block b-1's sites) and the logit chunks of every block (block b:
-    // K chunks hw, hw+6, ... of the units [0, f_{b-1}), block b+1's sites).  Their weight
-    // fragments do not depend on the draws, so each kind has a ring of fragments that runs
-    // ahead through the items of later blocks: slot g % PD holds item g when item g is
-    // used, and then takes item g + PD (a cursor over the item sequence).  Every step
-    // reloads its slot (a skipped slot reloads the item it holds), so the loads in flight
-    // are the same on every path and each use waits only for its own fragment.
-    auto cnt_u = [&](int bb) {
-      const int ub = fbs(bb + 1) & ~15;
-      const int nut = (bb >= 1 && ub < h) ? (h - ub + 15) / 16 : 0;
-      return (nut > hw) ? (nut - hw + SP_NHW - 1) / SP_NHW : 0;
-    };
-    auto cnt_z = [&](int bb) {
-      const int nzc = (bb + 1 < nb) ? (fbs(bb) + KC - 1) / KC : 0;
-      return (nzc > hw) ? (nzc - hw + SP_NHW - 1) / SP_NHW : 0;
-    };
-    // cursor: block, index in the block, the block's item count and (push) first tile
-    struct Cur { int b, j, cnt, base; };
-    auto next_u = [&](Cur c) {
-      if (++c.j < c.cnt) return c;
-      c.j = 0;
-      do {
-        if (++c.b >= nb) return c;
-        c.cnt = cnt_u(c.b);
-      } while (c.cnt == 0);
-      c.base = fbs(c.b + 1) & ~15;
+    // ---- work items.  Push tiles: block b pushes block b-1's spins into the 16-unit tiles
+    // hw, hw+6, ... of the units [f_b & ~15, h).  Logit chunks: block b adds the K chunks hw,
+    // hw+6, ... of the units [0, f_{b-1}) to block b+1's logits.  An item is (block, index);
+    // block nb marks "past the last item".  Their weight fragments do not depend on the
+    // draws, so each kind has a ring of PD slots that runs ahead through the items of later
+    // blocks: a slot holds one of the PD oldest items not yet used, and a used slot takes
+    // the next item of its cursor.  Each pass over a ring reloads every slot (an unused slot
+    // reloads the item it holds), so the loads in flight after any slot's load are the same
+    // on every path and each use waits for its own fragment only.
+    struct It { int bb, i; };
+    const int ntu = (h + 15) / 16;
+    auto next_u = [&](It c) {
+      c.i += SP_NHW;
+      while (c.i >= ntu) {
+        if (++c.bb >= nb) return It{nb, 0};
+        c.i = (fbs(c.bb + 1) >> 4) + hw;
+      }
       return c;
     };
-    auto next_z = [&](Cur c) {
-      if (++c.j < c.cnt) return c;
-      c.j = 0;
-      do {
-        if (++c.b >= nb) return c;
-        c.cnt = cnt_z(c.b);
-      } while (c.cnt == 0);
+    auto next_z = [&](It c, int& lim) {  // lim: chunk count of the cursor's block
+      c.i += SP_NHW;
+      while (c.i >= lim) {
+        if (++c.bb + 1 >= nb) return It{nb, 0};
+        lim = (fbs(c.bb) + KC - 1) / KC;
+        c.i = hw;
+      }
       return c;
     };
-    // fragment of an item (items past the last block load valid memory, never used)
-    auto load_u = [&](typename F::U& f, const Cur& c) {
-      const bool v = c.b < nb;
-      fetch_u(f, v ? SP_T * (c.b - 1) : 0, v ? c.base + 16 * (hw + SP_NHW * c.j) : 0);
+    // Fragments come through buffer loads: a resource per item whose base is the item's
+    // first element and whose size ends at the end of the matrix, so rows past the last
+    // site or unit read as zero, and the per-lane offsets are fixed.
+    constexpr int ES = sizeof(WT);
+    const uint32_t szP = (uint32_t)n * (uint32_t)ldh * ES, szPt = (uint32_t)h * (uint32_t)ldn * ES;
+    uint32_t voz[4], vou[2];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) voz[tt] = (uint32_t)(((16 * tt + l16) * (int)ldh + (ES == 2 ? 8 * g4 : g4)) * ES);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) vou[ks] = (uint32_t)((l16 * (int)ldn + 32 * ks + 8 * g4) * ES);
+    auto off_z = [&](It c) {  // P rows = block bb+1's sites, columns from unit KC i
+      return c.bb < nb ? ((uint32_t)(SP_T * (c.bb + 1)) * (uint32_t)ldh + (uint32_t)(KC * c.i)) * ES : 0u;
     };
-    auto load_z = [&](typename F::Z& f, const Cur& c) {
-      const bool v = c.b < nb;
-      fetch_z(f, v ? SP_T * (c.b + 1) : 0, v ? KC * (hw + SP_NHW * c.j) : 0);
+    auto off_u = [&](It c) {  // Pt rows = units 16 i.., columns from block bb-1's first site
+      return c.bb < nb ? ((uint32_t)(16 * c.i) * (uint32_t)ldn + (uint32_t)(SP_T * (c.bb - 1))) * ES : 0u;
     };
+    auto load_z = [&](typename F::Z& f, It c) {
+      const uint32_t o = off_z(c);
+      const sp_rsrc_t r = sp_rsrc(P, o, szP);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        if constexpr (ES == 2) f.a[tt] = sp_ld16(r, voz[tt]);
+        else f.a[tt] = sp_ld4(r, voz[tt]);
+      }
+    };
+    auto load_u = [&](typename F::U& f, It c) {
+      const uint32_t o = off_u(c);
+      const sp_rsrc_t r = sp_rsrc(Pt, o, szPt);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        if constexpr (ES == 2) {
+          f.a[ks] = sp_ld16(r, vou[ks]);
+        } else {
+          f.a[ks][0] = sp_ld16(r, vou[ks]);
+          f.a[ks][1] = sp_ld16(r, vou[ks] + 16);
+        }
+      }
+    };
+    // Products on 16x16 MFMA tiles whose columns are samples: columns 8-15 have no sample.
+    // In the push they multiply zero spins and read and write the zero row 8 of the state.
+    const int srow = (l16 < SP_MS) ? l16 : SP_MS;
+    float* const st_push = st + srow * LDA + 4 * g4;  // + k0: units k0+4g4..+3
+    // spins of block b-1 as the push's B operand (+-1 / 0 in BF16), sample column l16
+    auto spin_operand = [&](const int8_t* sblk, bf16x8_t (&sv)[2]) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        uint2 raw = make_uint2(0, 0);
+        if (l16 < SP_MS) raw = *(const uint2*)(sblk + l16 * SP_T + 32 * ks + 8 * g4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int8_t v = (int8_t)(((e < 4 ? raw.x : raw.y) >> (8 * (e & 3))) & 0xFF);
+          sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
+        }
+      }
+    };
+    // state rows k0+4g4..+3 += tile x block spins; rows below lo belong to the sweep
+    auto push_mfma = [&](const typename F::U& f, floatx4_t acc, const bf16x8_t (&sv)[2]) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        if constexpr (ES == 2) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, f.a[ks]), sv[ks], acc, 0, 0, 0);
+        } else {
+          const float4 w0 = __builtin_bit_cast(float4, f.a[ks][0]);
+          const float4 w1 = __builtin_bit_cast(float4, f.a[ks][1]);
+          const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          bf16x8_t wh, wm, wl;
+          sp_split3(w, wh, wm, wl);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, sv[ks], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, sv[ks], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, sv[ks], acc, 0, 0, 0);
+        }
+      }
+      return acc;
+    };
+    auto push_store = [&](float* cp, int k0, int lo, floatx4_t acc) {
+      if (k0 >= lo) {
+        *(float4*)cp = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      } else {  // the tile holding f_b: only the units from f_b on
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (k0 + 4 * g4 + e >= lo) cp[e] = acc[e];
+      }
+    };
+    // logits' B operand.  BF16 weights: each product pairs the three BF16 terms of the
+    // activations in one MFMA's 16 columns: columns 0-7 take hi (first product) and lo
+    // (second) of sample l16, columns 8-15 mid of sample l16-8 and zeros; the two halves
+    // are added when the block's partial logits are written.
+    const bf16_t* pl1 = pl + l16 * PLDA + 8 * g4;                              // [hi; mid]
+    const bf16_t* pl2 = pl + (l16 < SP_MS ? 2 * SP_MS + l16 : 3 * SP_MS) * PLDA + 8 * g4;  // [lo; 0]
+    const float* st_z = st + (ES == 2 ? (l16 & 7) : srow) * LDA + (ES == 2 ? 8 * g4 : g4);
+    const bool lowcol = l16 < SP_MS;
+
     constexpr int PDU = 4;
-    constexpr int PDZ = (sizeof(WT) == 2) ? 4 : 8;
+    constexpr int PDZ = (ES == 2) ? 4 : 8;
     typename F::U fu[PDU];
     typename F::Z fz[PDZ];
-    Cur du[PDU], dz[PDZ];  // item held by each slot
-    __syncthreads();       // the block bounds fb[] are written by every thread
-    Cur cu{-1, 0, 0, 0}, cz{-1, 0, 0, 0};
-    cu = next_u(cu);
-    cz = next_z(cz);
+    It su[PDU], sz[PDZ];  // item held by each slot
+    __syncthreads();      // the block bounds fb[] are written by every thread
+    int zlim = 0;
+    It cu = next_u(It{0, ntu});
+    It cz = next_z(It{-1, 0}, zlim);
 #pragma unroll
     for (int p = 0; p < PDU; ++p) {
-      du[p] = cu;
+      su[p] = cu;
       load_u(fu[p], cu);
       cu = next_u(cu);
     }
 #pragma unroll
     for (int p = 0; p < PDZ; ++p) {
-      dz[p] = cz;
+      sz[p] = cz;
       load_z(fz[p], cz);
-      cz = next_z(cz);
+      cz = next_z(cz, zlim);
     }
-    int gu = 0, gz = 0;  // global index of the current block's first item of each kind
     for (int b = 0; b < nb; ++b) {
       const int d0 = SP_T * b;
       const bool has_next = b + 1 < nb;
       const int fprev = fbs(b), fcur = fbs(b + 1);
-      const int cur = b & 1, nxt = cur ^ 1;
-      const int cntu = cnt_u(b), cntz = cnt_z(b);
+      const int nxt = (b & 1) ^ 1;
 
       // VALU work first: the ring's fragments for this block were issued a block ago
       if (hw < 2) {
@@ -477,32 +489,38 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       }
 
       // push of block b-1's spins into units [fcur, h)
-      if (cntu) {
+      auto any_u = [&]() {
+        bool a = false;
+#pragma unroll
+        for (int p = 0; p < PDU; ++p) a |= su[p].bb == b;
+        return a;
+      };
+      if (any_u()) {
         bf16x8_t sv[2];
         spin_operand(sb + nxt * BLK, sv);
-        for (int gb = gu - gu % PDU; gb < gu + cntu; gb += PDU) {
-          // two tiles per step: their LDS -> MFMA -> LDS chains overlap
+        do {
+          // the state of every slot's tile first (a slot of a later block reads rows no
+          // one writes during this block), then each used tile's product and store
+          floatx4_t cur[PDU];
 #pragma unroll
-          for (int p = 0; p < PDU; p += 2) {
-            const int g = gb + p;
-            const bool in0 = g >= gu && g < gu + cntu, in1 = g + 1 >= gu && g + 1 < gu + cntu;
-            if (in0) use_u(fu[p], (fcur & ~15) + 16 * (hw + SP_NHW * du[p].j), fcur, h, sv);
-            if (in1) use_u(fu[p + 1], (fcur & ~15) + 16 * (hw + SP_NHW * du[p + 1].j), fcur, h, sv);
-            if (in0) {
-              du[p] = cu;
-              cu = next_u(cu);
-            }
-            if (in1) {
-              du[p + 1] = cu;
+          for (int p = 0; p < PDU; ++p) {
+            const float4 v = *(const float4*)(st_push + 16 * su[p].i);
+            cur[p] = (floatx4_t){v.x, v.y, v.z, v.w};
+          }
+#pragma unroll
+          for (int p = 0; p < PDU; ++p) {
+            if (su[p].bb == b) {
+              const int k0 = 16 * su[p].i;
+              push_store(st_push + k0, k0, fcur, push_mfma(fu[p], cur[p], sv));
+              su[p] = cu;
               cu = next_u(cu);
             }
             __builtin_amdgcn_sched_barrier(0);
-            load_u(fu[p], du[p]);
-            load_u(fu[p + 1], du[p + 1]);
+            load_u(fu[p], su[p]);
           }
-        }
-        gu += cntu;
+        } while (any_u());
       }
+
       // block b+1's logits over the units complete before block b, [0, fprev) (the units of
       // block b are added by the sweep)
       if (has_next) {
@@ -527,84 +545,106 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float v = (g4 == 0) ? bq[e] : (g4 == 1) ? bq[4 + e] : (g4 == 2) ? bq[8 + e] : bq[12 + e];
-            acc[tt][e] = (tt == hw) ? v : 0.f;
+            acc[tt][e] = (tt == hw && lowcol) ? v : 0.f;
           }
         }
-        if (cntz) {
-          for (int gb = gz - gz % PDZ; gb < gz + cntz; gb += PDZ) {
+        auto any_z = [&]() {
+          bool a = false;
+#pragma unroll
+          for (int p = 0; p < PDZ; ++p) a |= sz[p].bb == b;
+          return a;
+        };
+        while (any_z()) {
+          if constexpr (PLANES) {
+            // every slot's activations first (units not complete yet are masked below)
+            uint4 x1[PDZ], x2[PDZ];
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
-              const int g = gb + p;
-              if (g >= gz && g < gz + cntz) {
-                const int k0 = KC * (hw + SP_NHW * dz[p].j);
-                if constexpr (PLANES) {
-                  // the split of the complete units, from the planes the sweep wrote;
-                  // units >= fprev (only in the last chunk) are not complete: zero them
-                  uint4 xv[3] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
-                  if (l16 < SP_MS) {
-                    const bf16_t* q = pl + l16 * PLDA + k0 + 8 * g4;
+              x1[p] = *(const uint4*)(pl1 + KC * sz[p].i);
+              x2[p] = *(const uint4*)(pl2 + KC * sz[p].i);
+            }
 #pragma unroll
-                    for (int c3 = 0; c3 < 3; ++c3) xv[c3] = *(const uint4*)(q + c3 * SP_MS * PLDA);
+            for (int p = 0; p < PDZ; ++p) {
+              if (sz[p].bb == b) {
+                const int k0 = KC * sz[p].i;
+                if (k0 + KC > fprev) {  // the chunk holding f_{b-1}: units from there are the sweep's
+                  bf16_t* e1 = (bf16_t*)&x1[p];
+                  bf16_t* e2 = (bf16_t*)&x2[p];
+#pragma unroll
+                  for (int e = 0; e < 8; ++e) {
+                    const bool keep = k0 + 8 * g4 + e < fprev;
+                    e1[e] = keep ? e1[e] : (bf16_t)0;
+                    e2[e] = keep ? e2[e] : (bf16_t)0;
                   }
-                  if (k0 + KC > fprev) {
-#pragma unroll
-                    for (int c3 = 0; c3 < 3; ++c3) {
-                      bf16_t* e16 = (bf16_t*)&xv[c3];
-#pragma unroll
-                      for (int e = 0; e < 8; ++e)
-                        if (k0 + 8 * g4 + e >= fprev) e16[e] = 0;
-                    }
-                  }
-                  const bf16x8_t xh = __builtin_bit_cast(bf16x8_t, xv[0]);
-                  const bf16x8_t xm = __builtin_bit_cast(bf16x8_t, xv[1]);
-                  const bf16x8_t xl = __builtin_bit_cast(bf16x8_t, xv[2]);
-#pragma unroll
-                  for (int tt = 0; tt < 4; ++tt) {
-                    const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
-                  }
-                } else if constexpr (sizeof(WT) == 2) {
-                  float rr[8];
-                  const float* srow = st + l16 * LDA + k0 + 8 * g4;
-                  if (l16 < SP_MS) {
-                    const float4 ra = *(const float4*)srow, rb = *(const float4*)(srow + 4);
-                    rr[0] = ra.x; rr[1] = ra.y; rr[2] = ra.z; rr[3] = ra.w;
-                    rr[4] = rb.x; rr[5] = rb.y; rr[6] = rb.z; rr[7] = rb.w;
-                  } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) rr[e] = 0.f;
-                  }
-#pragma unroll
-                  for (int e = 0; e < 8; ++e) rr[e] = (k0 + 8 * g4 + e < fprev) ? fmaxf(rr[e], 0.f) : 0.f;
-                  bf16x8_t xh, xm, xl;
-                  sp_split3(rr, xh, xm, xl);
-#pragma unroll
-                  for (int tt = 0; tt < 4; ++tt) {
-                    const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xh, acc[tt], 0, 0, 0);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xm, acc[tt], 0, 0, 0);
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xl, acc[tt], 0, 0, 0);
-                  }
-                } else {
-                  const int k = k0 + g4;
-                  const float rr = (l16 < SP_MS && k < fprev) ? fmaxf(st[l16 * LDA + k], 0.f) : 0.f;
-#pragma unroll
-                  for (int tt = 0; tt < 4; ++tt)
-                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fz[p].a[tt], rr, acc[tt], 0, 0, 0);
                 }
-                dz[p] = cz;
-                cz = next_z(cz);
+                const bf16x8_t xa = __builtin_bit_cast(bf16x8_t, x1[p]);
+                const bf16x8_t xb = __builtin_bit_cast(bf16x8_t, x2[p]);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                  const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xa, acc[tt], 0, 0, 0);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb, acc[tt], 0, 0, 0);
+                }
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
               }
               __builtin_amdgcn_sched_barrier(0);
-              load_z(fz[p], dz[p]);
+              load_z(fz[p], sz[p]);
+            }
+          } else if constexpr (ES == 2) {
+#pragma unroll
+            for (int p = 0; p < PDZ; ++p) {
+              if (sz[p].bb == b) {
+                const int k0 = KC * sz[p].i;
+                const float4 ra = *(const float4*)(st_z + k0), rb = *(const float4*)(st_z + k0 + 4);
+                float rr[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rr[e] = (k0 + 8 * g4 + e < fprev) ? fmaxf(rr[e], 0.f) : 0.f;
+                bf16x8_t xh, xm, xl;
+                sp_split3(rr, xh, xm, xl);
+                const uint4 uh = __builtin_bit_cast(uint4, xh), um = __builtin_bit_cast(uint4, xm),
+                            ul = __builtin_bit_cast(uint4, xl);
+                const uint4 u1 = lowcol ? uh : um;
+                const uint4 u2 = lowcol ? ul : make_uint4(0, 0, 0, 0);
+                const bf16x8_t xa = __builtin_bit_cast(bf16x8_t, u1);
+                const bf16x8_t xb = __builtin_bit_cast(bf16x8_t, u2);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                  const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xa, acc[tt], 0, 0, 0);
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb, acc[tt], 0, 0, 0);
+                }
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+              load_z(fz[p], sz[p]);
+            }
+          } else {
+#pragma unroll
+            for (int p = 0; p < PDZ; ++p) {
+              if (sz[p].bb == b) {
+                const int k0 = KC * sz[p].i;
+                const float rr = (k0 + g4 < fprev) ? fmaxf(st_z[k0], 0.f) : 0.f;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                  acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fz[p].a[tt], rr, acc[tt], 0, 0, 0);
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+              load_z(fz[p], sz[p]);
             }
           }
-          gz += cntz;
         }
-        // C layout: lane holds rows (sites) 16tt + 4g4 + e, column (sample) l16
-        if (l16 < SP_MS) {
+        // C layout: lane holds rows (sites) 16tt + 4g4 + e, column l16
+        if constexpr (ES == 2) {
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[tt][e] += VQMC_DPP(acc[tt][e], 0x128);  // row_ror:8
+        }
+        if (lowcol) {
           float* dst = red + nxt * SP_NHW * BLK + hw * BLK + l16 * SP_T + 4 * g4;
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
@@ -701,7 +741,12 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
   return hipGetLastError();
 }
 
-bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h, false) <= SP_LDS_MAX; }
+bool sample_pipe_supported(int n, int h) {
+  // fragments come through buffer loads with 32-bit offsets into P (n x ld(h)) and Pt (h x ld(n))
+  const int64_t lim = INT32_MAX;
+  return sp_smem_bytes(n, h, false) <= SP_LDS_MAX && (int64_t)n * round_up(h, kPad) * 4 <= lim &&
+         (int64_t)h * round_up(n, kPad) * 4 <= lim;
+}
 
 template <typename WT, bool PLANES>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
