@@ -63,9 +63,9 @@ typedef enum {
  *   P  : n rows x vqmc_ld(h) columns, dtype wdtype, zero padding.
  *   Pt : h rows x vqmc_ld(n) columns, the transpose of P (same values), zero padding.
  *   b1 : h floats (hidden bias), b2 : n floats (output bias), c : n int32 (see above).
- *   band (nullable): h records of VQMC_BAND_REC floats written by vqmc_band from P/Pt
- *   and c.  When present, vqmc_sample runs its pipelined kernel; it must be rebuilt
- *   whenever P changes. */
+ *   band (nullable): the pipelined sampler's tables, vqmc_band_bytes(n, h, wdtype) bytes
+ *   written by vqmc_band from P, Pt, b2 and c.  When present, vqmc_sample runs its
+ *   pipelined kernel; it must be rebuilt whenever P or b2 changes. */
 #define VQMC_BAND_REC 260
 typedef struct {
   int32_t n, h;
@@ -138,6 +138,10 @@ int vqmc_unpack(int32_t n, int32_t h, const float* P32, const int32_t* c, float*
 int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt,
               void* stream);
 
+/* Size in bytes of the pipelined sampler's tables (the band) for n sites, h hidden units
+ * and weights of type wdtype (VQMC_F32 or VQMC_BF16); 0 for invalid arguments. */
+size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype);
+
 /* The sampler's per-unit band (Algorithm 1, incremental form; the MADE masks of Sec. 2.3
  * split each unit's weights by site).  Unit k completes inside the 64-site block
  * [64q, 64q + 64), q = floor(m(k) / 64) (0-based block of site m(k)).  Its record holds,
@@ -147,9 +151,21 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
  *   rec[128 + j] = 2 W1[k][d], d = 64(q-1) + j  (every site of the block before feeds k)
  *   rec[192 + j] = W2[d][k],   d = 64(q+1) + j  (k feeds every site of the block after)
  *   rec[256..259] = -(sum of the W1 entries above, halved back), four copies
- * with the values of P in its working precision, widened to float.  band: h *
- * VQMC_BAND_REC floats (device, 16-byte aligned), overwritten.  Needs m->Pt and m->c;
- * m->band is ignored. */
+ * with the values of P in its working precision, widened to float.  After the h records
+ * (from byte offset round_up(4 * VQMC_BAND_REC * h, 256)) come the weights of the two
+ * products of eq. (2.3) that the sampler's helper waves run, reordered so that each
+ * fragment an MFMA lane group reads is one contiguous 1 KB row, zero past site n and unit h
+ * (nb = ceil(n / 64) site blocks q, K = 32 units for BF16 and 4 for F32):
+ *   logit tiles, nb x (1 + ceil(h / K)) tiles: tile 0 of block q holds b2 of sites 64q..+63
+ *     (BF16: the exact split b2 = hi + mid + lo into BF16 terms in units 0-2; F32: b2 in
+ *     unit 0), tile t >= 1 the second-layer weights P[64q + i][K (t-1) + u];
+ *     BF16 [4][64 lanes][8 units], lane = 16 (u / 8) + i % 16, site i = 16 x first index
+ *     + lane % 16; F32 [4][64 lanes] with u = lane / 16.
+ *   push tiles, nb x ceil(h / 16) tiles: tile t of block q holds P[64q + d][16t + u] (the
+ *     first-layer weights from the block's sites), [2 halves][64 lanes][8 sites], lane =
+ *     16 g + u, sites 32 half + 8 g .. + 7.
+ * band: vqmc_band_bytes(n, h, m->wdtype) bytes (device, 16-byte aligned), overwritten.
+ * Needs m->P, m->Pt, m->b2 and m->c; m->band is ignored. */
 int vqmc_band(const vqmc_made* m, float* band, void* stream);
 
 /* ------------------------------------------------------------------ the hot path */

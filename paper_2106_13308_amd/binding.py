@@ -58,6 +58,7 @@ _SIGS = {
     "vqmc_unpack": (ctypes.c_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "vqmc_band": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _vp]),
+    "vqmc_band_bytes": (ctypes.c_size_t, [_i32, _i32, _i32]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
     "vqmc_sample_fwd": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp, _vp,
                                        _vp]),
@@ -131,7 +132,8 @@ class Made:
         tdt = torch.bfloat16 if wdtype == BF16 else torch.float32
         self.P = torch.zeros((self.n, ld(self.h)), dtype=tdt, device=dev)
         self.Pt = torch.zeros((self.h, ld(self.n)), dtype=tdt, device=dev)
-        self.band = torch.zeros((self.h, BAND_REC), dtype=torch.float32, device=dev) if band else None
+        nbytes = int(_lib.vqmc_band_bytes(self.n, self.h, self.wdtype)) if band else 0
+        self.band = torch.zeros(nbytes // 4, dtype=torch.float32, device=dev) if band else None
         self.refresh()
 
     @classmethod

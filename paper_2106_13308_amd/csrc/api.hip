@@ -154,6 +154,11 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
   return hip_status(launch_cast(n, h, P32, dtype, P, Pt, (hipStream_t)stream), "vqmc_cast");
 }
 
+size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype) {
+  if (n < 2 || h < 1 || (wdtype != VQMC_F32 && wdtype != VQMC_BF16)) return 0;
+  return sample_tables_bytes(n, h, wdtype);
+}
+
 int vqmc_band(const vqmc_made* m, float* band, void* stream) {
   int r = check_made(m, true);
   if (r) return r;

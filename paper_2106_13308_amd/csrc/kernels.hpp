@@ -29,6 +29,7 @@ bool sample_blocked_supported(int n, int h);
 hipError_t launch_sample_blocked(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                  uint32_t tag, int8_t* S, float* logp, hipStream_t st);
 bool sample_pipe_supported(int n, int h);
+size_t sample_tables_bytes(int n, int h, int wdtype);
 // Zs (nullable): B x ld(n) floats s_d z_d; Rt (nullable): h x ld(B) relu(A) in the weight dtype
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                               uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs = nullptr,

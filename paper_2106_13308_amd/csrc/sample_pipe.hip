@@ -74,6 +74,36 @@ __host__ inline bool sp_planes(int n, int h, int wdtype) {
   return wdtype == VQMC_BF16 && sp_smem_bytes(n, h, true) <= SP_LDS_MAX;
 }
 
+// The sampler's tables (the band buffer): the h unit records of the sweep, then the
+// weight fragments of the helpers' products laid out in the order the MFMA lanes read
+// them, so that every fragment load is one contiguous 1 KB row per instruction.
+//  logit tiles: for every 64-site block q, NZT = 1 + ceil(h / KC) tiles.  Tile 0 holds b2
+//    of the block (BF16: hi, mid, lo of its exact three-term split in units 0-2; FP32: b2
+//    in unit 0), tile t >= 1 the weights P[64q + site][KC (t-1) + unit] (zero past n).
+//    BF16: [4 site tiles][64 lanes][8 units], lane = (unit group g, site i) = 16 g + i.
+//    FP32: [4 site tiles][64 lanes] floats, unit = lane / 16.
+//  push tiles: for every 64-site block q, NUT = ceil(h / 16) tiles; tile t holds
+//    P[64q + site][16 t + unit] (zero past n and h), [2 site halves][64 lanes][8 sites]
+//    with lane = 16 g + unit and sites 32 half + 8 g .. + 7.
+struct SpTables {
+  int64_t z, u, bytes;  // byte offsets of the logit and push tiles, total size
+  int nzt, nut, zt, ut;  // tiles per block and bytes per tile
+};
+__host__ __device__ inline SpTables sp_tables(int n, int h, int wdtype) {
+  SpTables t;
+  const int nb = (n + SP_T - 1) / SP_T;
+  const bool bf = wdtype == VQMC_BF16;
+  const int kc = bf ? 32 : 4;
+  t.nzt = 1 + (h + kc - 1) / kc;
+  t.nut = (h + 15) / 16;
+  t.zt = bf ? 4096 : 1024;
+  t.ut = bf ? 2048 : 4096;
+  t.z = round_up((int64_t)h * VQMC_BAND_REC * 4, 256);
+  t.u = t.z + (int64_t)nb * t.nzt * t.zt;
+  t.bytes = t.u + (int64_t)nb * t.nut * t.ut;
+  return t;
+}
+
 // Exact 3-term BF16 split of 8 floats by truncation: hi keeps the top 8 significant bits
 // of x, mid the top 8 of the exact remainder x - hi, and lo = x - hi - mid has at most 8
 // significant bits left, so hi + mid + lo = x with every term a BF16 value (normal range).
@@ -118,15 +148,16 @@ struct SpFrag<float> {
   struct U { uint4 a[2][2]; };
 };
 
-// Raw buffer loads (range-checked: bytes at or past num_records read as zero).
+// Raw buffer loads of one table tile: base and size in scalar registers, lane offset in a
+// vector register.
 typedef __amdgpu_buffer_rsrc_t sp_rsrc_t;
-__device__ inline sp_rsrc_t sp_rsrc(const void* base, uint32_t off, uint32_t size) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)((const uint8_t*)base + off), 0, (int)(size - off), 0x00020000);
+__device__ inline sp_rsrc_t sp_rsrc(const uint8_t* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, bytes, 0x00020000);
 }
-__device__ inline uint4 sp_ld16(sp_rsrc_t r, uint32_t voff) {
+__device__ inline uint4 sp_ld16(sp_rsrc_t r, int voff) {
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
 }
-__device__ inline float sp_ld4(sp_rsrc_t r, uint32_t voff) {
+__device__ inline float sp_ld4(sp_rsrc_t r, int voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
 
@@ -141,8 +172,9 @@ struct SpRec {
 
 template <typename WT, bool PLANES>
 __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
-    const WT* __restrict__ P, const WT* __restrict__ Pt, const float* __restrict__ band, int64_t ldh,
-    int64_t ldn, const float* __restrict__ b1, const float* __restrict__ b2, const int32_t* __restrict__ c,
+    const uint8_t* __restrict__ ztab, const uint8_t* __restrict__ utab, int nzt, int nut,
+    const float* __restrict__ band, const float* __restrict__ b1, const float* __restrict__ b2,
+    const int32_t* __restrict__ c,
     int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
     int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp, float* __restrict__ Zs, WT* __restrict__ Rt,
     int64_t ldB) {
@@ -335,8 +367,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
     };
     // ---- work items.  Push tiles: block b pushes block b-1's spins into the 16-unit tiles
-    // hw, hw+6, ... of the units [f_b & ~15, h).  Logit chunks: block b adds the K chunks hw,
-    // hw+6, ... of the units [0, f_{b-1}) to block b+1's logits.  An item is (block, index);
+    // hw, hw+6, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles hw, hw+6,
+    // ... of block b+1 to its logits: tile 0 is b2, tile t >= 1 the K chunk t-1 of the units
+    // [0, f_{b-1}).  An item is (block, index);
     // block nb marks "past the last item".  Their weight fragments do not depend on the
     // draws, so each kind has a ring of PD slots that runs ahead through the items of later
     // blocks: a slot holds one of the PD oldest items not yet used, and a used slot takes
@@ -357,46 +390,33 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       c.i += SP_NHW;
       while (c.i >= lim) {
         if (++c.bb + 1 >= nb) return It{nb, 0};
-        lim = (fbs(c.bb) + KC - 1) / KC;
+        lim = 1 + (fbs(c.bb) + KC - 1) / KC;  // the bias tile and the chunks of [0, f_{bb-1})
         c.i = hw;
       }
       return c;
     };
-    // Fragments come through buffer loads: a resource per item whose base is the item's
-    // first element and whose size ends at the end of the matrix, so rows past the last
-    // site or unit read as zero, and the per-lane offsets are fixed.
+    // Fragments come from the tables: one contiguous row of 64 lanes per load, zeros baked
+    // in past the last site and unit.
     constexpr int ES = sizeof(WT);
-    const uint32_t szP = (uint32_t)n * (uint32_t)ldh * ES, szPt = (uint32_t)h * (uint32_t)ldn * ES;
-    uint32_t voz[4], vou[2];
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) voz[tt] = (uint32_t)(((16 * tt + l16) * (int)ldh + (ES == 2 ? 8 * g4 : g4)) * ES);
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) vou[ks] = (uint32_t)((l16 * (int)ldn + 32 * ks + 8 * g4) * ES);
-    auto off_z = [&](It c) {  // P rows = block bb+1's sites, columns from unit KC i
-      return c.bb < nb ? ((uint32_t)(SP_T * (c.bb + 1)) * (uint32_t)ldh + (uint32_t)(KC * c.i)) * ES : 0u;
-    };
-    auto off_u = [&](It c) {  // Pt rows = units 16 i.., columns from block bb-1's first site
-      return c.bb < nb ? ((uint32_t)(16 * c.i) * (uint32_t)ldn + (uint32_t)(SP_T * (c.bb - 1))) * ES : 0u;
-    };
-    auto load_z = [&](typename F::Z& f, It c) {
-      const uint32_t o = off_z(c);
-      const sp_rsrc_t r = sp_rsrc(P, o, szP);
+    constexpr int ZT = (ES == 2) ? 4096 : 1024, UT = (ES == 2) ? 2048 : 4096;
+    // (buffer loads: the tile's address stays in scalar registers, the lane's offset is fixed)
+    auto load_z = [&](typename F::Z& f, It c) {  // logit tile i of block bb+1
+      const sp_rsrc_t r = sp_rsrc(ztab + (c.bb < nb ? ((int64_t)(c.bb + 1) * nzt + c.i) * ZT : 0), ZT);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
-        if constexpr (ES == 2) f.a[tt] = sp_ld16(r, voz[tt]);
-        else f.a[tt] = sp_ld4(r, voz[tt]);
+        if constexpr (ES == 2) f.a[tt] = sp_ld16(r, tt * 1024 + lane * 16);
+        else f.a[tt] = sp_ld4(r, tt * 256 + lane * 4);
       }
     };
-    auto load_u = [&](typename F::U& f, It c) {
-      const uint32_t o = off_u(c);
-      const sp_rsrc_t r = sp_rsrc(Pt, o, szPt);
+    auto load_u = [&](typename F::U& f, It c) {  // push tile i of block bb-1
+      const sp_rsrc_t r = sp_rsrc(utab + (c.bb < nb ? ((int64_t)(c.bb - 1) * nut + c.i) * UT : 0), UT);
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         if constexpr (ES == 2) {
-          f.a[ks] = sp_ld16(r, vou[ks]);
+          f.a[ks] = sp_ld16(r, ks * 1024 + lane * 16);
         } else {
-          f.a[ks][0] = sp_ld16(r, vou[ks]);
-          f.a[ks][1] = sp_ld16(r, vou[ks] + 16);
+          f.a[ks][0] = sp_ld16(r, ks * 2048 + lane * 32);
+          f.a[ks][1] = sp_ld16(r, ks * 2048 + lane * 32 + 16);
         }
       }
     };
@@ -453,6 +473,22 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     const bf16_t* pl2 = pl + (l16 < SP_MS ? 2 * SP_MS + l16 : 3 * SP_MS) * PLDA + 8 * g4;  // [lo; 0]
     const float* st_z = st + (ES == 2 ? (l16 & 7) : srow) * LDA + (ES == 2 ? 8 * g4 : g4);
     const bool lowcol = l16 < SP_MS;
+    // tile 0 (b2) times ones in its first units: BF16 units 0-2 hold hi, mid, lo of b2, whose
+    // sum is exact in the FP32 accumulator; FP32 unit 0 holds b2
+    auto bias_mfma = [&](const typename F::Z& f, floatx4_t (&acc)[4]) {
+      const bool on = g4 == 0 && lowcol;
+      if constexpr (ES == 2) {
+        const uint32_t o2 = on ? 0x3F803F80u : 0u, o1 = on ? 0x3F80u : 0u;
+        const bf16x8_t ones = __builtin_bit_cast(bf16x8_t, make_uint4(o2, o1, 0u, 0u));
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, f.a[tt]), ones, acc[tt], 0, 0, 0);
+      } else {
+        const float one = on ? 1.f : 0.f;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[tt], one, acc[tt], 0, 0, 0);
+      }
+    };
 
     constexpr int PDU = 4;
     constexpr int PDZ = (ES == 2) ? 4 : 8;
@@ -524,30 +560,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       // block b+1's logits over the units complete before block b, [0, fprev) (the units of
       // block b are added by the sweep)
       if (has_next) {
-        const int d0n = d0 + SP_T;
-        // b2 of the block's sites 16hw..16hw+15 (helpers hw < 4) through scalar loads: they
-        // are waited for on the scalar/LDS counter, while a vector load here could be the
-        // youngest in flight on some path and make every later fragment wait drain all loads
-        typedef const __attribute__((address_space(4))) float cfloat;
-        const cfloat* b2c = (const cfloat*)b2;
-        const int r0 = d0n + 16 * hw;
-        float bq[16];
-        if (hw < 4 && r0 + 16 <= n) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) bq[i] = b2c[r0 + i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) bq[i] = (hw < 4 && r0 + i < n) ? b2c[min(r0 + i, n - 1)] : 0.f;
-        }
         floatx4_t acc[4];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float v = (g4 == 0) ? bq[e] : (g4 == 1) ? bq[4 + e] : (g4 == 2) ? bq[8 + e] : bq[12 + e];
-            acc[tt][e] = (tt == hw && lowcol) ? v : 0.f;
-          }
-        }
+        for (int tt = 0; tt < 4; ++tt) acc[tt] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
         auto any_z = [&]() {
           bool a = false;
 #pragma unroll
@@ -560,13 +575,18 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             uint4 x1[PDZ], x2[PDZ];
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
-              x1[p] = *(const uint4*)(pl1 + KC * sz[p].i);
-              x2[p] = *(const uint4*)(pl2 + KC * sz[p].i);
+              const int kq = KC * max(sz[p].i - 1, 0);
+              x1[p] = *(const uint4*)(pl1 + kq);
+              x2[p] = *(const uint4*)(pl2 + kq);
             }
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
-              if (sz[p].bb == b) {
-                const int k0 = KC * sz[p].i;
+              if (sz[p].bb == b && sz[p].i == 0) {
+                bias_mfma(fz[p], acc);
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
+              } else if (sz[p].bb == b) {
+                const int k0 = KC * (sz[p].i - 1);
                 if (k0 + KC > fprev) {  // the chunk holding f_{b-1}: units from there are the sweep's
                   bf16_t* e1 = (bf16_t*)&x1[p];
                   bf16_t* e2 = (bf16_t*)&x2[p];
@@ -594,8 +614,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
           } else if constexpr (ES == 2) {
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
-              if (sz[p].bb == b) {
-                const int k0 = KC * sz[p].i;
+              if (sz[p].bb == b && sz[p].i == 0) {
+                bias_mfma(fz[p], acc);
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
+              } else if (sz[p].bb == b) {
+                const int k0 = KC * (sz[p].i - 1);
                 const float4 ra = *(const float4*)(st_z + k0), rb = *(const float4*)(st_z + k0 + 4);
                 float rr[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
@@ -623,8 +647,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
           } else {
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
-              if (sz[p].bb == b) {
-                const int k0 = KC * sz[p].i;
+              if (sz[p].bb == b && sz[p].i == 0) {
+                bias_mfma(fz[p], acc);
+                sz[p] = cz;
+                cz = next_z(cz, zlim);
+              } else if (sz[p].bb == b) {
+                const int k0 = KC * (sz[p].i - 1);
                 const float rr = (k0 + g4 < fprev) ? fmaxf(st_z[k0], 0.f) : 0.f;
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt)
@@ -731,6 +759,69 @@ __global__ __launch_bounds__(256) void band_kernel(const WT* __restrict__ Pt, in
 
 size_t band_floats(int h) { return (size_t)h * SP_REC; }
 
+
+// Logit tiles (layout: see SpTables), one thread per lane row of a site tile.
+template <typename WT>
+__global__ __launch_bounds__(256) void ztile_kernel(const WT* __restrict__ P, int64_t ldh, const float* __restrict__ b2,
+                                                    int n, int nb, int nzt, uint8_t* __restrict__ zt) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = (int)(gid & 63), tt = (int)((gid >> 6) & 3);
+  const int64_t tile = gid >> 8;  // q * nzt + t
+  if (tile >= (int64_t)nb * nzt) return;
+  const int q = (int)(tile / nzt), t = (int)(tile % nzt);
+  const int i = lane & 15, g = lane >> 4;
+  const int d = SP_T * q + 16 * tt + i;
+  if constexpr (sizeof(WT) == 2) {
+    uint32_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (d < n) {
+      if (t == 0) {
+        if (g == 0) {  // exact three-term split of b2 by truncation
+          const float x = b2[d];
+          const float hi = __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
+          const float r = x - hi;
+          const float mid = __uint_as_float(__float_as_uint(r) & 0xFFFF0000u);
+          const float lo = r - mid;
+          v[0] = __float_as_uint(hi) >> 16;
+          v[1] = __float_as_uint(mid) >> 16;
+          v[2] = __float_as_uint(lo) >> 16;
+        }
+      } else {
+        const WT* row = P + (int64_t)d * ldh + 32 * (t - 1) + 8 * g;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = row[e];
+      }
+    }
+    *(uint4*)(zt + tile * 4096 + tt * 1024 + lane * 16) =
+        make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+  } else {
+    float v = 0.f;
+    if (d < n) v = (t == 0) ? (g == 0 ? b2[d] : 0.f) : P[(int64_t)d * ldh + 4 * (t - 1) + g];
+    *(float*)(zt + tile * 1024 + tt * 256 + lane * 4) = v;
+  }
+}
+
+// Push tiles (layout: see SpTables), one thread per lane row of a site half.
+template <typename WT>
+__global__ __launch_bounds__(256) void utile_kernel(const WT* __restrict__ Pt, int64_t ldn, int h, int nb, int nut,
+                                                    uint8_t* __restrict__ ut) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = (int)(gid & 63), ks = (int)((gid >> 6) & 1);
+  const int64_t tile = gid >> 7;  // q * nut + t
+  if (tile >= (int64_t)nb * nut) return;
+  const int q = (int)(tile / nut), t = (int)(tile % nut);
+  const int k = 16 * t + (lane & 15), d0 = SP_T * q + 32 * ks + 8 * (lane >> 4);
+  WT v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (k < h) ? Pt[(int64_t)k * ldn + d0 + e] : (WT)0;
+  if constexpr (sizeof(WT) == 2) {
+    *(uint4*)(ut + tile * 2048 + ks * 1024 + lane * 16) = *(const uint4*)v;
+  } else {
+    uint8_t* o = ut + tile * 4096 + ks * 2048 + lane * 32;
+    *(uint4*)o = *(const uint4*)v;
+    *(uint4*)(o + 16) = *(const uint4*)(v + 4);
+  }
+}
+
 hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
   const unsigned grid = (unsigned)((m.h + 3) / 4);
   const int64_t ldn = round_up(m.n, kPad);
@@ -738,15 +829,27 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
     band_kernel<bf16_t><<<grid, 256, 0, st>>>((const bf16_t*)m.Pt, ldn, m.c, m.n, m.h, band);
   else
     band_kernel<float><<<grid, 256, 0, st>>>((const float*)m.Pt, ldn, m.c, m.n, m.h, band);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const SpTables tb = sp_tables(m.n, m.h, m.wdtype);
+  const int nb = (m.n + SP_T - 1) / SP_T;
+  const int64_t ldh = round_up(m.h, kPad);
+  uint8_t* tab = (uint8_t*)band;
+  const unsigned gz = (unsigned)(((int64_t)nb * tb.nzt * 256 + 255) / 256);
+  const unsigned gu = (unsigned)(((int64_t)nb * tb.nut * 128 + 255) / 256);
+  if (m.wdtype == VQMC_BF16) {
+    ztile_kernel<bf16_t><<<gz, 256, 0, st>>>((const bf16_t*)m.P, ldh, m.b2, m.n, nb, tb.nzt, tab + tb.z);
+    utile_kernel<bf16_t><<<gu, 256, 0, st>>>((const bf16_t*)m.Pt, ldn, m.h, nb, tb.nut, tab + tb.u);
+  } else {
+    ztile_kernel<float><<<gz, 256, 0, st>>>((const float*)m.P, ldh, m.b2, m.n, nb, tb.nzt, tab + tb.z);
+    utile_kernel<float><<<gu, 256, 0, st>>>((const float*)m.Pt, ldn, m.h, nb, tb.nut, tab + tb.u);
+  }
   return hipGetLastError();
 }
 
-bool sample_pipe_supported(int n, int h) {
-  // fragments come through buffer loads with 32-bit offsets into P (n x ld(h)) and Pt (h x ld(n))
-  const int64_t lim = INT32_MAX;
-  return sp_smem_bytes(n, h, false) <= SP_LDS_MAX && (int64_t)n * round_up(h, kPad) * 4 <= lim &&
-         (int64_t)h * round_up(n, kPad) * 4 <= lim;
-}
+bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h, false) <= SP_LDS_MAX; }
+
+size_t sample_tables_bytes(int n, int h, int wdtype) { return (size_t)sp_tables(n, h, wdtype).bytes; }
 
 template <typename WT, bool PLANES>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
@@ -757,8 +860,10 @@ static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, ui
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
+  const SpTables tb = sp_tables(m.n, m.h, m.wdtype);
+  const uint8_t* tab = (const uint8_t*)m.band;
   sample_pipe_kernel<WT, PLANES><<<grid, SP_THREADS, smem, st>>>(
-      (const WT*)m.P, (const WT*)m.Pt, m.band, round_up(m.h, kPad), round_up(m.n, kPad), m.b1, m.b2, m.c, m.n, m.h,
+      tab + tb.z, tab + tb.u, tb.nzt, tb.nut, m.band, m.b1, m.b2, m.c, m.n, m.h,
       sp_lda(m.h), B, seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs, (WT*)Rt, ldB);
   return hipGetLastError();
 }

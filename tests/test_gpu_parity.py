@@ -345,7 +345,7 @@ def test_band_layout():
     n, h = 150, 90
     p, _ = instance(n, h, seed=5, graph=None)
     M = build_made(p, B_.BF16)
-    band = M.band.cpu().numpy().astype(np.float64)
+    band = M.band.cpu().numpy()[:h * 260].reshape(h, 260).astype(np.float64)
     q = oracle_params(p, B_.BF16)
     M1, M2 = omade.masks(n, p["degrees"])
     W1 = M1 * np.asarray(q["W1"], np.float64)
@@ -368,6 +368,69 @@ def test_band_layout():
         assert np.array_equal(band[k, 128:192], 2 * p1), k
         assert np.array_equal(band[k, 192:256], n2), k
         assert np.allclose(band[k, 256:], -(w1.sum() + p1.sum()), rtol=1e-6, atol=1e-6), k
+
+
+@pytest.mark.parametrize("wd", ["bf16", "f32"])
+def test_sampler_tables(wd):
+    """The weight tiles after the band records, against P = W2 (masked) + W1^T (masked)
+    built from the oracle's masks, and the bias tile against b2."""
+    _banner(f"sampler tables {wd}")
+    n, h = 150, 90
+    dt = B_.BF16 if wd == "bf16" else B_.F32
+    p, _ = instance(n, h, seed=6, graph=None)
+    M = build_made(p, dt)
+    raw = M.band.cpu().numpy().view(np.uint8)
+    q = oracle_params(p, dt)
+    M1, M2 = omade.masks(n, p["degrees"])
+    P = M2 * np.asarray(q["W2"], np.float64) + (M1 * np.asarray(q["W1"], np.float64)).T  # n x h
+    nb = (n + 63) // 64
+    kc = 32 if wd == "bf16" else 4
+    nzt, nut = 1 + (h + kc - 1) // kc, (h + 15) // 16
+    zt, ut = (4096, 2048) if wd == "bf16" else (1024, 4096)
+    zoff = (h * 260 * 4 + 255) // 256 * 256
+    uoff = zoff + nb * nzt * zt
+    assert raw.size * 1 >= uoff + nb * nut * ut
+
+    def as_f64(b):
+        if wd == "bf16":
+            return (b.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        return b.view(np.float32).astype(np.float64)
+
+    Pp = np.zeros((64 * nb + 64, 64 * ((h + 63) // 64) + 64))
+    Pp[:n, :h] = P
+    lane = np.arange(64)
+    i, g = lane % 16, lane // 16
+    Z = as_f64(raw[zoff:uoff])
+    b2 = np.asarray(p["b2"], np.float32).astype(np.float64)
+    if wd == "bf16":
+        Z = Z.reshape(nb, nzt, 4, 64, 8)
+        for qb in range(nb):
+            for tt in range(4):
+                d = 64 * qb + 16 * tt + i
+                for t in range(1, nzt):
+                    k = 32 * (t - 1) + 8 * g[:, None] + np.arange(8)[None, :]
+                    assert np.array_equal(Z[qb, t, tt], Pp[d[:, None], k]), (qb, t, tt)
+                tile0 = Z[qb, 0, tt]
+                ok = d < n
+                assert np.array_equal(tile0[g > 0], np.zeros_like(tile0[g > 0]))
+                assert np.array_equal(tile0[:, 3:], np.zeros_like(tile0[:, 3:]))
+                s3 = tile0[(g == 0) & ok, 0] + tile0[(g == 0) & ok, 1] + tile0[(g == 0) & ok, 2]
+                assert np.array_equal(s3, b2[d[(g == 0) & ok]]), (qb, tt)
+    else:
+        Z = Z.reshape(nb, nzt, 4, 64)
+        for qb in range(nb):
+            for tt in range(4):
+                d = 64 * qb + 16 * tt + i
+                for t in range(1, nzt):
+                    assert np.array_equal(Z[qb, t, tt], Pp[d, 4 * (t - 1) + g]), (qb, t, tt)
+                exp0 = np.where((g == 0) & (d < n), b2[np.minimum(d, n - 1)], 0.0)
+                assert np.array_equal(Z[qb, 0, tt], exp0), (qb, tt)
+    U = as_f64(raw[uoff:uoff + nb * nut * ut]).reshape(nb, nut, 2, 64, 8)
+    for qb in range(nb):
+        for t in range(nut):
+            for ks in range(2):
+                d = 64 * qb + 32 * ks + 8 * g[:, None] + np.arange(8)[None, :]
+                assert np.array_equal(U[qb, t, ks], Pp[d, (16 * t + i)[:, None]]), (qb, t, ks)
 
 
 def test_sample_deterministic():
