@@ -29,6 +29,7 @@ int hip_status(hipError_t e, const char* where) {
 }
 
 constexpr int kMaxSamplerH = 4096;  // units held per thread: 16 x 256
+constexpr int kMaxEnergyCsrN = 160000;  // site bytes of the CSR energy kernel in one CU's LDS
 
 size_t step_energy_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
   const size_t bw = logprob_ws_bytes(n, h, B, wdtype, true);
@@ -237,7 +238,7 @@ static int check_ham(const vqmc_hamiltonian* H) {
   }
   if (H->kind != VQMC_H_CSR_INT && H->kind != VQMC_H_CSR_F32)
     return fail(VQMC_EINVAL, "unknown hamiltonian kind %d", H->kind);
-  if (H->n > 49152) return fail(VQMC_EINVAL, "CSR energy supports n <= 49152");
+  if (H->n > kMaxEnergyCsrN) return fail(VQMC_EINVAL, "CSR energy supports n <= %d", kMaxEnergyCsrN);
   if (!H->rowptr || (H->nnz > 0 && (!H->col || !H->w))) return fail(VQMC_EINVAL, "null CSR pointer");
   return VQMC_OK;
 }

@@ -12,43 +12,51 @@
 namespace vqmc {
 
 // ---------------------------------------------------------------- sparse (CSR upper)
-// One workgroup handles MSE samples: their spins are staged in LDS (int8, 16-byte global
-// loads issued together), and so is the row pointer (int32) when it fits.  Each thread walks
-// rows i = t, t + 256, ... four at a time: the edge loads of the four rows are issued
-// together, so one memory latency covers them (consecutive threads take consecutive rows,
-// so the loads coalesce).  Every edge adds w_ij s_i s_j for each staged sample.  Integer
-// weights accumulate exactly in int64; float weights in double (the products w * (+-1) are
-// exact).  A fixed thread -> row map and fixed-shape reductions make the result
-// deterministic.
+// One workgroup of 1024 threads handles EMSE samples.  Their spins are staged in LDS as
+// one byte per site (bit q = [s_q = +1]), so an edge costs one byte read for all samples,
+// and so is the row pointer (int32) when it fits.  Thread t walks rows i = t, t + 1024,
+// ..., two edges per step with their loads issued together.  Row i of the upper triangle
+// contributes
+//   s_iq sum_j w_ij s_jq = s_iq (2 Y_q - W_i),  Y_q = sum_j w_ij [s_jq = +1],  W_i = sum_j w_ij,
+// accumulated exactly in int64 (integer weights) or in double (float weights, whose sums
+// of exact terms only differ from the oracle's by summation order).  A fixed thread -> row
+// map and fixed-shape reductions make the result deterministic.
 constexpr int EMSE = 8;
+constexpr int EB_THREADS = 1024;
 template <typename WT, typename AT, bool RP_LDS>
-__global__ __launch_bounds__(256) void energy_csr_kernel(int n, int64_t lds, const int64_t* __restrict__ rowptr,
-                                                          const int32_t* __restrict__ col,
-                                                          const WT* __restrict__ w,
-                                                          const int8_t* __restrict__ S, int64_t B,
-                                                          int mse, int nst, AT* __restrict__ E) {
-  // mse rows of nst spins, then the row pointer (n + 1 int32, if staged), then scratch
-  extern __shared__ __attribute__((aligned(16))) int8_t sh[];
-  int32_t* rp = (int32_t*)(sh + mse * nst);
-  AT* red = (AT*)(sh + mse * nst + (RP_LDS ? round_up((int64_t)(n + 1) * 4, 16) : 0));
+__global__ __launch_bounds__(EB_THREADS) void energy_csr_bits_kernel(int n, int64_t lds,
+                                                                    const int64_t* __restrict__ rowptr,
+                                                                    const int32_t* __restrict__ col,
+                                                                    const WT* __restrict__ w,
+                                                                    const int8_t* __restrict__ S, int64_t B,
+                                                                    int nst, AT* __restrict__ E) {
+  // nst bytes of site bits, then the row pointer (n + 1 int32, if staged), then scratch
+  extern __shared__ __attribute__((aligned(16))) uint8_t shb[];
+  uint8_t* bits = shb;
+  int32_t* rp = (int32_t*)(shb + nst);
+  AT* red = (AT*)(shb + nst + (RP_LDS ? round_up((int64_t)(n + 1) * 4, 16) : 0));
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t b0 = (int64_t)blockIdx.x * mse;
-  const int nq = (int)min<int64_t>(mse, B - b0);
-  {
-    // nst = round_up(n, 16) <= lds: every 16-byte chunk lies inside the padded row
-    const int nch = nst / 16;
-    for (int c0 = t; c0 < nch; c0 += 256) {
-      uint4 v[EMSE];
+  const int64_t b0 = (int64_t)blockIdx.x * EMSE;
+  const int nq = (int)min<int64_t>(EMSE, B - b0);
+  // nst = round_up(n, 16) <= lds: every 16-byte chunk lies inside the padded row.  The
+  // spins are +1 = 0x01 and -1 = 0xFF: bit 7 of a byte is clear exactly for +1 (the row
+  // padding, 0, also reads +1 and is never referenced).
+  for (int c0 = t; c0 < nst / 16; c0 += EB_THREADS) {
+    uint32_t a[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int q = 0; q < EMSE; ++q)
-        v[q] = (q < nq) ? *(const uint4*)(S + (b0 + q) * lds + 16 * c0) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < EMSE; ++q)
-        if (q < mse) *(uint4*)(sh + q * nst + 16 * c0) = v[q];
+    for (int q = 0; q < EMSE; ++q) {
+      if (q < nq) {
+        const uint4 v = *(const uint4*)(S + (b0 + q) * lds + 16 * c0);
+        a[0] |= ((~v.x >> 7) & 0x01010101u) << q;
+        a[1] |= ((~v.y >> 7) & 0x01010101u) << q;
+        a[2] |= ((~v.z >> 7) & 0x01010101u) << q;
+        a[3] |= ((~v.w >> 7) & 0x01010101u) << q;
+      }
     }
-    if constexpr (RP_LDS)
-      for (int i = t; i <= n; i += 256) rp[i] = (int32_t)rowptr[i];
+    *(uint4*)(bits + 16 * c0) = make_uint4(a[0], a[1], a[2], a[3]);
   }
+  if constexpr (RP_LDS)
+    for (int i = t; i <= n; i += EB_THREADS) rp[i] = (int32_t)rowptr[i];
   __syncthreads();
   auto rowp = [&](int i) -> int64_t {
     if constexpr (RP_LDS) return rp[i];
@@ -57,61 +65,51 @@ __global__ __launch_bounds__(256) void energy_csr_kernel(int n, int64_t lds, con
   AT acc[EMSE];
 #pragma unroll
   for (int q = 0; q < EMSE; ++q) acc[q] = 0;
-  for (int i0 = t; i0 < n; i0 += 4 * 256) {
-    int64_t e0[4], e1[4];
-    int len = 0;
+  for (int i = t; i < n; i += EB_THREADS) {
+    const int64_t e0 = rowp(i), e1 = rowp(i + 1);
+    AT y[EMSE];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + 256 * r;
-      e0[r] = (i < n) ? rowp(i) : 0;
-      e1[r] = (i < n) ? rowp(i + 1) : 0;
-      len = max(len, (int)(e1[r] - e0[r]));
+    for (int q = 0; q < EMSE; ++q) y[q] = 0;
+    AT wsum = 0;
+    int64_t e = e0;
+    for (; e + 1 < e1; e += 2) {  // two edges per step: their loads are issued together
+      const int j0 = col[e], j1 = col[e + 1];
+      const AT w0 = (AT)w[e], w1 = (AT)w[e + 1];
+      const uint32_t m0 = bits[j0], m1 = bits[j1];
+      wsum += w0 + w1;
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q) y[q] += (((m0 >> q) & 1u) ? w0 : (AT)0) + (((m1 >> q) & 1u) ? w1 : (AT)0);
     }
-    AT row[4][EMSE];
+    if (e < e1) {
+      const AT w0 = (AT)w[e];
+      const uint32_t m0 = bits[col[e]];
+      wsum += w0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < EMSE; ++q) row[r][q] = 0;
-    for (int k = 0; k < len; k += 2) {
-      int jj[4][2];
-      AT ww[4][2];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int64_t e = e0[r] + k + u;
-          const bool ok = e < e1[r];
-          jj[r][u] = ok ? col[e] : 0;
-          ww[r][u] = ok ? (AT)w[e] : (AT)0;
-        }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int q = 0; q < EMSE; ++q)
-            if (q < mse) row[r][q] += (sh[q * nst + jj[r][u]] > 0) ? ww[r][u] : -ww[r][u];
+      for (int q = 0; q < EMSE; ++q) y[q] += ((m0 >> q) & 1u) ? w0 : (AT)0;
     }
+    const uint32_t mi = bits[i];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + 256 * r;
-      if (i < n) {
-#pragma unroll
-        for (int q = 0; q < EMSE; ++q)
-          if (q < mse) acc[q] += (sh[q * nst + i] > 0) ? row[r][q] : -row[r][q];
-      }
+    for (int q = 0; q < EMSE; ++q) {
+      const AT r = 2 * y[q] - wsum;
+      acc[q] += ((mi >> q) & 1u) ? r : -r;
     }
   }
-  // per sample: fixed butterfly over the wave, then the four waves in order
+  // per sample: fixed butterfly over the wave, then the sixteen waves in order
+  constexpr int NW = EB_THREADS / 64;
 #pragma unroll
   for (int q = 0; q < EMSE; ++q) {
     AT v = acc[q];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0 && q < mse) red[q * 4 + wv] = v;
+    if (lane == 0) red[q * NW + wv] = v;
   }
   __syncthreads();
-  if (t < nq) E[b0 + t] = (red[t * 4] + red[t * 4 + 1]) + (red[t * 4 + 2] + red[t * 4 + 3]);
+  if (t < nq) {
+    AT s = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[t * NW + k];
+    E[b0 + t] = s;
+  }
 }
 
 // ---------------------------------------------------------------- dense J (FP64)
@@ -236,25 +234,26 @@ hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, 
     return hipGetLastError();
   }
   const int nst = (int)round_up(n, 16);
-  const int mse = std::min(EMSE, std::max(1, 98304 / nst));
-  // the row pointer goes to LDS as int32 when it fits next to the spins
+  // site bytes and reduction scratch always in LDS; the row pointer too when two
+  // workgroups still fit on a CU
   const size_t rpb = (size_t)round_up((int64_t)(n + 1) * 4, 16);
-  const bool rp_lds = H.nnz < (int64_t)1 << 31 && (size_t)mse * nst + rpb + EMSE * 4 * 8 <= 160 * 1024;
-  const size_t shbytes = (size_t)mse * nst + (rp_lds ? rpb : 0) + EMSE * 4 * 8;
-  const unsigned grid = (unsigned)((B + mse - 1) / mse);
+  const size_t redb = (size_t)EMSE * (EB_THREADS / 64) * 8;
+  const bool rp_lds = H.nnz < (int64_t)1 << 31 && (size_t)nst + rpb + redb <= 64 * 1024;
+  const size_t shbytes = (size_t)nst + (rp_lds ? rpb : 0) + redb;
+  const unsigned grid = (unsigned)((B + EMSE - 1) / EMSE);
   hipError_t e;
   auto go = [&](auto kern, auto wptr, auto eptr) {
     e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shbytes);
     if (e != hipSuccess) return;
-    kern<<<grid, 256, shbytes, st>>>(n, lds, H.rowptr, H.col, wptr, S, B, mse, nst, eptr);
+    kern<<<grid, EB_THREADS, shbytes, st>>>(n, lds, H.rowptr, H.col, wptr, S, B, nst, eptr);
     e = hipGetLastError();
   };
   if (H.kind == VQMC_H_CSR_INT) {
-    if (rp_lds) go(energy_csr_kernel<int32_t, int64_t, true>, (const int32_t*)H.w, (int64_t*)E);
-    else go(energy_csr_kernel<int32_t, int64_t, false>, (const int32_t*)H.w, (int64_t*)E);
+    if (rp_lds) go(energy_csr_bits_kernel<int32_t, int64_t, true>, (const int32_t*)H.w, (int64_t*)E);
+    else go(energy_csr_bits_kernel<int32_t, int64_t, false>, (const int32_t*)H.w, (int64_t*)E);
   } else {
-    if (rp_lds) go(energy_csr_kernel<float, double, true>, (const float*)H.w, (double*)E);
-    else go(energy_csr_kernel<float, double, false>, (const float*)H.w, (double*)E);
+    if (rp_lds) go(energy_csr_bits_kernel<float, double, true>, (const float*)H.w, (double*)E);
+    else go(energy_csr_bits_kernel<float, double, false>, (const float*)H.w, (double*)E);
   }
   return e;
 }
