@@ -58,7 +58,7 @@ __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; 
 __host__ __device__ inline int sp_plda(int h) { return (int)round_up(h, 32) + 8; }
 
 constexpr int SP_NSW = 2;          // sweep waves (four samples each)
-constexpr int SP_NHW = 6;          // helper waves
+constexpr int SP_NHW = 10;         // helper waves
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
 __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
@@ -490,8 +490,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       }
     };
 
-    constexpr int PDU = 4;
-    constexpr int PDZ = (ES == 2) ? 4 : 8;
+    constexpr int PDU = 3;
+    constexpr int PDZ = (ES == 2) ? 3 : 6;
     typename F::U fu[PDU];
     typename F::Z fz[PDZ];
     It su[PDU], sz[PDZ];  // item held by each slot
@@ -571,16 +571,19 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         };
         while (any_z()) {
           if constexpr (PLANES) {
-            // every slot's activations first (units not complete yet are masked below)
-            uint4 x1[PDZ], x2[PDZ];
-#pragma unroll
-            for (int p = 0; p < PDZ; ++p) {
+            // each slot's activations are read one slot ahead (units not complete yet are
+            // masked below)
+            auto read_pl = [&](int p, uint4& a1, uint4& a2) {
               const int kq = KC * max(sz[p].i - 1, 0);
-              x1[p] = *(const uint4*)(pl1 + kq);
-              x2[p] = *(const uint4*)(pl2 + kq);
-            }
+              a1 = *(const uint4*)(pl1 + kq);
+              a2 = *(const uint4*)(pl2 + kq);
+            };
+            uint4 y1, y2;
+            read_pl(0, y1, y2);
 #pragma unroll
             for (int p = 0; p < PDZ; ++p) {
+              uint4 x1[1] = {y1}, x2[1] = {y2};
+              if (p + 1 < PDZ) read_pl(p + 1, y1, y2);
               if (sz[p].bb == b && sz[p].i == 0) {
                 bias_mfma(fz[p], acc);
                 sz[p] = cz;
@@ -588,8 +591,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
               } else if (sz[p].bb == b) {
                 const int k0 = KC * (sz[p].i - 1);
                 if (k0 + KC > fprev) {  // the chunk holding f_{b-1}: units from there are the sweep's
-                  bf16_t* e1 = (bf16_t*)&x1[p];
-                  bf16_t* e2 = (bf16_t*)&x2[p];
+                  bf16_t* e1 = (bf16_t*)&x1[0];
+                  bf16_t* e2 = (bf16_t*)&x2[0];
 #pragma unroll
                   for (int e = 0; e < 8; ++e) {
                     const bool keep = k0 + 8 * g4 + e < fprev;
@@ -597,8 +600,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
                     e2[e] = keep ? e2[e] : (bf16_t)0;
                   }
                 }
-                const bf16x8_t xa = __builtin_bit_cast(bf16x8_t, x1[p]);
-                const bf16x8_t xb = __builtin_bit_cast(bf16x8_t, x2[p]);
+                const bf16x8_t xa = __builtin_bit_cast(bf16x8_t, x1[0]);
+                const bf16x8_t xb = __builtin_bit_cast(bf16x8_t, x2[0]);
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt) {
                   const bf16x8_t w = __builtin_bit_cast(bf16x8_t, fz[p].a[tt]);
