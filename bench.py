@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Throughput of one VQMC optimisation step on one MI355X.
 
-A step is the whole hot path on one batch: incremental autoregressive sampling of B
-strings (Algorithm 1), the Max-Cut local energy, FP64 batch statistics, and the
-score-function gradient through the masked network (log p forward recomputation plus
-the backward), i.e. one ``vqmc_step`` call.  The Adam update is outside the step.
+A step is the whole hot path on one batch, as one training iteration runs it after an
+optimiser update: the working-precision weights and the sampler's tables re-derived
+from the FP32 master weights (``vqmc_cast`` + ``vqmc_band``), incremental
+autoregressive sampling of B strings (Algorithm 1), the Max-Cut local energy, FP64 batch
+statistics, and the score-function gradient through the masked network, i.e. one
+``vqmc_step`` call.  The Adam update itself (torch) is outside the step.
 
 Workload (default): Max-Cut on a seeded random 10-regular graph with n = 10000 vertices
 and integer weights in {1..5} (CSR), MADE with h = 1000 hidden units in BF16 weights,
@@ -84,12 +86,14 @@ def time_steps(made, H, B_, steps, warmup, algo=0, seed=2):
     from paper_2106_13308_amd import binding as B
     bufs = B.StepBuffers.allocate(made, H, B_)
     for i in range(warmup):
+        made.refresh()
         B.step(made, H, B_, seed, i, bufs, algo=algo)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
     for i in range(steps):
+        made.refresh()
         B.step(made, H, B_, seed, warmup + i, bufs, algo=algo)
     ev1.record()
     torch.cuda.synchronize()
@@ -104,7 +108,7 @@ def time_calls(made, H, B_, reps=10, seed=2):
     bufs = B.StepBuffers.allocate(made, H, B_)
     B.step(made, H, B_, seed, 0, bufs)
     ws_bw = B.workspace(B.WS_BACKWARD, made, B_)
-    calls = {}
+    calls = {"refresh": made.refresh}
     if made.band is not None:
         # the calls vqmc_step makes: sampling with the forward byproducts, energy, statistics,
         # and the backward from those byproducts
@@ -310,7 +314,7 @@ def main():
             d["gbs"] = wk["bytes"] / (t / 1e3) / 1e9
         kernels[name] = d
     grad_call = "backward_sampled" if "backward_sampled" in calls else "logprob_backward"
-    step_calls = {k: calls[k] for k in ("sample", "energy", "stats", grad_call)}
+    step_calls = {k: calls[k] for k in ("refresh", "sample", "energy", "stats", grad_call)}
     dom = max(step_calls, key=step_calls.get)
     roof = roofline(dom, kernels, made, H, w.name)
     forms = {"bf16_incremental": {"ms_per_step": ms, "samples_per_s": value}}

@@ -678,13 +678,23 @@ __global__ __launch_bounds__(256) void grad_out_kernel(const float* __restrict__
 }
 
 // ---------------------------------------------------------------- reductions
+// out[i] = sum_p part[p][i]; the loads of eight parts are issued together and summed in
+// a fixed order (four running sums, then ((s0 + s1) + (s2 + s3))).
 __global__ void sum_rows_kernel(const float* __restrict__ part, int nparts, int64_t stride, int64_t len,
                                 float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
-  float s = 0.f;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * stride + i];
-  out[i] = s;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  int p = 0;
+  for (; p + 8 <= nparts; p += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(p + u) * stride + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u & 3] += v[u];
+  }
+  for (; p < nparts; ++p) s[p & 3] += part[(int64_t)p * stride + i];
+  out[i] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 __global__ void fill_kernel(float* __restrict__ x, int64_t len, float v) {

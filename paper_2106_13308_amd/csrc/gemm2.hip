@@ -141,16 +141,24 @@ struct G2 {
 __global__ __launch_bounds__(256) void mask_w2t_kernel(const bf16_t* __restrict__ Pt, int64_t ldn,
                                                         const int32_t* __restrict__ c, int n, int h,
                                                         bf16_t* __restrict__ Pm) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // one 8-element vector
-  const int64_t nv = ldn / 8;
-  if (i >= (int64_t)h * nv) return;
-  const int k = (int)(i / nv);
-  const int d0 = (int)(i % nv) * 8;
+  // block (x, k): row k, eight-element vectors 256x .. 256x + 255
+  const int k = blockIdx.y;
+  const int d0 = (blockIdx.x * 256 + threadIdx.x) * 8;
+  if (d0 >= ldn) return;
   uint4 v = *(const uint4*)(Pt + (int64_t)k * ldn + d0);
+  int cd[8];
+  if (d0 + 8 <= n) {
+    const int4 c0 = *(const int4*)(c + d0), c1 = *(const int4*)(c + d0 + 4);
+    cd[0] = c0.x; cd[1] = c0.y; cd[2] = c0.z; cd[3] = c0.w;
+    cd[4] = c1.x; cd[5] = c1.y; cd[6] = c1.z; cd[7] = c1.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cd[q] = (d0 + q < n) ? c[d0 + q] : 0;
+  }
   bf16_t* e = (bf16_t*)&v;
 #pragma unroll
   for (int q = 0; q < 8; ++q)
-    if (d0 + q >= n || c[d0 + q] <= k) e[q] = 0;
+    if (cd[q] <= k) e[q] = 0;  // also every site >= n (cd = 0)
   *(uint4*)(Pm + (int64_t)k * ldn + d0) = v;
 }
 
@@ -271,8 +279,8 @@ hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t
                                      const bf16_t* St, const bf16_t* Rt, bf16_t* Dt, bf16_t* Pm,
                                      float* db1_part, float* dP, hipStream_t st) {
   const int64_t ldn = round_up(m.n, kPad), ldB = round_up(B, kPad), ldh = round_up(m.h, kPad);
-  const int64_t nvec = (int64_t)m.h * (ldn / 8);
-  mask_w2t_kernel<<<(unsigned)((nvec + 255) / 256), 256, 0, st>>>((const bf16_t*)m.Pt, ldn, m.c, m.n, m.h, Pm);
+  mask_w2t_kernel<<<dim3((unsigned)((ldn / 8 + 255) / 256), (unsigned)m.h), 256, 0, st>>>((const bf16_t*)m.Pt, ldn,
+                                                                                         m.c, m.n, m.h, Pm);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   bwd_hidden2_kernel<<<dim3((unsigned)((m.h + HB_BN - 1) / HB_BN), (unsigned)(ldB / HB_BM)), 256, 0, st>>>(

@@ -788,10 +788,10 @@ __global__ __launch_bounds__(256) void ztile_kernel(const WT* __restrict__ P, in
           v[1] = __float_as_uint(mid) >> 16;
           v[2] = __float_as_uint(lo) >> 16;
         }
-      } else {
-        const WT* row = P + (int64_t)d * ldh + 32 * (t - 1) + 8 * g;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = row[e];
+      } else {  // eight consecutive units of row d (inside the padded row: 32 t <= ldh)
+        const uint4 r = *(const uint4*)(P + (int64_t)d * ldh + 32 * (t - 1) + 8 * g);
+        *(uint4*)(zt + tile * 4096 + tt * 1024 + lane * 16) = r;
+        return;
       }
     }
     *(uint4*)(zt + tile * 4096 + tt * 1024 + lane * 16) =
@@ -813,15 +813,15 @@ __global__ __launch_bounds__(256) void utile_kernel(const WT* __restrict__ Pt, i
   if (tile >= (int64_t)nb * nut) return;
   const int q = (int)(tile / nut), t = (int)(tile % nut);
   const int k = 16 * t + (lane & 15), d0 = SP_T * q + 32 * ks + 8 * (lane >> 4);
-  WT v[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (k < h) ? Pt[(int64_t)k * ldn + d0 + e] : (WT)0;
+  // eight consecutive sites of row k (inside the padded row: d0 + 8 <= 64 nb <= ldn)
+  const WT* row = Pt + (int64_t)k * ldn + d0;
+  const uint4 z = make_uint4(0, 0, 0, 0);
   if constexpr (sizeof(WT) == 2) {
-    *(uint4*)(ut + tile * 2048 + ks * 1024 + lane * 16) = *(const uint4*)v;
+    *(uint4*)(ut + tile * 2048 + ks * 1024 + lane * 16) = (k < h) ? *(const uint4*)row : z;
   } else {
     uint8_t* o = ut + tile * 4096 + ks * 2048 + lane * 32;
-    *(uint4*)o = *(const uint4*)v;
-    *(uint4*)(o + 16) = *(const uint4*)(v + 4);
+    *(uint4*)o = (k < h) ? *(const uint4*)row : z;
+    *(uint4*)(o + 16) = (k < h) ? *(const uint4*)(row + 4) : z;
   }
 }
 
