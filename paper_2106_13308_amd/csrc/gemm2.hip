@@ -138,6 +138,18 @@ struct G2 {
 
 // ---------------------------------------------------------------- masked copy of P^T
 // Pm[k][d] = P[d][k] where unit k feeds site d (k < c[d]), 0 elsewhere (and for d >= n).
+// Workgroup index -> (row tile, column tile) such that the column tiles of one row tile run back to
+// back on one XCD: workgroups are dealt round-robin to the 8 XCDs, each with its own L2, so the
+// row tile's operand is then fetched into one L2 instead of eight.  Launch 8 * ceil(nrow / 8) * ncol
+// workgroups; r >= nrow marks a surplus one.
+__device__ inline void xcd_tile(int w, int nrow, int ncol, int& r, int& c) {
+  const int x = w & 7, j = w >> 3;
+  r = x + 8 * (j / ncol);
+  c = j % ncol;
+  (void)nrow;
+}
+__host__ inline unsigned xcd_grid(int nrow, int ncol) { return (unsigned)(8 * ((nrow + 7) / 8) * ncol); }
+
 __global__ __launch_bounds__(256) void mask_w2t_kernel(const bf16_t* __restrict__ Pt, int64_t ldn,
                                                         const int32_t* __restrict__ c, int n, int h,
                                                         bf16_t* __restrict__ Pm) {
@@ -177,8 +189,12 @@ __global__ __launch_bounds__(256) void bwd_hidden2_kernel(const bf16_t* __restri
   __shared__ float colacc[2][HB_BN];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (HB_BM / 2), wn = (wv & 1) * (HB_BN / 2);
-  const int64_t m0 = (int64_t)blockIdx.y * HB_BM;  // samples
-  const int n0 = blockIdx.x * HB_BN;               // units
+  int mt, nt;
+  const int nmt = (int)((B + HB_BM - 1) / HB_BM);  // = ldB / HB_BM: padding rows of Dt are written too
+  xcd_tile(blockIdx.x, nmt, (h + HB_BN - 1) / HB_BN, mt, nt);
+  if (mt >= nmt) return;
+  const int64_t m0 = (int64_t)mt * HB_BM;  // samples
+  const int n0 = nt * HB_BN;               // units
   // first site using unit n0 (c non-decreasing)
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(256) void bwd_hidden2_kernel(const bf16_t* __restri
   __syncthreads();
   if (t < HB_BN) {
     const int k = n0 + t;
-    if (k < ldh) db1_part[(int64_t)blockIdx.y * ldh + k] = colacc[0][t] + colacc[1][t];
+    if (k < ldh) db1_part[(int64_t)mt * ldh + k] = colacc[0][t] + colacc[1][t];
   }
 }
 
@@ -246,8 +262,11 @@ __global__ __launch_bounds__(256) void bwd_weight2_kernel(const bf16_t* __restri
   __shared__ __attribute__((aligned(16))) uint4 B0[WB_BN * 8], B1[WB_BN * 8], B2[WB_BN * 8];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wm = (wv >> 1) * (WB_BM / 2), wn = (wv & 1) * (WB_BN / 2);
-  const int d0 = blockIdx.y * WB_BM;   // sites
-  const int k0 = blockIdx.x * WB_BN;   // units
+  int dt, kt;
+  xcd_tile(blockIdx.x, (n + WB_BM - 1) / WB_BM, (h + WB_BN - 1) / WB_BN, dt, kt);
+  if (dt * WB_BM >= n) return;
+  const int d0 = dt * WB_BM;   // sites
+  const int k0 = kt * WB_BN;   // units
   const int dlast = min(d0 + WB_BM - 1, n - 1), klast = min(k0 + WB_BN - 1, h - 1);
   const bool lower = k0 < c[dlast];
   const bool upper = klast >= c[d0];
@@ -283,11 +302,11 @@ hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t
                                                                                          m.c, m.n, m.h, Pm);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  bwd_hidden2_kernel<<<dim3((unsigned)((m.h + HB_BN - 1) / HB_BN), (unsigned)(ldB / HB_BM)), 256, 0, st>>>(
+  bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 256, 0, st>>>(
       G, ldn, Pm, m.c, m.n, m.h, B, Rt, Dt, ldB, db1_part, ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_weight2_kernel<<<dim3((unsigned)((m.h + WB_BN - 1) / WB_BN), (unsigned)((m.n + WB_BM - 1) / WB_BM)), 256, 0,
-                       st>>>(Gt, Rt, St, Dt, ldB, m.c, m.n, m.h, dP);
+  bwd_weight2_kernel<<<xcd_grid((m.n + WB_BM - 1) / WB_BM, (m.h + WB_BN - 1) / WB_BN), 256, 0, st>>>(
+      Gt, Rt, St, Dt, ldB, m.c, m.n, m.h, dP);
   return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ __host__ __device__ inline int sp_lda(int h) { return (int)round_up(h, 32) + 4; 
 __host__ __device__ inline int sp_plda(int h) { return (int)round_up(h, 32) + 8; }
 
 constexpr int SP_NSW = 2;          // sweep waves (four samples each)
+constexpr int SP_RS = SP_T + 4;    // row stride of the helpers' partial logits: samples on distinct banks
 constexpr int SP_NHW = 10;         // helper waves
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
@@ -65,7 +66,7 @@ __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
   const size_t st = (size_t)(SP_MS + 1) * sp_lda(h) * 4;   // + a spare row of zeros
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
-  return st + 2 * SP_NHW * blk /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
+  return st + 2 * SP_NHW * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
          round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? (3 * (size_t)SP_MS + 1) * sp_plda(h) * 2 : 0);
 }
 constexpr size_t SP_LDS_MAX = 160 * 1024;
@@ -184,8 +185,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
                                    // row 8: zeros, the rows of the products' unused columns
-  float* red = st + (SP_MS + 1) * LDA;  // [2][6][8][64] helpers' partial logits of a block (+ b2)
-  float* th = red + 2 * SP_NHW * BLK;  // [2][8][64] -logit(u) * 2^100
+  constexpr int RB = SP_MS * SP_RS;
+  float* red = st + (SP_MS + 1) * LDA;  // [2][10][8][68] helpers' partial logits of a block (+ b2)
+  float* th = red + 2 * SP_NHW * RB;   // [2][8][64] -logit(u) * 2^100
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
 
@@ -230,9 +232,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   if constexpr (PLANES) {
     for (int i = t; i < PLDA; i += SP_THREADS) pl[3 * SP_MS * PLDA + i] = 0;
   }
-  for (int i = t; i < SP_NHW * BLK; i += SP_THREADS) {
-    const int j = i % SP_T;
-    red[i] = (i < BLK && j < n) ? b2[j] : 0.f;
+  for (int i = t; i < SP_NHW * RB; i += SP_THREADS) {  // block 0's logits: b2 in helper 0's slot
+    const int j = i % SP_RS;
+    red[i] = (i < RB && j < SP_T && j < n) ? b2[j] : 0.f;
   }
   for (int i = t; i <= nb; i += SP_THREADS) fb[i] = (i == 0) ? 0 : c[min(SP_T * i - 1, n - 1)];
   if (t < 128) thresholds(0, th, t);
@@ -263,11 +265,11 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       const int cur = b & 1;
       float zr[4], tz[4];
       {
-        const float* r0 = red + cur * SP_NHW * BLK + ss * SP_T + 4 * g;
+        const float* r0 = red + cur * SP_NHW * RB + ss * SP_RS + 4 * g;
         float4 acc4 = *(const float4*)r0;
 #pragma unroll
         for (int q = 1; q < SP_NHW; ++q) {
-          const float4 x = *(const float4*)(r0 + q * BLK);
+          const float4 x = *(const float4*)(r0 + q * RB);
           acc4.x += x.x; acc4.y += x.y; acc4.z += x.z; acc4.w += x.w;
         }
         const float4 t4 = *(const float4*)(th + cur * BLK + ss * SP_T + 4 * g);
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             for (int e = 0; e < 4; ++e) acc[tt][e] += VQMC_DPP(acc[tt][e], 0x128);  // row_ror:8
         }
         if (lowcol) {
-          float* dst = red + nxt * SP_NHW * BLK + hw * BLK + l16 * SP_T + 4 * g4;
+          float* dst = red + nxt * SP_NHW * RB + hw * RB + l16 * SP_RS + 4 * g4;
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
             *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
