@@ -9,16 +9,17 @@
 // The first product's mask is a property of the weight operand, so it runs on a masked
 // copy of P^T (W1 entries zeroed); the second's masks select output elements.
 //
-// Engine: a BM x BN tile per workgroup of 4 waves (2 x 2, each BM/2 x BN/2 as 16x16 MFMA
-// blocks, v_mfma_f32_16x16x32_bf16, FP32 accumulation).  K advances 64 elements (one
-// 128-byte row segment) per stage; three stages rotate through three separate LDS
-// buffers.  Each stage is brought in by global_load_lds_dwordx4 (16 bytes per lane straight
-// into LDS, no registers): a wave instruction fills 8 rows, lane l the 16-byte chunk
-// l % 8 of row l / 8.  Chunk c of row r is stored at position c ^ (r % 8), so the 16 rows
-// an MFMA operand read touches spread over the LDS banks.  A wave waits for its own loads
-// of a stage (vmcnt) before the stage's barrier; after the barrier every wave's loads of
-// that stage have landed.  Stage i+2 is issued right after the barrier of stage i, into
-// the buffer every wave finished reading at stage i-1.
+// Engine: a BM x BN tile per workgroup of WGM x WGN waves (each BM/WGM x BN/WGN as 16x16 MFMA
+// blocks, v_mfma_f32_16x16x32_bf16, FP32 accumulation; eight waves, two per SIMD, so one wave's
+// loads and barrier waits overlap the other's products).  K advances 64 elements (one 128-byte
+// row segment) per stage; three (or four) stages rotate through separate LDS buffers.  Each
+// stage is brought in by global_load_lds_dwordx4 (16 bytes per lane straight into LDS, no
+// registers): a wave instruction fills 8 rows, lane l the 16-byte chunk l % 8 of row l / 8, from
+// a per-lane byte offset fixed for the whole run plus the stage's column (scalar).  Chunk c of
+// row r is stored at position c ^ (r % 8), so the 16 rows an MFMA operand read touches spread
+// over the LDS banks.  A wave waits for its own loads of a stage (vmcnt) before the stage's
+// barrier; after the barrier every wave's loads of that stage have landed.  The next stage to
+// fetch is issued right after the barrier, into the buffer every wave finished reading before it.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -33,11 +34,13 @@ __device__ inline void g2_wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int WGM, int WGN>
 struct G2 {
-  static constexpr int FM = BM / 32, FN = BN / 32;  // 16x16 blocks per wave
-  static constexpr int AI = BM / 32, BI = BN / 32;  // load instructions per wave per stage
+  static constexpr int NW = WGM * WGN;                          // waves: WGM x WGN grid
+  static constexpr int FM = BM / (16 * WGM), FN = BN / (16 * WGN);  // 16x16 blocks per wave
+  static constexpr int AI = BM / (8 * NW), BI = BN / (8 * NW);  // load instructions per wave per stage
   static constexpr int NLD = AI + BI;
+  static_assert(AI * 8 * NW == BM && BI * 8 * NW == BN, "tile rows must split evenly over the waves");
 
   // operands: rows row0 + r (clamped to rows - 1: rows past the end are loaded but their
   // results are never stored), K columns [k, k + 64) of a row-major bf16 matrix whose
@@ -48,22 +51,38 @@ struct G2 {
     int row0, rows;
   };
 
-  __device__ static void issue(const Op& a, const Op& b, int k, uint4* As, uint4* Bs, int wv, int lane) {
+  // byte offsets of this lane's 16-byte chunks from column 0 of the operands (fixed for a run)
+  struct Lanes {
+    uint32_t a[AI], b[BI];
+  };
+  __device__ static Lanes lanes(const Op& a, const Op& b, int wv, int lane) {
+    Lanes L;
     const int rl = 8 * wv + (lane >> 3), p = lane & 7;
 #pragma unroll
     for (int j = 0; j < AI; ++j) {
-      const int r = 32 * j + rl;
+      const int r = 8 * NW * j + rl;
       const int gr = min(a.row0 + r, a.rows - 1);
-      const bf16_t* src = a.X + (int64_t)gr * a.ld + k + 8 * (p ^ (r & 7));
-      __builtin_amdgcn_global_load_lds((const void*)src, (g2_lds_t*)(As + (32 * j + 8 * wv) * 8), 16, 0, 0);
+      L.a[j] = (uint32_t)(((int64_t)gr * a.ld + 8 * (p ^ (r & 7))) * 2);
     }
 #pragma unroll
     for (int j = 0; j < BI; ++j) {
-      const int r = 32 * j + rl;
+      const int r = 8 * NW * j + rl;
       const int gr = min(b.row0 + r, b.rows - 1);
-      const bf16_t* src = b.X + (int64_t)gr * b.ld + k + 8 * (p ^ (r & 7));
-      __builtin_amdgcn_global_load_lds((const void*)src, (g2_lds_t*)(Bs + (32 * j + 8 * wv) * 8), 16, 0, 0);
+      L.b[j] = (uint32_t)(((int64_t)gr * b.ld + 8 * (p ^ (r & 7))) * 2);
     }
+    return L;
+  }
+  __device__ static void issue(const Op& a, const Op& b, const Lanes& L, int k, uint4* As, uint4* Bs, int wv) {
+    const uint8_t* ab = (const uint8_t*)(a.X + k);
+    const uint8_t* bb = (const uint8_t*)(b.X + k);
+#pragma unroll
+    for (int j = 0; j < AI; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(ab + L.a[j]), (g2_lds_t*)(As + (8 * NW * j + 8 * wv) * 8), 16,
+                                       0, 0);
+#pragma unroll
+    for (int j = 0; j < BI; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(bb + L.b[j]), (g2_lds_t*)(Bs + (8 * NW * j + 8 * wv) * 8), 16,
+                                       0, 0);
   }
 
   __device__ static void compute(const uint4* As, const uint4* Bs, int wm, int wn, int lane,
@@ -94,7 +113,7 @@ struct G2 {
   __device__ static void run(const Op& a, const Op& b, int kbeg, int nst, uint4* A0, uint4* A1, uint4* A2,
                              uint4* B0, uint4* B1, uint4* B2, floatx4_t (&acc)[FM][FN]) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
+    const int wm = (wv / WGN) * (BM / WGM), wn = (wv % WGN) * (BN / WGN);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -103,21 +122,22 @@ struct G2 {
     // every step issues one stage (past the end: the last stage again, never read), so the
     // count of loads in flight is the same on every path
     auto kof = [&](int s) { return kbeg + 64 * min(s, nst - 1); };
-    issue(a, b, kof(0), A0, B0, wv, lane);
-    issue(a, b, kof(1), A1, B1, wv, lane);
+    const Lanes L = lanes(a, b, wv, lane);
+    issue(a, b, L, kof(0), A0, B0, wv);
+    issue(a, b, L, kof(1), A1, B1, wv);
     int i = 0;
     for (; i + 3 <= nst; i += 3) {
       g2_wait_vm<NLD>();
       __builtin_amdgcn_s_barrier();
-      issue(a, b, kof(i + 2), A2, B2, wv, lane);
+      issue(a, b, L, kof(i + 2), A2, B2, wv);
       compute(A0, B0, wm, wn, lane, acc);
       g2_wait_vm<NLD>();
       __builtin_amdgcn_s_barrier();
-      issue(a, b, kof(i + 3), A0, B0, wv, lane);
+      issue(a, b, L, kof(i + 3), A0, B0, wv);
       compute(A1, B1, wm, wn, lane, acc);
       g2_wait_vm<NLD>();
       __builtin_amdgcn_s_barrier();
-      issue(a, b, kof(i + 4), A1, B1, wv, lane);
+      issue(a, b, L, kof(i + 4), A1, B1, wv);
       compute(A2, B2, wm, wn, lane, acc);
     }
     if (i < nst) {
@@ -131,6 +151,60 @@ struct G2 {
       compute(A1, B1, wm, wn, lane, acc);
     }
     // drain the loads still in flight before the buffers are reused
+    g2_wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+  }
+
+  // run with four rotating stages: three in flight while one is multiplied
+  __device__ static void run4(const Op& a, const Op& b, int kbeg, int nst, uint4* A0, uint4* A1, uint4* A2,
+                              uint4* A3, uint4* B0, uint4* B1, uint4* B2, uint4* B3, floatx4_t (&acc)[FM][FN]) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wm = (wv / WGN) * (BM / WGM), wn = (wv % WGN) * (BN / WGN);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+    if (nst <= 0) return;
+    auto kof = [&](int s) { return kbeg + 64 * min(s, nst - 1); };
+    const Lanes L = lanes(a, b, wv, lane);
+    issue(a, b, L, kof(0), A0, B0, wv);
+    issue(a, b, L, kof(1), A1, B1, wv);
+    issue(a, b, L, kof(2), A2, B2, wv);
+    int i = 0;
+    for (; i + 4 <= nst; i += 4) {
+      g2_wait_vm<2 * NLD>();
+      __builtin_amdgcn_s_barrier();
+      issue(a, b, L, kof(i + 3), A3, B3, wv);
+      compute(A0, B0, wm, wn, lane, acc);
+      g2_wait_vm<2 * NLD>();
+      __builtin_amdgcn_s_barrier();
+      issue(a, b, L, kof(i + 4), A0, B0, wv);
+      compute(A1, B1, wm, wn, lane, acc);
+      g2_wait_vm<2 * NLD>();
+      __builtin_amdgcn_s_barrier();
+      issue(a, b, L, kof(i + 5), A1, B1, wv);
+      compute(A2, B2, wm, wn, lane, acc);
+      g2_wait_vm<2 * NLD>();
+      __builtin_amdgcn_s_barrier();
+      issue(a, b, L, kof(i + 6), A2, B2, wv);
+      compute(A3, B3, wm, wn, lane, acc);
+    }
+    // stages i, i + 1, i + 2 are in flight in A0/B0, A1/B1, A2/B2
+    if (i < nst) {
+      g2_wait_vm<2 * NLD>();
+      __builtin_amdgcn_s_barrier();
+      compute(A0, B0, wm, wn, lane, acc);
+    }
+    if (i + 1 < nst) {
+      g2_wait_vm<NLD>();
+      __builtin_amdgcn_s_barrier();
+      compute(A1, B1, wm, wn, lane, acc);
+    }
+    if (i + 2 < nst) {
+      g2_wait_vm<0>();
+      __builtin_amdgcn_s_barrier();
+      compute(A2, B2, wm, wn, lane, acc);
+    }
     g2_wait_vm<0>();
     __builtin_amdgcn_s_barrier();
   }
@@ -177,18 +251,18 @@ __global__ __launch_bounds__(256) void mask_w2t_kernel(const bf16_t* __restrict_
 // ---------------------------------------------------------------- hidden adjoint
 // D = [A > 0] (G Pm^T); writes Dt (h x ldB) and db1 partials (per 64-sample tile).
 // Unit tile n0 only sees sites d >= count_le(c, n0) (earlier sites do not use it).
-constexpr int HB_BM = 64, HB_BN = 128;
-__global__ __launch_bounds__(256) void bwd_hidden2_kernel(const bf16_t* __restrict__ G, int64_t ldn,
+constexpr int HB_BM = 64, HB_BN = 128, HB_WGM = 2, HB_WGN = 4;
+__global__ __launch_bounds__(64 * HB_WGM * HB_WGN) void bwd_hidden2_kernel(const bf16_t* __restrict__ G, int64_t ldn,
                                                            const bf16_t* __restrict__ Pm,
                                                            const int32_t* __restrict__ c, int n, int h, int64_t B,
                                                            const bf16_t* __restrict__ Rt, bf16_t* __restrict__ Dt,
                                                            int64_t ldB, float* __restrict__ db1_part, int64_t ldh) {
-  using E = G2<HB_BM, HB_BN>;
+  using E = G2<HB_BM, HB_BN, HB_WGM, HB_WGN>;
   __shared__ __attribute__((aligned(16))) uint4 A0[HB_BM * 8], A1[HB_BM * 8], A2[HB_BM * 8];
   __shared__ __attribute__((aligned(16))) uint4 B0[HB_BN * 8], B1[HB_BN * 8], B2[HB_BN * 8];
-  __shared__ float colacc[2][HB_BN];
+  __shared__ float colacc[HB_WGM][HB_BN];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * (HB_BM / 2), wn = (wv & 1) * (HB_BN / 2);
+  const int wm = (wv / HB_WGN) * (HB_BM / HB_WGM), wn = (wv % HB_WGN) * (HB_BN / HB_WGN);
   int mt, nt;
   const int nmt = (int)((B + HB_BM - 1) / HB_BM);  // = ldB / HB_BM: padding rows of Dt are written too
   xcd_tile(blockIdx.x, nmt, (h + HB_BN - 1) / HB_BN, mt, nt);
@@ -239,12 +313,15 @@ __global__ __launch_bounds__(256) void bwd_hidden2_kernel(const bf16_t* __restri
   }
   if (lane < 16) {
 #pragma unroll
-    for (int j = 0; j < E::FN; ++j) colacc[wv >> 1][wn + j * 16 + lane] = cs[j];
+    for (int j = 0; j < E::FN; ++j) colacc[wv / HB_WGN][wn + j * 16 + lane] = cs[j];
   }
   __syncthreads();
   if (t < HB_BN) {
     const int k = n0 + t;
-    if (k < ldh) db1_part[(int64_t)mt * ldh + k] = colacc[0][t] + colacc[1][t];
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < HB_WGM; ++q) v += colacc[q][t];
+    if (k < ldh) db1_part[(int64_t)mt * ldh + k] = v;
   }
 }
 
@@ -252,16 +329,16 @@ __global__ __launch_bounds__(256) void bwd_hidden2_kernel(const bf16_t* __restri
 // Both halves in one launch: a tile runs the lower product (Gt x Rt) if any of its
 // elements has k < c[d], the upper one (St x Dt) if any has k >= c[d], and stores each
 // element from the product of its half.
-constexpr int WB_BM = 128, WB_BN = 128;
-__global__ __launch_bounds__(256) void bwd_weight2_kernel(const bf16_t* __restrict__ Gt, const bf16_t* __restrict__ Rt,
+constexpr int WB_BM = 128, WB_BN = 128, WB_WGM = 2, WB_WGN = 4;
+__global__ __launch_bounds__(64 * WB_WGM * WB_WGN) void bwd_weight2_kernel(const bf16_t* __restrict__ Gt, const bf16_t* __restrict__ Rt,
                                                            const bf16_t* __restrict__ St, const bf16_t* __restrict__ Dt,
                                                            int64_t ldB, const int32_t* __restrict__ c, int n, int h,
                                                            float* __restrict__ dP) {
-  using E = G2<WB_BM, WB_BN>;
-  __shared__ __attribute__((aligned(16))) uint4 A0[WB_BM * 8], A1[WB_BM * 8], A2[WB_BM * 8];
-  __shared__ __attribute__((aligned(16))) uint4 B0[WB_BN * 8], B1[WB_BN * 8], B2[WB_BN * 8];
+  using E = G2<WB_BM, WB_BN, WB_WGM, WB_WGN>;
+  __shared__ __attribute__((aligned(16))) uint4 A0[WB_BM * 8], A1[WB_BM * 8], A2[WB_BM * 8], A3[WB_BM * 8];
+  __shared__ __attribute__((aligned(16))) uint4 B0[WB_BN * 8], B1[WB_BN * 8], B2[WB_BN * 8], B3[WB_BN * 8];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wm = (wv >> 1) * (WB_BM / 2), wn = (wv & 1) * (WB_BN / 2);
+  const int wm = (wv / WB_WGN) * (WB_BM / WB_WGM), wn = (wv % WB_WGN) * (WB_BN / WB_WGN);
   int dt, kt;
   xcd_tile(blockIdx.x, (n + WB_BM - 1) / WB_BM, (h + WB_BN - 1) / WB_BN, dt, kt);
   if (dt * WB_BM >= n) return;
@@ -277,7 +354,7 @@ __global__ __launch_bounds__(256) void bwd_weight2_kernel(const bf16_t* __restri
     if (half == 0 ? !lower : !upper) continue;
     const E::Op a{half == 0 ? Gt : St, ldB, d0, n};
     const E::Op b{half == 0 ? Rt : Dt, ldB, k0, h};
-    E::run(a, b, 0, nst, A0, A1, A2, B0, B1, B2, acc);
+    E::run4(a, b, 0, nst, A0, A1, A2, A3, B0, B1, B2, B3, acc);
 #pragma unroll
     for (int i = 0; i < E::FM; ++i)
 #pragma unroll
@@ -302,10 +379,11 @@ hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t
                                                                                          m.c, m.n, m.h, Pm);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 256, 0, st>>>(
+  bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 64 * HB_WGM * HB_WGN, 0, st>>>(
       G, ldn, Pm, m.c, m.n, m.h, B, Rt, Dt, ldB, db1_part, ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_weight2_kernel<<<xcd_grid((m.n + WB_BM - 1) / WB_BM, (m.h + WB_BN - 1) / WB_BN), 256, 0, st>>>(
+  bwd_weight2_kernel<<<xcd_grid((m.n + WB_BM - 1) / WB_BM, (m.h + WB_BN - 1) / WB_BN), 64 * WB_WGM * WB_WGN, 0,
+                       st>>>(
       Gt, Rt, St, Dt, ldB, m.c, m.n, m.h, dP);
   return hipGetLastError();
 }
