@@ -329,7 +329,7 @@ __global__ __launch_bounds__(64 * HB_WGM * HB_WGN) void bwd_hidden2_kernel(const
 // Both halves in one launch: a tile runs the lower product (Gt x Rt) if any of its
 // elements has k < c[d], the upper one (St x Dt) if any has k >= c[d], and stores each
 // element from the product of its half.
-constexpr int WB_BM = 128, WB_BN = 128, WB_WGM = 2, WB_WGN = 4;
+constexpr int WB_BM = 128, WB_BN = 128, WB_WGM = 4, WB_WGN = 4;
 __global__ __launch_bounds__(64 * WB_WGM * WB_WGN) void bwd_weight2_kernel(const bf16_t* __restrict__ Gt, const bf16_t* __restrict__ Rt,
                                                            const bf16_t* __restrict__ St, const bf16_t* __restrict__ Dt,
                                                            int64_t ldB, const int32_t* __restrict__ c, int n, int h,
