@@ -8,6 +8,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace vqmc {
 
@@ -65,32 +66,52 @@ __global__ __launch_bounds__(EB_THREADS) void energy_csr_bits_kernel(int n, int6
   AT acc[EMSE];
 #pragma unroll
   for (int q = 0; q < EMSE; ++q) acc[q] = 0;
+  // row sums Y: int32 for integer weights while the row's sum of |w| fits (then no partial
+  // sum can overflow; a row beyond that is summed again in int64), else AT
+  constexpr bool INT = std::is_integral<WT>::value;
+  typedef typename std::conditional<INT, int32_t, AT>::type RT;
   for (int i = t; i < n; i += EB_THREADS) {
     const int64_t e0 = rowp(i), e1 = rowp(i + 1);
-    AT y[EMSE];
+    RT y[EMSE];
 #pragma unroll
     for (int q = 0; q < EMSE; ++q) y[q] = 0;
     AT wsum = 0;
+    int64_t wabs = 0;
     int64_t e = e0;
     for (; e + 1 < e1; e += 2) {  // two edges per step: their loads are issued together
       const int j0 = col[e], j1 = col[e + 1];
-      const AT w0 = (AT)w[e], w1 = (AT)w[e + 1];
+      const RT w0 = (RT)w[e], w1 = (RT)w[e + 1];
       const uint32_t m0 = bits[j0], m1 = bits[j1];
-      wsum += w0 + w1;
+      wsum += (AT)w0 + (AT)w1;
+      if constexpr (INT) wabs += llabs((int64_t)w0) + llabs((int64_t)w1);
 #pragma unroll
-      for (int q = 0; q < EMSE; ++q) y[q] += (((m0 >> q) & 1u) ? w0 : (AT)0) + (((m1 >> q) & 1u) ? w1 : (AT)0);
+      for (int q = 0; q < EMSE; ++q) y[q] += (((m0 >> q) & 1u) ? w0 : (RT)0) + (((m1 >> q) & 1u) ? w1 : (RT)0);
     }
     if (e < e1) {
-      const AT w0 = (AT)w[e];
+      const RT w0 = (RT)w[e];
       const uint32_t m0 = bits[col[e]];
-      wsum += w0;
+      wsum += (AT)w0;
+      if constexpr (INT) wabs += llabs((int64_t)w0);
 #pragma unroll
-      for (int q = 0; q < EMSE; ++q) y[q] += ((m0 >> q) & 1u) ? w0 : (AT)0;
+      for (int q = 0; q < EMSE; ++q) y[q] += ((m0 >> q) & 1u) ? w0 : (RT)0;
+    }
+    AT ya[EMSE];
+#pragma unroll
+    for (int q = 0; q < EMSE; ++q) ya[q] = (AT)y[q];
+    if (INT && wabs > (int64_t)INT32_MAX) {
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q) ya[q] = 0;
+      for (int64_t f = e0; f < e1; ++f) {
+        const AT wf = (AT)w[f];
+        const uint32_t mf = bits[col[f]];
+#pragma unroll
+        for (int q = 0; q < EMSE; ++q) ya[q] += ((mf >> q) & 1u) ? wf : (AT)0;
+      }
     }
     const uint32_t mi = bits[i];
 #pragma unroll
     for (int q = 0; q < EMSE; ++q) {
-      const AT r = 2 * y[q] - wsum;
+      const AT r = 2 * ya[q] - wsum;
       acc[q] += ((mi >> q) & 1u) ? r : -r;
     }
   }

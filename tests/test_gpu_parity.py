@@ -94,6 +94,22 @@ def test_energy_csr_int_bit_exact(n, deg, B):
     assert (B_.energy(H, S).cpu().numpy() == int(w.sum())).all()
 
 
+def test_energy_csr_int_large_weights():
+    """Rows whose sum of |w| exceeds the int32 range take the int64 row path."""
+    _banner("energy csr int large weights")
+    n, B = 300, 19
+    edges = inputs.random_regular_graph(n, 6, 3)
+    w = inputs.integer_weights(len(edges), -(1 << 30), 1 << 30, 4)
+    w[: len(w) // 2] = np.where(w[: len(w) // 2] >= 0, (1 << 31) - 1, -(1 << 31))  # extremes on half the edges
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    S_np = inputs.random_spins(B, n, 5)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    E = B_.energy(H, S).cpu().numpy()
+    ref = oen.energy_edges(edges, w, S_np)
+    assert np.array_equal(E, ref)
+
+
 def test_energy_csr_f32_and_dense():
     _banner("energy csr f32 / dense")
     n, B = 300, 130
