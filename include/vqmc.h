@@ -138,6 +138,15 @@ int vqmc_unpack(int32_t n, int32_t h, const float* P32, const int32_t* c, float*
 int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt,
               void* stream);
 
+/* vqmc_cast followed by vqmc_band in one pass over the weights, as after every optimiser
+ * update (Sec. 5.1: Adam on the FP32 master weights, then the kernels' working copies are
+ * re-derived): writes P and Pt from P32 (as vqmc_cast) and, when band is not NULL, the
+ * sampler's tables for the model (P, Pt, b1, b2, c) (as vqmc_band; band of
+ * vqmc_band_bytes(n, h, dtype) bytes, 16-byte aligned).  The logit and push tiles are written
+ * by the same workgroups that cast P32, from the tile they hold on chip. */
+int vqmc_refresh(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt, const float* b1,
+                 const float* b2, const int32_t* c, float* band, void* stream);
+
 /* Size in bytes of the pipelined sampler's tables (the band) for n sites, h hidden units
  * and weights of type wdtype (VQMC_F32 or VQMC_BF16); 0 for invalid arguments. */
 size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype);

@@ -59,6 +59,7 @@ _SIGS = {
     "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "vqmc_band": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _vp]),
     "vqmc_band_bytes": (ctypes.c_size_t, [_i32, _i32, _i32]),
+    "vqmc_refresh": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
     "vqmc_sample_fwd": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp, _vp,
                                        _vp]),
@@ -152,12 +153,12 @@ class Made:
         return cls(n, h, P32, b1t, b2t, c, wdtype, band)
 
     def refresh(self):
-        """Re-derive the working copies after P32 changed (e.g. after an optimiser step)."""
-        _check("vqmc_cast", _lib.vqmc_cast(self.n, self.h, self.P32.data_ptr(), self.wdtype,
-                                           self.P.data_ptr(), self.Pt.data_ptr(), _stream()))
-        if self.band is not None:
-            m = self.cstruct()
-            _check("vqmc_band", _lib.vqmc_band(ctypes.byref(m), self.band.data_ptr(), _stream()))
+        """Re-derive the working copies (and the sampler tables) after P32 changed (e.g. after an
+        optimiser step): one vqmc_refresh call."""
+        _check("vqmc_refresh", _lib.vqmc_refresh(self.n, self.h, self.P32.data_ptr(), self.wdtype,
+                                                 self.P.data_ptr(), self.Pt.data_ptr(), self.b1.data_ptr(),
+                                                 self.b2.data_ptr(), self.c.data_ptr(), _ptr(self.band),
+                                                 _stream()))
 
     def cstruct(self) -> MadeC:
         return MadeC(self.n, self.h, self.wdtype, self.P.data_ptr(), self.Pt.data_ptr(),

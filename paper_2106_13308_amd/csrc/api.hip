@@ -155,6 +155,20 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
   return hip_status(launch_cast(n, h, P32, dtype, P, Pt, (hipStream_t)stream), "vqmc_cast");
 }
 
+int vqmc_refresh(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt, const float* b1,
+                 const float* b2, const int32_t* c, float* band, void* stream) {
+  if (n < 2 || h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1");
+  if (dtype != VQMC_F32 && dtype != VQMC_BF16) return fail(VQMC_EDTYPE, "cast dtype %d", dtype);
+  if (!P32 || !P || !Pt) return fail(VQMC_EINVAL, "null pointer");
+  if (band && (!b1 || !b2 || !c)) return fail(VQMC_EINVAL, "band needs b1, b2 and c");
+  if (band && ((uintptr_t)band & 15)) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_cast(n, h, P32, dtype, P, Pt, st, b2, band);
+  if (e != hipSuccess || !band) return hip_status(e, "vqmc_refresh");
+  const vqmc_made m{n, h, dtype, P, Pt, b1, b2, c, band};
+  return hip_status(launch_band(m, band, st, false), "vqmc_refresh");
+}
+
 size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype) {
   if (n < 2 || h < 1 || (wdtype != VQMC_F32 && wdtype != VQMC_BF16)) return 0;
   return sample_tables_bytes(n, h, wdtype);

@@ -12,7 +12,8 @@ hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int
                        hipStream_t st);
 hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float* W1, float* W2,
                          hipStream_t st);
-hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st);
+hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
+                       const float* b2 = nullptr, void* tables = nullptr);
 
 // energy.hip
 hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, void* E,
@@ -34,7 +35,8 @@ size_t sample_tables_bytes(int n, int h, int wdtype);
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                               uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs = nullptr,
                               void* Rt = nullptr);
-hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st);
+hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st, bool tiles = true);
+void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int* nzt, int* nut);
 hipError_t launch_uniforms(int n, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
                            float* u, hipStream_t st);
 

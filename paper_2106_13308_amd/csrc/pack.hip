@@ -69,10 +69,16 @@ __device__ inline bf16_t convert<bf16_t>(float x) { return f32_to_bf16(x); }
 // transpose through LDS written as 8-element rows of Pt.  The grid covers the padded
 // extents, so padding is written as zero.
 constexpr int CT = 64;
-template <typename T>
+// With TABLES the same workgroup also writes the pipelined sampler's weight tiles of its
+// 64 sites x 64 units (layout: the sampler tables after the band records, see vqmc_band):
+// logit tiles of the block's units (and, in the first column of workgroups, the block's b2
+// tile) and push tiles, straight from the LDS tile, so the weights are read once.
+template <typename T, bool TABLES>
 __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, int64_t ldn,
                                                     const float* __restrict__ P32,
-                                                    T* __restrict__ P, T* __restrict__ Pt) {
+                                                    T* __restrict__ P, T* __restrict__ Pt,
+                                                    const float* __restrict__ b2, uint8_t* __restrict__ ztab,
+                                                    uint8_t* __restrict__ utab, int nzt, int nut) {
   __shared__ T tile[CT][CT + 2];  // odd row stride in dwords for either T: column reads spread
   const int d0 = blockIdx.y * CT, k0 = blockIdx.x * CT;
   const int t = threadIdx.x;
@@ -125,6 +131,82 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
       }
     }
   }
+  if constexpr (TABLES) {
+    const int q = d0 / CT;  // site block
+    if constexpr (sizeof(T) == 2) {
+      // logit tiles t = 1 + k0/32 + cc: [4 site tiles][64 lanes][8 units], lane = 16 g + i
+      uint8_t* zq = ztab + (int64_t)q * nzt * 4096;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int u = t + 256 * r, cc = u >> 8, tt = (u >> 6) & 3, lane = u & 63;
+        const int zt = 1 + k0 / 32 + cc;
+        if (zt < nzt) {
+          const int dl = 16 * tt + (lane & 15), kl = 32 * cc + 8 * (lane >> 4);
+          const uint32_t* src = (const uint32_t*)&tile[dl][kl];  // 4-byte aligned: even column
+          *(uint4*)(zq + (int64_t)zt * 4096 + tt * 1024 + lane * 16) = make_uint4(src[0], src[1], src[2], src[3]);
+        }
+      }
+      // push tiles i = k0/16 + ii: [2 halves][64 lanes][8 sites], lane = 16 g + unit
+      uint8_t* uq = utab + (int64_t)q * nut * 2048;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int u = t + 256 * r, ii = u >> 7, ks = (u >> 6) & 1, lane = u & 63;
+        const int ut = k0 / 16 + ii;
+        if (ut < nut) {
+          const int kl = 16 * ii + (lane & 15), dl = 32 * ks + 8 * (lane >> 4);
+          T o[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) o[e] = tile[dl + e][kl];
+          *(uint4*)(uq + (int64_t)ut * 2048 + ks * 1024 + lane * 16) = *(const uint4*)o;
+        }
+      }
+      if (k0 == 0) {  // b2 tile: units 0-2 of lane group 0 hold hi, mid, lo of b2
+        const int tt = t >> 6, lane = t & 63, i = lane & 15, g = lane >> 4;
+        const int d = d0 + 16 * tt + i;
+        uint32_t v[3] = {0u, 0u, 0u};
+        if (g == 0 && d < n) {
+          const float x = b2[d];
+          const float hi = __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
+          const float rr = x - hi;
+          const float mid = __uint_as_float(__float_as_uint(rr) & 0xFFFF0000u);
+          const float lo = rr - mid;
+          v[0] = __float_as_uint(hi) >> 16;
+          v[1] = __float_as_uint(mid) >> 16;
+          v[2] = __float_as_uint(lo) >> 16;
+        }
+        *(uint4*)(zq + tt * 1024 + lane * 16) = make_uint4(v[0] | (v[1] << 16), v[2], 0u, 0u);
+      }
+    } else {
+      // logit tiles t = 1 + k0/4 + cc: [4 site tiles][64 lanes] floats, unit = lane / 16
+      uint8_t* zq = ztab + (int64_t)q * nzt * 1024;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int u = t + 256 * r, cc = u >> 8, tt = (u >> 6) & 3, lane = u & 63;
+        const int zt = 1 + k0 / 4 + cc;
+        if (zt < nzt) *(float*)(zq + (int64_t)zt * 1024 + tt * 256 + lane * 4) = (float)tile[16 * tt + (lane & 15)][4 * cc + (lane >> 4)];
+      }
+      // push tiles: [2 halves][64 lanes][8 sites] floats
+      uint8_t* uq = utab + (int64_t)q * nut * 4096;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int u = t + 256 * r, ii = u >> 7, ks = (u >> 6) & 1, lane = u & 63;
+        const int ut = k0 / 16 + ii;
+        if (ut < nut) {
+          const int kl = 16 * ii + (lane & 15), dl = 32 * ks + 8 * (lane >> 4);
+          float o[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) o[e] = (float)tile[dl + e][kl];
+          uint8_t* dst = uq + (int64_t)ut * 4096 + ks * 2048 + lane * 32;
+          *(float4*)dst = *(const float4*)o;
+          *(float4*)(dst + 16) = *(const float4*)(o + 4);
+        }
+      }
+      if (k0 == 0) {
+        const int tt = t >> 6, lane = t & 63, d = d0 + 16 * tt + (lane & 15);
+        *(float*)(zq + tt * 256 + lane * 4) = ((lane >> 4) == 0 && d < n) ? b2[d] : 0.f;
+      }
+    }
+  }
 }
 
 hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int32_t* c, float* P32,
@@ -141,14 +223,30 @@ hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float
   return hipGetLastError();
 }
 
-hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st) {
+hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
+                       const float* b2, void* tables) {
   const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad);
   // grid covers the padded extents so that padding is written as zero
   dim3 grid((unsigned)(ldh / CT), (unsigned)(ldn / CT));
-  if (dtype == VQMC_BF16)
-    cast_kernel<bf16_t><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt);
-  else
-    cast_kernel<float><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt);
+  uint8_t *zt = nullptr, *ut = nullptr;
+  int nzt = 0, nut = 0;
+  if (tables) {
+    int64_t zo, uo;
+    sample_tables_layout(n, h, dtype, &zo, &uo, &nzt, &nut);
+    zt = (uint8_t*)tables + zo;
+    ut = (uint8_t*)tables + uo;
+  }
+  if (dtype == VQMC_BF16) {
+    if (tables)
+      cast_kernel<bf16_t, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, zt, ut, nzt, nut);
+    else
+      cast_kernel<bf16_t, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, zt, ut, 0, 0);
+  } else {
+    if (tables)
+      cast_kernel<float, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, zt, ut, nzt, nut);
+    else
+      cast_kernel<float, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, zt, ut, 0, 0);
+  }
   return hipGetLastError();
 }
 

@@ -827,7 +827,7 @@ __global__ __launch_bounds__(256) void utile_kernel(const WT* __restrict__ Pt, i
   }
 }
 
-hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
+hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st, bool tiles) {
   const unsigned grid = (unsigned)((m.h + 3) / 4);
   const int64_t ldn = round_up(m.n, kPad);
   if (m.wdtype == VQMC_BF16)
@@ -835,7 +835,7 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
   else
     band_kernel<float><<<grid, 256, 0, st>>>((const float*)m.Pt, ldn, m.c, m.n, m.h, band);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !tiles) return e;
   const SpTables tb = sp_tables(m.n, m.h, m.wdtype);
   const int nb = (m.n + SP_T - 1) / SP_T;
   const int64_t ldh = round_up(m.h, kPad);
@@ -855,6 +855,14 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st) {
 bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h, false) <= SP_LDS_MAX; }
 
 size_t sample_tables_bytes(int n, int h, int wdtype) { return (size_t)sp_tables(n, h, wdtype).bytes; }
+
+void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int* nzt, int* nut) {
+  const SpTables t = sp_tables(n, h, wdtype);
+  *z = t.z;
+  *u = t.u;
+  *nzt = t.nzt;
+  *nut = t.nut;
+}
 
 template <typename WT, bool PLANES>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,

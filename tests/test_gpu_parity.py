@@ -448,6 +448,15 @@ def test_sampler_tables(wd):
             for ks in range(2):
                 d = 64 * qb + 32 * ks + 8 * g[:, None] + np.arange(8)[None, :]
                 assert np.array_equal(U[qb, t, ks], Pp[d, (16 * t + i)[:, None]]), (qb, t, ks)
+    # vqmc_band (tiles read back from P and Pt) writes the same bytes as vqmc_refresh (tiles
+    # written by the workgroups that cast P32)
+    band2 = torch.full_like(M.band, 7.0)
+    m = M.cstruct()
+    B_._check("vqmc_band", B_.lib.vqmc_band(B_.ctypes.byref(m), band2.data_ptr(), B_._stream()))
+    raw2 = band2.cpu().numpy().view(np.uint8)
+    end = uoff + nb * nut * ut
+    assert np.array_equal(raw2[:h * 260 * 4], raw[:h * 260 * 4])  # records (the gap up to zoff is unused)
+    assert np.array_equal(raw2[zoff:end], raw[zoff:end])
 
 
 def test_sample_deterministic():
