@@ -324,25 +324,29 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
                  : (algo == 0) ? launch_sample_incremental(*m, B, seed, step, sample_offset, 0, S, logp, st)
                                : launch_sample_plain(*m, B, seed, step, sample_offset, 0, S, logp, ws, st);
   if (e != hipSuccess) return hip_status(e, "vqmc_step sample");
-  // energy + statistics on the auxiliary stream, overlapping the first backward product
-  // (which only needs the spins); the main stream waits for them before reading coef
-  StepAux* aux = nullptr;
-  if ((e = step_aux(&aux)) != hipSuccess) return hip_status(e, "vqmc_step aux stream");
   void* ws_energy = (uint8_t*)ws + step_energy_offset(m->n, m->h, B, m->wdtype);
-  if ((e = hipEventRecord(aux->sampled, st)) != hipSuccess) return hip_status(e, "vqmc_step record");
-  if ((e = hipStreamWaitEvent(aux->stream, aux->sampled, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
-  if ((e = launch_energy(*H, S, B, E, ws_energy, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step energy");
-  if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, aux->stream)) != hipSuccess)
-    return hip_status(e, "vqmc_step stats");
-  if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
   if (fused) {
-    if ((e = hipStreamWaitEvent(st, aux->stats_done, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
+    // every backward product needs coef, so energy and statistics stay on the stream: a hop
+    // to another stream and back would only add two synchronisations
+    if ((e = launch_energy(*H, S, B, E, ws_energy, st)) != hipSuccess) return hip_status(e, "vqmc_step energy");
+    if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, st)) != hipSuccess)
+      return hip_status(e, "vqmc_step stats");
     void* Pm = (uint8_t*)ws + step_pm_offset(m->n, m->h, B, m->wdtype);
     if ((e = launch_backward_sampled(*m, S, B, coef, Zs, backward_rt_slot(*m, B, ws), dP, db1, db2, ws, Pm, st)) !=
         hipSuccess)
       return hip_status(e, "vqmc_step backward");
     return VQMC_OK;
   }
+  // energy + statistics on the auxiliary stream, overlapping the first backward product
+  // (which only needs the spins); the main stream waits for them before reading coef
+  StepAux* aux = nullptr;
+  if ((e = step_aux(&aux)) != hipSuccess) return hip_status(e, "vqmc_step aux stream");
+  if ((e = hipEventRecord(aux->sampled, st)) != hipSuccess) return hip_status(e, "vqmc_step record");
+  if ((e = hipStreamWaitEvent(aux->stream, aux->sampled, 0)) != hipSuccess) return hip_status(e, "vqmc_step wait");
+  if ((e = launch_energy(*H, S, B, E, ws_energy, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step energy");
+  if ((e = launch_stats(E, H->kind == VQMC_H_CSR_INT, B, stats, coef, aux->stream)) != hipSuccess)
+    return hip_status(e, "vqmc_step stats");
+  if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
   if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st, aux->stats_done)) != hipSuccess)
     return hip_status(e, "vqmc_step backward");
   return VQMC_OK;
