@@ -163,7 +163,7 @@ int vqmc_refresh(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P,
   if (band && (!b1 || !b2 || !c)) return fail(VQMC_EINVAL, "band needs b1, b2 and c");
   if (band && ((uintptr_t)band & 15)) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_cast(n, h, P32, dtype, P, Pt, st, b2, band);
+  hipError_t e = launch_cast(n, h, P32, dtype, P, Pt, st, b2, c, band);
   if (e != hipSuccess || !band) return hip_status(e, "vqmc_refresh");
   const vqmc_made m{n, h, dtype, P, Pt, b1, b2, c, band};
   return hip_status(launch_band(m, band, st, false), "vqmc_refresh");

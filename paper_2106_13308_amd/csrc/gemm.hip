@@ -846,7 +846,16 @@ static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if constexpr (sizeof(T) == 2) {
     // BF16: the direct-to-LDS engine, the adjoint's mask on a masked copy of P^T
-    e = launch_backward_products2(m, B, G, Gt, St, Rt, Dt, (bf16_t*)Pm, db1_part, dP, st);
+    // the masked copy of P^T comes with the sampler tables when there are any
+    bool ready = false;
+    if (m.band) {
+      int64_t zo, uo, po;
+      int nzt, nut;
+      sample_tables_layout(m.n, m.h, m.wdtype, &zo, &uo, &po, &nzt, &nut);
+      Pm = (uint8_t*)m.band + po;
+      ready = true;
+    }
+    e = launch_backward_products2(m, B, G, Gt, St, Rt, Dt, (bf16_t*)Pm, db1_part, dP, st, ready);
     if (e != hipSuccess) return e;
   } else {
     bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,

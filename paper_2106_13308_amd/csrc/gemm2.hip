@@ -371,13 +371,18 @@ __global__ __launch_bounds__(64 * WB_WGM * WB_WGN) void bwd_weight2_kernel(const
 
 size_t mask_w2t_bytes(int n, int h) { return (size_t)h * round_up(n, kPad) * sizeof(bf16_t); }
 
-hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t* G, const bf16_t* Gt,
-                                     const bf16_t* St, const bf16_t* Rt, bf16_t* Dt, bf16_t* Pm,
-                                     float* db1_part, float* dP, hipStream_t st) {
-  const int64_t ldn = round_up(m.n, kPad), ldB = round_up(B, kPad), ldh = round_up(m.h, kPad);
+hipError_t launch_mask_w2t(const vqmc_made& m, bf16_t* Pm, hipStream_t st) {
+  const int64_t ldn = round_up(m.n, kPad);
   mask_w2t_kernel<<<dim3((unsigned)((ldn / 8 + 255) / 256), (unsigned)m.h), 256, 0, st>>>((const bf16_t*)m.Pt, ldn,
                                                                                          m.c, m.n, m.h, Pm);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t* G, const bf16_t* Gt,
+                                     const bf16_t* St, const bf16_t* Rt, bf16_t* Dt, bf16_t* Pm,
+                                     float* db1_part, float* dP, hipStream_t st, bool pm_ready) {
+  const int64_t ldn = round_up(m.n, kPad), ldB = round_up(B, kPad), ldh = round_up(m.h, kPad);
+  hipError_t e = pm_ready ? hipSuccess : launch_mask_w2t(m, Pm, st);
   if (e != hipSuccess) return e;
   bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 64 * HB_WGM * HB_WGN, 0, st>>>(
       G, ldn, Pm, m.c, m.n, m.h, B, Rt, Dt, ldB, db1_part, ldh);

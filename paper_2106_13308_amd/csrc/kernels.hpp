@@ -13,7 +13,7 @@ hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int
 hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float* W1, float* W2,
                          hipStream_t st);
 hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
-                       const float* b2 = nullptr, void* tables = nullptr);
+                       const float* b2 = nullptr, const int32_t* c = nullptr, void* tables = nullptr);
 
 // energy.hip
 hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, void* E,
@@ -36,7 +36,8 @@ hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint
                               uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs = nullptr,
                               void* Rt = nullptr);
 hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st, bool tiles = true);
-void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int* nzt, int* nut);
+void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int64_t* pm, int* nzt, int* nut);
+hipError_t launch_mask_w2t(const vqmc_made& m, uint16_t* Pm, hipStream_t st);
 hipError_t launch_uniforms(int n, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
                            float* u, hipStream_t st);
 
@@ -59,7 +60,7 @@ hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t 
 size_t mask_w2t_bytes(int n, int h);
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Gt,
                                      const uint16_t* St, const uint16_t* Rt, uint16_t* Dt, uint16_t* Pm,
-                                     float* db1_part, float* dP, hipStream_t st);
+                                     float* db1_part, float* dP, hipStream_t st, bool pm_ready);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,

@@ -77,8 +77,9 @@ template <typename T, bool TABLES>
 __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, int64_t ldn,
                                                     const float* __restrict__ P32,
                                                     T* __restrict__ P, T* __restrict__ Pt,
-                                                    const float* __restrict__ b2, uint8_t* __restrict__ ztab,
-                                                    uint8_t* __restrict__ utab, int nzt, int nut) {
+                                                    const float* __restrict__ b2, const int32_t* __restrict__ c,
+                                                    uint8_t* __restrict__ ztab, uint8_t* __restrict__ utab,
+                                                    bf16_t* __restrict__ Pm, int nzt, int nut) {
   __shared__ T tile[CT][CT + 2];  // odd row stride in dwords for either T: column reads spread
   const int d0 = blockIdx.y * CT, k0 = blockIdx.x * CT;
   const int t = threadIdx.x;
@@ -114,6 +115,11 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
   __syncthreads();
   {
     const int dx = t & 7, kr = t >> 3;  // sites 8 dx .. +7, units kr + 32 s
+    int cd[8];  // TABLES, BF16: c of the eight sites, for the masked copy of P^T (0 past n)
+    if constexpr (TABLES && sizeof(T) == 2) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cd[e] = (d0 + 8 * dx + e < n) ? c[d0 + 8 * dx + e] : 0;
+    }
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const int kk = kr + 32 * s2, k = k0 + kk;
@@ -124,6 +130,12 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
         T* dst = Pt + (int64_t)k * ldn + d0 + 8 * dx;  // inside the padded row
         if constexpr (sizeof(T) == 2) {
           *(uint4*)dst = *(const uint4*)o;
+          if constexpr (TABLES) {  // unit k feeds site d iff k < c[d]
+            T pm[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) pm[e] = (k < cd[e]) ? o[e] : (T)0;
+            *(uint4*)(Pm + (int64_t)k * ldn + d0 + 8 * dx) = *(const uint4*)pm;
+          }
         } else {
           *(float4*)dst = *(const float4*)o;
           *(float4*)(dst + 4) = *(const float4*)(o + 4);
@@ -224,28 +236,34 @@ hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float
 }
 
 hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
-                       const float* b2, void* tables) {
+                       const float* b2, const int32_t* c, void* tables) {
   const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad);
   // grid covers the padded extents so that padding is written as zero
   dim3 grid((unsigned)(ldh / CT), (unsigned)(ldn / CT));
   uint8_t *zt = nullptr, *ut = nullptr;
+  bf16_t* pm = nullptr;
   int nzt = 0, nut = 0;
   if (tables) {
-    int64_t zo, uo;
-    sample_tables_layout(n, h, dtype, &zo, &uo, &nzt, &nut);
+    int64_t zo, uo, po;
+    sample_tables_layout(n, h, dtype, &zo, &uo, &po, &nzt, &nut);
     zt = (uint8_t*)tables + zo;
     ut = (uint8_t*)tables + uo;
+    pm = (bf16_t*)((uint8_t*)tables + po);
   }
   if (dtype == VQMC_BF16) {
     if (tables)
-      cast_kernel<bf16_t, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, zt, ut, nzt, nut);
+      cast_kernel<bf16_t, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, c, zt, ut, pm,
+                                                       nzt, nut);
     else
-      cast_kernel<bf16_t, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, zt, ut, 0, 0);
+      cast_kernel<bf16_t, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, c, zt, ut, pm,
+                                                        0, 0);
   } else {
     if (tables)
-      cast_kernel<float, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, zt, ut, nzt, nut);
+      cast_kernel<float, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, c, zt, ut, pm,
+                                                      nzt, nut);
     else
-      cast_kernel<float, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, zt, ut, 0, 0);
+      cast_kernel<float, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, c, zt, ut, pm,
+                                                       0, 0);
   }
   return hipGetLastError();
 }

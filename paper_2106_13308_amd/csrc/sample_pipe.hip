@@ -87,7 +87,7 @@ __host__ inline bool sp_planes(int n, int h, int wdtype) {
 //    P[64q + site][16 t + unit] (zero past n and h), [2 site halves][64 lanes][8 sites]
 //    with lane = 16 g + unit and sites 32 half + 8 g .. + 7.
 struct SpTables {
-  int64_t z, u, bytes;  // byte offsets of the logit and push tiles, total size
+  int64_t z, u, pm, bytes;  // byte offsets of the logit tiles, push tiles, masked P^T; total size
   int nzt, nut, zt, ut;  // tiles per block and bytes per tile
 };
 __host__ __device__ inline SpTables sp_tables(int n, int h, int wdtype) {
@@ -101,7 +101,9 @@ __host__ __device__ inline SpTables sp_tables(int n, int h, int wdtype) {
   t.ut = bf ? 2048 : 4096;
   t.z = round_up((int64_t)h * VQMC_BAND_REC * 4, 256);
   t.u = t.z + (int64_t)nb * t.nzt * t.zt;
-  t.bytes = t.u + (int64_t)nb * t.nut * t.ut;
+  t.pm = round_up(t.u + (int64_t)nb * t.nut * t.ut, 256);
+  // BF16: then the backward's masked copy of P^T, h x ld(n) (unit k feeds site d: k < c[d])
+  t.bytes = bf ? t.pm + (int64_t)h * round_up(n, 64) * 2 : t.pm;
   return t;
 }
 
@@ -845,6 +847,8 @@ hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st, bool til
   if (m.wdtype == VQMC_BF16) {
     ztile_kernel<bf16_t><<<gz, 256, 0, st>>>((const bf16_t*)m.P, ldh, m.b2, m.n, nb, tb.nzt, tab + tb.z);
     utile_kernel<bf16_t><<<gu, 256, 0, st>>>((const bf16_t*)m.Pt, ldn, m.h, nb, tb.nut, tab + tb.u);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_mask_w2t(m, (bf16_t*)(tab + tb.pm), st);
   } else {
     ztile_kernel<float><<<gz, 256, 0, st>>>((const float*)m.P, ldh, m.b2, m.n, nb, tb.nzt, tab + tb.z);
     utile_kernel<float><<<gu, 256, 0, st>>>((const float*)m.Pt, ldn, m.h, nb, tb.nut, tab + tb.u);
@@ -856,10 +860,11 @@ bool sample_pipe_supported(int n, int h) { return sp_smem_bytes(n, h, false) <= 
 
 size_t sample_tables_bytes(int n, int h, int wdtype) { return (size_t)sp_tables(n, h, wdtype).bytes; }
 
-void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int* nzt, int* nut) {
+void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int64_t* pm, int* nzt, int* nut) {
   const SpTables t = sp_tables(n, h, wdtype);
   *z = t.z;
   *u = t.u;
+  *pm = t.pm;
   *nzt = t.nzt;
   *nut = t.nut;
 }

@@ -457,6 +457,15 @@ def test_sampler_tables(wd):
     end = uoff + nb * nut * ut
     assert np.array_equal(raw2[:h * 260 * 4], raw[:h * 260 * 4])  # records (the gap up to zoff is unused)
     assert np.array_equal(raw2[zoff:end], raw[zoff:end])
+    if wd == "bf16":  # then the masked copy of P^T the backward uses: P^T where k < c[d], else 0
+        pmoff = (end + 255) // 256 * 256
+        ldn = B_.ld(n)
+        assert raw.size >= pmoff + h * ldn * 2
+        assert np.array_equal(raw2[pmoff:pmoff + h * ldn * 2], raw[pmoff:pmoff + h * ldn * 2])
+        Pm = as_f64(raw[pmoff:pmoff + h * ldn * 2]).reshape(h, ldn)
+        want = np.zeros((h, ldn))
+        want[:, :n] = (M2 * np.asarray(q["W2"], np.float64)).T
+        assert np.array_equal(Pm, want)
 
 
 def test_sample_deterministic():
