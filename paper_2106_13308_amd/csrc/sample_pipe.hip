@@ -157,11 +157,12 @@ typedef __amdgpu_buffer_rsrc_t sp_rsrc_t;
 __device__ inline sp_rsrc_t sp_rsrc(const uint8_t* base, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, bytes, 0x00020000);
 }
-__device__ inline uint4 sp_ld16(sp_rsrc_t r, int voff) {
-  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+// voff: the lane's byte offset (vector register), soff: the tile's (scalar register)
+__device__ inline uint4 sp_ld16(sp_rsrc_t r, int voff, uint32_t soff = 0) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, (int)soff, 0));
 }
-__device__ inline float sp_ld4(sp_rsrc_t r, int voff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+__device__ inline float sp_ld4(sp_rsrc_t r, int voff, uint32_t soff = 0) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)soff, 0));
 }
 
 // one band record of the sweep lane's 4 sites
@@ -403,24 +404,27 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     // in past the last site and unit.
     constexpr int ES = sizeof(WT);
     constexpr int ZT = (ES == 2) ? 4096 : 1024, UT = (ES == 2) ? 2048 : 4096;
-    // (buffer loads: the tile's address stays in scalar registers, the lane's offset is fixed)
+    // Buffer loads: one resource per table (under 4 GB, checked at launch); the tile's byte
+    // offset is a scalar operand and the lane's offset a fixed vector one.
+    const sp_rsrc_t rz = sp_rsrc(ztab, (int)(uint32_t)((int64_t)nb * nzt * ZT));
+    const sp_rsrc_t ru = sp_rsrc(utab, (int)(uint32_t)((int64_t)nb * nut * UT));
     auto load_z = [&](typename F::Z& f, It c) {  // logit tile i of block bb+1
-      const sp_rsrc_t r = sp_rsrc(ztab + (c.bb < nb ? ((int64_t)(c.bb + 1) * nzt + c.i) * ZT : 0), ZT);
+      const uint32_t so = c.bb < nb ? ((uint32_t)(c.bb + 1) * (uint32_t)nzt + (uint32_t)c.i) * ZT : 0u;
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
-        if constexpr (ES == 2) f.a[tt] = sp_ld16(r, tt * 1024 + lane * 16);
-        else f.a[tt] = sp_ld4(r, tt * 256 + lane * 4);
+        if constexpr (ES == 2) f.a[tt] = sp_ld16(rz, tt * 1024 + lane * 16, so);
+        else f.a[tt] = sp_ld4(rz, tt * 256 + lane * 4, so);
       }
     };
     auto load_u = [&](typename F::U& f, It c) {  // push tile i of block bb-1
-      const sp_rsrc_t r = sp_rsrc(utab + (c.bb < nb ? ((int64_t)(c.bb - 1) * nut + c.i) * UT : 0), UT);
+      const uint32_t so = c.bb < nb ? ((uint32_t)(c.bb - 1) * (uint32_t)nut + (uint32_t)c.i) * UT : 0u;
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         if constexpr (ES == 2) {
-          f.a[ks] = sp_ld16(r, ks * 1024 + lane * 16);
+          f.a[ks] = sp_ld16(ru, ks * 1024 + lane * 16, so);
         } else {
-          f.a[ks][0] = sp_ld16(r, ks * 2048 + lane * 32);
-          f.a[ks][1] = sp_ld16(r, ks * 2048 + lane * 32 + 16);
+          f.a[ks][0] = sp_ld16(ru, ks * 2048 + lane * 32, so);
+          f.a[ks][1] = sp_ld16(ru, ks * 2048 + lane * 32 + 16, so);
         }
       }
     };
@@ -467,6 +471,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (k0 + 4 * g4 + e >= lo) cp[e] = acc[e];
+        // (keeps the last masked store from being merged with the full-tile store above,
+        // which would split that one into two)
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
     // logits' B operand.  BF16 weights: each product pairs the three BF16 terms of the
@@ -879,6 +886,10 @@ static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, ui
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
   const SpTables tb = sp_tables(m.n, m.h, m.wdtype);
+  // the helpers address each table through one buffer resource with 32-bit offsets
+  const int64_t nbk = (m.n + SP_T - 1) / SP_T;
+  if (nbk * tb.nzt * tb.zt >= (INT64_C(1) << 32) || nbk * tb.nut * tb.ut >= (INT64_C(1) << 32))
+    return hipErrorInvalidValue;
   const uint8_t* tab = (const uint8_t*)m.band;
   sample_pipe_kernel<WT, PLANES><<<grid, SP_THREADS, smem, st>>>(
       tab + tb.z, tab + tb.u, tb.nzt, tb.nut, m.band, m.b1, m.b2, m.c, m.n, m.h,
