@@ -501,6 +501,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       }
     };
 
+    // the B operand of the bias tile for BF16: ones in units 0-2 of the low columns
+    const uint4 ones_u = (g4 == 0 && lowcol) ? make_uint4(0x3F803F80u, 0x3F80u, 0u, 0u) : make_uint4(0u, 0u, 0u, 0u);
+
     constexpr int PDU = 3;
     constexpr int PDZ = (ES == 2) ? 3 : 6;
     typename F::U fu[PDU];
@@ -595,20 +598,23 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             for (int p = 0; p < PDZ; ++p) {
               uint4 x1[1] = {y1}, x2[1] = {y2};
               if (p + 1 < PDZ) read_pl(p + 1, y1, y2);
-              if (sz[p].bb == b && sz[p].i == 0) {
-                bias_mfma(fz[p], acc);
-                sz[p] = cz;
-                cz = next_z(cz, zlim);
-              } else if (sz[p].bb == b) {
-                const int k0 = KC * (sz[p].i - 1);
-                if (k0 + KC > fprev) {  // the chunk holding f_{b-1}: units from there are the sweep's
-                  bf16_t* e1 = (bf16_t*)&x1[0];
-                  bf16_t* e2 = (bf16_t*)&x2[0];
+              if (sz[p].bb == b) {
+                // the bias tile runs the same two products as a chunk, on (ones, zeros), so
+                // that both kinds of item accumulate in the same registers
+                if (sz[p].i == 0) {
+                  x1[0] = ones_u;
+                  x2[0] = make_uint4(0u, 0u, 0u, 0u);
+                } else {
+                  const int k0 = KC * (sz[p].i - 1);
+                  if (k0 + KC > fprev) {  // the chunk holding f_{b-1}: units from there are the sweep's
+                    bf16_t* e1 = (bf16_t*)&x1[0];
+                    bf16_t* e2 = (bf16_t*)&x2[0];
 #pragma unroll
-                  for (int e = 0; e < 8; ++e) {
-                    const bool keep = k0 + 8 * g4 + e < fprev;
-                    e1[e] = keep ? e1[e] : (bf16_t)0;
-                    e2[e] = keep ? e2[e] : (bf16_t)0;
+                    for (int e = 0; e < 8; ++e) {
+                      const bool keep = k0 + 8 * g4 + e < fprev;
+                      e1[e] = keep ? e1[e] : (bf16_t)0;
+                      e2[e] = keep ? e2[e] : (bf16_t)0;
+                    }
                   }
                 }
                 const bf16x8_t xa = __builtin_bit_cast(bf16x8_t, x1[0]);
