@@ -67,6 +67,7 @@ __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
   return st + 2 * SP_NHW * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
+         2 * SP_MS * SP_T * 2 /*sbf*/ +
          round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? (3 * (size_t)SP_MS + 1) * sp_plda(h) * 2 : 0);
 }
 constexpr size_t SP_LDS_MAX = 160 * 1024;
@@ -220,7 +221,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   };
 
   // ---- prologue: state = b1, block 0's logits = b2, block 0's thresholds, block bounds
-  int* fb = (int*)(sb + 2 * BLK);  // fb[b + 1] = f_b, fb[0] = 0
+  // [2][8][64] the same spins in BF16 (+1, -1, 0): the B operand of the push products as is
+  bf16_t* sbf = (bf16_t*)(sb + 2 * BLK);
+  int* fb = (int*)(sbf + 2 * BLK);  // fb[b + 1] = f_b, fb[0] = 0
   // the bounds are the same for every lane: read them into scalar registers so that all
   // loop control and addressing derived from them stays scalar
   auto fbs = [&](int i) { return __builtin_amdgcn_readfirstlane(fb[i]); };
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         }
       }
       // decisions, spins and s*z of the block
-      uint32_t word = 0;
+      uint32_t word = 0, bw[2] = {0u, 0u};
       float zsv[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -346,10 +349,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
         const float ce = __builtin_amdgcn_fmed3f(fmaf(zr[e], SP_SCALE, tz[e]), 0.f, 1.f);
         const bool up = ce > 0.5f;
         word |= ((j < Tb) ? (up ? 0x01u : 0xFFu) : 0u) << (8 * e);
+        bw[e >> 1] |= ((j < Tb) ? (up ? 0x3F80u : 0xBF80u) : 0u) << (16 * (e & 1));
         zsv[e] = (j < Tb) ? (up ? zr[e] : -zr[e]) : 0.f;
         cp[e] = (j < Tb && up) ? 1.f : 0.f;
       }
       *(uint32_t*)(sb + cur * BLK + ss * SP_T + 4 * g) = word;
+      *(uint2*)(sbf + cur * BLK + ss * SP_T + 4 * g) = make_uint2(bw[0], bw[1]);
       *(float4*)(zs + cur * BLK + ss * SP_T + 4 * g) = make_float4(zsv[0], zsv[1], zsv[2], zsv[3]);
       lds_barrier();
     }
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
     };
     // ---- work items.  Push tiles: block b pushes block b-1's spins into the 16-unit tiles
-    // hw, hw+6, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles hw, hw+6,
+    // hw, hw + SP_NHW, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles hw, hw + SP_NHW,
     // ... of block b+1 to its logits: tile 0 is b2, tile t >= 1 the K chunk t-1 of the units
     // [0, f_{b-1}).  An item is (block, index);
     // block nb marks "past the last item".  Their weight fragments do not depend on the
@@ -433,16 +438,12 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     const int srow = (l16 < SP_MS) ? l16 : SP_MS;
     float* const st_push = st + srow * LDA + 4 * g4;  // + k0: units k0+4g4..+3
     // spins of block b-1 as the push's B operand (+-1 / 0 in BF16), sample column l16
-    auto spin_operand = [&](const int8_t* sblk, bf16x8_t (&sv)[2]) {
+    auto spin_operand = [&](const bf16_t* sblk, bf16x8_t (&sv)[2]) {
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        uint2 raw = make_uint2(0, 0);
-        if (l16 < SP_MS) raw = *(const uint2*)(sblk + l16 * SP_T + 32 * ks + 8 * g4);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int8_t v = (int8_t)(((e < 4 ? raw.x : raw.y) >> (8 * (e & 3))) & 0xFF);
-          sv[ks][e] = __builtin_bit_cast(__bf16, (bf16_t)(v == 0 ? 0 : (v > 0 ? 0x3F80 : 0xBF80)));
-        }
+        uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+        if (l16 < SP_MS) raw = *(const uint4*)(sblk + l16 * SP_T + 32 * ks + 8 * g4);
+        sv[ks] = __builtin_bit_cast(bf16x8_t, raw);
       }
     };
     // state rows k0+4g4..+3 += tile x block spins; rows below lo belong to the sweep
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       };
       if (any_u()) {
         bf16x8_t sv[2];
-        spin_operand(sb + nxt * BLK, sv);
+        spin_operand(sbf + nxt * BLK, sv);
         do {
           // the state of every slot's tile first (a slot of a later block reads rows no
           // one writes during this block), then each used tile's product and store
