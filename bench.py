@@ -101,8 +101,9 @@ def time_steps(made, H, B_, steps, warmup, algo=0, seed=2):
     return ev0.elapsed_time(ev1) / steps, wall / steps, bufs
 
 
-def time_calls(made, H, B_, reps=10, seed=2):
-    """Average duration of each library call of the step, HIP events on its stream."""
+def time_calls(made, H, B_, reps=10, seed=2, names=None):
+    """Average duration of each library call of the step (or of those in names), HIP events on
+    its stream, over reps back-to-back calls after one untimed call."""
     import torch
     from paper_2106_13308_amd import binding as B
     bufs = B.StepBuffers.allocate(made, H, B_)
@@ -126,8 +127,23 @@ def time_calls(made, H, B_, reps=10, seed=2):
     })
     out = {}
     for name, fn in calls.items():
+        if names is not None and name not in names:
+            continue
         fn()
         torch.cuda.synchronize()
+        if name == "sample" and made.band is not None:
+            # in the step the sampler runs right after the refresh rewrote its tables; time
+            # it in that context: events around each sampling launch only
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for e0, e1 in ev:
+                made.refresh()
+                e0.record()
+                fn()
+                e1.record()
+            torch.cuda.synchronize()
+            out[name] = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
+            continue
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
@@ -298,6 +314,10 @@ def main():
     ms, wall_ms, bufs = time_steps(made, H, w.B, a.steps, a.warmup)
     log(f"bf16 incremental step: {ms:.3f} ms (event), {wall_ms * 1e3:.3f} ms (wall)")
     if a.profile_only:
+        # then the sampling call as the roofline times it (one untimed launch, then five
+        # launches each right after a refresh), so that the trace holds that loop too
+        calls = time_calls(made, H, w.B, reps=5, names=("sample",))
+        log("per-call ms (profiled loop): " + json.dumps({k: round(v, 4) for k, v in calls.items()}))
         return
     value = w.B / (ms / 1e3)
     st = B.stats_to_dict(bufs.stats)
