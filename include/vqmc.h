@@ -245,9 +245,10 @@ int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const 
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,
  * E, stats, coef and the gradient (dP, db1, db2).  With algo 0 and a band this is
- * vqmc_sample_fwd, then the energy and statistics on a library-owned auxiliary stream
- * (default priority), then vqmc_backward_sampled; otherwise the gradient recomputes the
- * forward pass as vqmc_logprob_backward does. */
+ * vqmc_sample_fwd, the energy, the statistics and vqmc_backward_sampled, all on `stream`;
+ * otherwise the gradient recomputes the forward pass as vqmc_logprob_backward does, its
+ * first product overlapping the energy and statistics, which then run on a library-owned
+ * auxiliary stream (default priority). */
 int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed,
               uint64_t step, int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E,
               vqmc_stats* stats, float* coef, float* dP, float* db1, float* db2, void* ws,
