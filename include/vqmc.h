@@ -216,6 +216,7 @@ int vqmc_sample_plain(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t ste
 
 /* Local energy of a diagonal Hamiltonian (Sec. 2.1 local energy = H_xx).  E is int64
  * for CSR_INT (exact), double otherwise (FP64 accumulation of exact products).
+ * S: B x ld(n) int8 spins (+1/-1; columns >= n are ignored), 16-byte aligned, else EINVAL.
  * The dense kind needs vqmc_energy_workspace_bytes() of workspace (CSR kinds need none;
  * ws may then be NULL). */
 int vqmc_energy(const vqmc_hamiltonian* H, const int8_t* S, int64_t B, void* E, void* ws,

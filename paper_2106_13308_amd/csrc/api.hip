@@ -49,8 +49,8 @@ size_t step_pm_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
 }
 
 // One auxiliary stream (default priority) and two events per device, created on first
-// use and kept for the life of the process: vqmc_step runs the energy and statistics
-// on it while the main stream starts the backward.
+// use and kept for the life of the process: vqmc_step without a band runs the energy and
+// statistics on it while the main stream starts the recomputing backward.
 struct StepAux {
   hipStream_t stream = nullptr;
   hipEvent_t sampled = nullptr, stats_done = nullptr;
@@ -262,6 +262,8 @@ int vqmc_energy(const vqmc_hamiltonian* H, const int8_t* S, int64_t B, void* E, 
   int r = check_ham(H);
   if (r) return r;
   if (B < 1 || !S || !E) return fail(VQMC_EINVAL, "bad batch arguments");
+  // the kernels read each spin row in 16-byte (CSR) or 8-byte (dense) pieces
+  if ((uintptr_t)S & 15) return fail(VQMC_EINVAL, "S must be 16-byte aligned");
   const size_t need = energy_workspace_bytes(*H, B);
   if (ws_bytes < need || (need && !ws)) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   return hip_status(launch_energy(*H, S, B, E, ws, (hipStream_t)stream), "vqmc_energy");

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(EB_THREADS) void energy_csr_bits_kernel(int n, int6
 // FP64 MFMA 16x16x4 on exact operands (+-1 and float32 J widened to double).
 // Each workgroup writes one partial per sample; a second pass sums the partials of
 // the row tiles in a fixed order.
-constexpr int DT = 64, DK = 16;
+constexpr int DT = 64, DK = 32;
+constexpr int DKT = DK / 4;  // stage columns per thread (4 threads per row)
 __global__ __launch_bounds__(256) void energy_dense_kernel(int n, int64_t lds, const float* __restrict__ J,
                                                             const int8_t* __restrict__ S, int64_t B,
                                                             double* __restrict__ part) {
@@ -156,20 +157,42 @@ __global__ __launch_bounds__(256) void energy_dense_kernel(int n, int64_t lds, c
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (doublex4_t){0, 0, 0, 0};
   const int jbeg = (i0 / DK) * DK;
-  for (int j0 = jbeg; j0 < n; j0 += DK) {
-    // stage: 64 rows x 16 columns each, 4 elements per thread
-    {
-      const int r = t >> 2, q = (t & 3) * 4;
+  // stage: 64 rows x DK columns of each operand, DKT elements per thread.  The next stage's
+  // values are loaded into registers before the current stage is multiplied, so the loads
+  // overlap the products.
+  const int r = t >> 2, q = (t & 3) * DKT;
+  const int64_t bq = m0 + r;
+  const int iq = i0 + r;
+  uint2 sv = make_uint2(0u, 0u);  // DKT = 8 spins (int8), columns j0 + q .. (inside the padded row)
+  float jv[DKT];
+  const bool vec = (n & 3) == 0 && ((uintptr_t)J & 15) == 0;  // rows of J start 16-byte aligned
+  auto fetch = [&](int j0) {
+    sv = (bq < B) ? *(const uint2*)(S + bq * lds + j0 + q) : make_uint2(0u, 0u);
+    const int jq = j0 + q;
+    if (vec && iq < n && jq + DKT <= n) {  // eight columns inside the row: two 16-byte loads
+      const float4 a0 = *(const float4*)(J + (int64_t)iq * n + jq), a1 = *(const float4*)(J + (int64_t)iq * n + jq + 4);
+      const float v8[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = j0 + q + e;
-        const int64_t b = m0 + r;
-        Ss[r][q + e] = (b < B && j < n) ? (double)S[b * lds + j] : 0.0;
-        const int i = i0 + r;
-        Js[r][q + e] = (i < n && j < n && j > i) ? (double)J[(int64_t)i * n + j] : 0.0;
+      for (int e = 0; e < DKT; ++e) jv[e] = (jq + e > iq) ? v8[e] : 0.f;
+    } else {
+#pragma unroll
+      for (int e = 0; e < DKT; ++e) {
+        const int j = jq + e;
+        jv[e] = (iq < n && j < n && j > iq) ? J[(int64_t)iq * n + j] : 0.f;
       }
     }
+  };
+  static_assert(DKT == 8, "the spin fetch reads eight bytes");
+  fetch(jbeg);
+  for (int j0 = jbeg; j0 < n; j0 += DK) {
+#pragma unroll
+    for (int e = 0; e < DKT; ++e) {
+      const uint32_t w = (e < 4) ? sv.x : sv.y;
+      Ss[r][q + e] = (j0 + q + e < n) ? (double)(int8_t)(w >> (8 * (e & 3))) : 0.0;
+      Js[r][q + e] = (double)jv[e];
+    }
     __syncthreads();
+    if (j0 + DK < n) fetch(j0 + DK);
 #pragma unroll
     for (int kk = 0; kk < DK; kk += 4) {
       double a[2], bb[2];
