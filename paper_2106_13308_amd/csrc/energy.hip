@@ -133,6 +133,122 @@ __global__ __launch_bounds__(EB_THREADS) void energy_csr_bits_kernel(int n, int6
   }
 }
 
+// ---------------------------------------------------------------- sparse, byte lanes
+// Integer weights, same rows and sums as above, with each site staged as eight bytes (byte q =
+// [s_q = +1]) instead of eight bits: then w * site adds w to all eight samples' row sums Y_q at
+// once, each in its own byte, as two 32-bit multiply-adds per edge.  A byte holds Y_q exactly
+// while the row's weights are non-negative and sum to at most 255 (every Max-Cut graph with
+// small integer weights); a row outside that range is summed again sample by sample.
+template <bool RP_LDS>
+__global__ __launch_bounds__(EB_THREADS) void energy_csr_bytes_kernel(int n, int64_t lds,
+                                                                     const int64_t* __restrict__ rowptr,
+                                                                     const int32_t* __restrict__ col,
+                                                                     const int32_t* __restrict__ w,
+                                                                     const int8_t* __restrict__ S, int64_t B,
+                                                                     int nsp, int64_t* __restrict__ E) {
+  // nsp uint2 site words (n rounded up to 16), then the row pointer (n + 1 int32, if staged),
+  // then scratch
+  extern __shared__ __attribute__((aligned(16))) uint8_t shb[];
+  uint2* sw = (uint2*)shb;
+  int32_t* rp = (int32_t*)(shb + (size_t)nsp * 8);
+  int64_t* red = (int64_t*)(shb + (size_t)nsp * 8 + (RP_LDS ? round_up((int64_t)(n + 1) * 4, 16) : 0));
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * EMSE;
+  const int nq = (int)min<int64_t>(EMSE, B - b0);
+  // sixteen sites per item: one 16-byte piece of each sample's row (inside the padded row),
+  // gathered into a bit per sample, then spread to a byte per sample
+  for (int c0 = t; c0 < nsp / 16; c0 += EB_THREADS) {
+    uint32_t a[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < EMSE; ++q) {
+      if (q < nq) {
+        const uint4 v = *(const uint4*)(S + (b0 + q) * lds + 16 * c0);
+        a[0] |= ((~v.x >> 7) & 0x01010101u) << q;
+        a[1] |= ((~v.y >> 7) & 0x01010101u) << q;
+        a[2] |= ((~v.z >> 7) & 0x01010101u) << q;
+        a[3] |= ((~v.w >> 7) & 0x01010101u) << q;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const uint32_t m = (a[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      // bit k of a 4-bit value to bit 8k: the four shifted copies (x 1, 2^7, 2^14, 2^21) do not
+      // overlap, so the product carries nothing
+      sw[16 * c0 + e] = make_uint2(((m & 0xFu) * 0x00204081u) & 0x01010101u, ((m >> 4) * 0x00204081u) & 0x01010101u);
+    }
+  }
+  if constexpr (RP_LDS)
+    for (int i = t; i <= n; i += EB_THREADS) rp[i] = (int32_t)rowptr[i];
+  __syncthreads();
+  auto rowp = [&](int i) -> int64_t {
+    if constexpr (RP_LDS) return rp[i];
+    else return rowptr[i];
+  };
+  int64_t acc[EMSE];
+#pragma unroll
+  for (int q = 0; q < EMSE; ++q) acc[q] = 0;
+  for (int i = t; i < n; i += EB_THREADS) {
+    const int64_t e0 = rowp(i), e1 = rowp(i + 1);
+    uint32_t ylo = 0u, yhi = 0u;  // Y_q in byte q (q < 4 in ylo)
+    int64_t wsum = 0;
+    bool small = true;
+    int64_t e = e0;
+    for (; e + 1 < e1; e += 2) {  // two edges per step: their loads are issued together
+      const int j0 = col[e], j1 = col[e + 1];
+      const int32_t w0 = w[e], w1 = w[e + 1];
+      const uint2 s0 = sw[j0], s1 = sw[j1];
+      wsum += (int64_t)w0 + (int64_t)w1;
+      small = small && (uint32_t)w0 <= 255u && (uint32_t)w1 <= 255u;
+      ylo += (uint32_t)w0 * s0.x + (uint32_t)w1 * s1.x;
+      yhi += (uint32_t)w0 * s0.y + (uint32_t)w1 * s1.y;
+    }
+    if (e < e1) {
+      const int32_t w0 = w[e];
+      const uint2 s0 = sw[col[e]];
+      wsum += (int64_t)w0;
+      small = small && (uint32_t)w0 <= 255u;
+      ylo += (uint32_t)w0 * s0.x;
+      yhi += (uint32_t)w0 * s0.y;
+    }
+    int64_t ya[EMSE];
+    if (small && wsum <= 255) {
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q) ya[q] = (int64_t)(((q < 4 ? ylo : yhi) >> (8 * (q & 3))) & 0xFFu);
+    } else {  // the row again, one int64 sum per sample
+#pragma unroll
+      for (int q = 0; q < EMSE; ++q) ya[q] = 0;
+      for (int64_t f = e0; f < e1; ++f) {
+        const int64_t wf = w[f];
+        const uint2 sf = sw[col[f]];
+#pragma unroll
+        for (int q = 0; q < EMSE; ++q) ya[q] += (((q < 4 ? sf.x : sf.y) >> (8 * (q & 3))) & 1u) ? wf : 0;
+      }
+    }
+    const uint2 si = sw[i];
+#pragma unroll
+    for (int q = 0; q < EMSE; ++q) {
+      const int64_t r = 2 * ya[q] - wsum;
+      acc[q] += (((q < 4 ? si.x : si.y) >> (8 * (q & 3))) & 1u) ? r : -r;
+    }
+  }
+  // per sample: fixed butterfly over the wave, then the sixteen waves in order
+  constexpr int NW = EB_THREADS / 64;
+#pragma unroll
+  for (int q = 0; q < EMSE; ++q) {
+    int64_t v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[q * NW + wv] = v;
+  }
+  __syncthreads();
+  if (t < nq) {
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[t * NW + k];
+    E[b0 + t] = s;
+  }
+}
+
 // ---------------------------------------------------------------- dense J (FP64)
 // E_b = sum_i s_bi * y_bi with y_bi = sum_{j>i} J_ij s_bj (strict upper triangle only).
 // Tile: 64 samples x 64 rows i per workgroup, K loop over j >= i0 in chunks of 32,
@@ -293,6 +409,18 @@ hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, 
     e = hipGetLastError();
   };
   if (H.kind == VQMC_H_CSR_INT) {
+    // byte lanes when the site words fit in one CU's LDS (the row pointer too if it fits)
+    const size_t swb = (size_t)nst * 8;
+    if (H.nnz < (int64_t)1 << 31 && swb + redb <= 160 * 1024) {
+      const bool rpl = swb + rpb + redb <= 160 * 1024;
+      const size_t sb = swb + (rpl ? rpb : 0) + redb;
+      auto kern = rpl ? energy_csr_bytes_kernel<true> : energy_csr_bytes_kernel<false>;
+      if ((e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sb)) !=
+          hipSuccess)
+        return e;
+      kern<<<grid, EB_THREADS, sb, st>>>(n, lds, H.rowptr, H.col, (const int32_t*)H.w, S, B, nst, (int64_t*)E);
+      return hipGetLastError();
+    }
     if (rp_lds) go(energy_csr_bits_kernel<int32_t, int64_t, true>, (const int32_t*)H.w, (int64_t*)E);
     else go(energy_csr_bits_kernel<int32_t, int64_t, false>, (const int32_t*)H.w, (int64_t*)E);
   } else {

@@ -110,6 +110,40 @@ def test_energy_csr_int_large_weights():
     assert np.array_equal(E, ref)
 
 
+def test_energy_csr_int_mixed_rows():
+    """Rows whose weights are non-negative and sum to at most 255 use byte lanes, the others
+    (a negative weight, a sum of 256 or more) the per-sample row sums: both in one graph."""
+    _banner("energy csr int mixed rows")
+    n, B = 500, 37
+    edges = inputs.random_regular_graph(n, 8, 7)
+    w = inputs.integer_weights(len(edges), 1, 5, 8)
+    rng = np.random.default_rng(9)
+    big = rng.choice(len(w), size=len(w) // 10, replace=False)
+    w[big[: len(big) // 3]] = 200          # rows above 255
+    w[big[len(big) // 3: 2 * len(big) // 3]] = -3  # negative weights
+    w[big[2 * len(big) // 3:]] = 0
+    # one row summing to exactly 255 and one to exactly 256 (first row of the CSR ordering
+    # that owns at least two edges)
+    order = np.lexsort((edges[:, 1], edges[:, 0]))
+    rows = edges[order, 0]
+    r0 = rows[0]
+    idx0 = order[rows == r0]
+    w[idx0] = 0
+    w[idx0[0]] = 255
+    r1 = rows[len(idx0)]
+    idx1 = order[rows == r1]
+    w[idx1] = 0
+    w[idx1[0]] = 255
+    w[idx1[1]] = 1
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    S_np = inputs.random_spins(B, n, 10)
+    S = torch.zeros((B, B_.ld(n)), dtype=torch.int8, device=DEV)
+    S[:, :n] = torch.from_numpy(S_np).to(DEV)
+    E = B_.energy(H, S).cpu().numpy()
+    ref = oen.energy_edges(edges, w, S_np)
+    assert E.dtype == np.int64 and np.array_equal(E, ref)
+
+
 def test_energy_csr_f32_and_dense():
     _banner("energy csr f32 / dense")
     n, B = 300, 130
