@@ -96,6 +96,9 @@ def test_validation_rejects_before_launch(B):
     assert lib.vqmc_energy(ctypes.byref(H), fake, 8, fake, None, 0, None) == B.EINVAL
     Hd = B.HamC(8, B.H_DENSE_F32, 0, None, None, None, fake)
     assert lib.vqmc_energy(ctypes.byref(Hd), fake, 8, fake, None, 0, None) == B.EWORKSPACE
+    Hi = B.HamC(8, B.H_CSR_INT, 3, fake, fake, fake, None)
+    assert lib.vqmc_energy(ctypes.byref(Hi), fake + 8, 8, fake, None, 0, None) == B.EINVAL  # spins misaligned
+    assert b"16-byte" in lib.vqmc_last_error()
     Hc = B.HamC(9, B.H_CSR_INT, 3, fake, fake, fake, None)
     assert lib.vqmc_step(ctypes.byref(ok), ctypes.byref(Hc), 8, 0, 0, 0, 0, fake, fake, fake, fake, fake,
                          fake, fake, fake, fake, 1 << 30, None) == B.EINVAL  # n mismatch
