@@ -86,6 +86,22 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// sum_p part[p][i] over nparts rows of stride floats: the loads of eight parts are issued
+// together and summed in a fixed order (four running sums, then ((s0 + s1) + (s2 + s3))).
+__device__ inline float sum_parts(const float* __restrict__ part, int nparts, int64_t stride, int64_t i) {
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  int p = 0;
+  for (; p + 8 <= nparts; p += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(p + u) * stride + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u & 3] += v[u];
+  }
+  for (; p < nparts; ++p) s[p & 3] += part[(int64_t)p * stride + i];
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 // ---------------------------------------------------------------- wave reductions (wave64)
 #define VQMC_DPP(v, ctrl) \
   __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false))

@@ -678,23 +678,12 @@ __global__ __launch_bounds__(256) void grad_out_kernel(const float* __restrict__
 }
 
 // ---------------------------------------------------------------- reductions
-// out[i] = sum_p part[p][i]; the loads of eight parts are issued together and summed in
-// a fixed order (four running sums, then ((s0 + s1) + (s2 + s3))).
+// out[i] = sum_p part[p][i] in the fixed order of sum_parts
 __global__ void sum_rows_kernel(const float* __restrict__ part, int nparts, int64_t stride, int64_t len,
                                 float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
-  float s[4] = {0.f, 0.f, 0.f, 0.f};
-  int p = 0;
-  for (; p + 8 <= nparts; p += 8) {
-    float v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(p + u) * stride + i];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u & 3] += v[u];
-  }
-  for (; p < nparts; ++p) s[p & 3] += part[(int64_t)p * stride + i];
-  out[i] = (s[0] + s[1]) + (s[2] + s[3]);
+  out[i] = sum_parts(part, nparts, stride, i);
 }
 
 __global__ void fill_kernel(float* __restrict__ x, int64_t len, float v) {
@@ -855,8 +844,9 @@ static hipError_t backward_sampled_t(const vqmc_made& m, const int8_t* S, int64_
       Pm = (uint8_t*)m.band + po;
       ready = true;
     }
-    e = launch_backward_products2(m, B, G, Gt, St, Rt, Dt, (bf16_t*)Pm, db1_part, dP, st, ready);
-    if (e != hipSuccess) return e;
+    // (the weight-gradient launch also sums the bias-gradient partials)
+    return launch_backward_products2(m, B, G, Gt, St, Rt, Dt, (bf16_t*)Pm, db1_part, g.mt_h, db2_part, g.mt_o, dP,
+                                     db1, db2, st, ready);
   } else {
     bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
                                                                g.ldB, db1_part, g.ldh);

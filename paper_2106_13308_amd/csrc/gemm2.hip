@@ -333,7 +333,17 @@ constexpr int WB_BM = 128, WB_BN = 128, WB_WGM = 4, WB_WGN = 4;
 __global__ __launch_bounds__(64 * WB_WGM * WB_WGN) void bwd_weight2_kernel(const bf16_t* __restrict__ Gt, const bf16_t* __restrict__ Rt,
                                                            const bf16_t* __restrict__ St, const bf16_t* __restrict__ Dt,
                                                            int64_t ldB, const int32_t* __restrict__ c, int n, int h,
-                                                           float* __restrict__ dP) {
+                                                           float* __restrict__ dP,
+                                                           const float* __restrict__ db1_part, int np1, int64_t ldh,
+                                                           const float* __restrict__ db2_part, int np2, int64_t ldn,
+                                                           float* __restrict__ db1, float* __restrict__ db2) {
+  // the bias gradients first: thread i of the launch sums the partials of db2[i] (i < n) or of
+  // db1[i - n] (the grid has more than n + h threads)
+  {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) db2[i] = sum_parts(db2_part, np2, ldn, i);
+    else if (i < n + h) db1[i - n] = sum_parts(db1_part, np1, ldh, i - n);
+  }
   using E = G2<WB_BM, WB_BN, WB_WGM, WB_WGN>;
   __shared__ __attribute__((aligned(16))) uint4 A0[WB_BM * 8], A1[WB_BM * 8], A2[WB_BM * 8], A3[WB_BM * 8];
   __shared__ __attribute__((aligned(16))) uint4 B0[WB_BN * 8], B1[WB_BN * 8], B2[WB_BN * 8], B3[WB_BN * 8];
@@ -380,16 +390,18 @@ hipError_t launch_mask_w2t(const vqmc_made& m, bf16_t* Pm, hipStream_t st) {
 
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t* G, const bf16_t* Gt,
                                      const bf16_t* St, const bf16_t* Rt, bf16_t* Dt, bf16_t* Pm,
-                                     float* db1_part, float* dP, hipStream_t st, bool pm_ready) {
+                                     float* db1_part, int np1, const float* db2_part, int np2, float* dP, float* db1,
+                                     float* db2, hipStream_t st, bool pm_ready) {
   const int64_t ldn = round_up(m.n, kPad), ldB = round_up(B, kPad), ldh = round_up(m.h, kPad);
   hipError_t e = pm_ready ? hipSuccess : launch_mask_w2t(m, Pm, st);
   if (e != hipSuccess) return e;
   bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 64 * HB_WGM * HB_WGN, 0, st>>>(
       G, ldn, Pm, m.c, m.n, m.h, B, Rt, Dt, ldB, db1_part, ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_weight2_kernel<<<xcd_grid((m.n + WB_BM - 1) / WB_BM, (m.h + WB_BN - 1) / WB_BN), 64 * WB_WGM * WB_WGN, 0,
-                       st>>>(
-      Gt, Rt, St, Dt, ldB, m.c, m.n, m.h, dP);
+  const unsigned wgrid = xcd_grid((m.n + WB_BM - 1) / WB_BM, (m.h + WB_BN - 1) / WB_BN);
+  if ((int64_t)wgrid * 64 * WB_WGM * WB_WGN < (int64_t)m.n + m.h) return hipErrorInvalidValue;  // never: >= 64 n threads
+  bwd_weight2_kernel<<<wgrid, 64 * WB_WGM * WB_WGN, 0, st>>>(Gt, Rt, St, Dt, ldB, m.c, m.n, m.h, dP, db1_part, np1,
+                                                             ldh, db2_part, np2, ldn, db1, db2);
   return hipGetLastError();
 }
 

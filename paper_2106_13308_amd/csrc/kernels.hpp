@@ -58,9 +58,11 @@ hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t 
                                    void* Pm, hipStream_t st);
 // gemm2.hip: BF16 backward products on the direct-to-LDS engine; Pm: h x ld(n) bf16 scratch
 size_t mask_w2t_bytes(int n, int h);
+// db1_part (np1 rows of ld(h)) and db2_part (np2 rows of ld(n)) are summed into db1 and db2
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Gt,
                                      const uint16_t* St, const uint16_t* Rt, uint16_t* Dt, uint16_t* Pm,
-                                     float* db1_part, float* dP, hipStream_t st, bool pm_ready);
+                                     float* db1_part, int np1, const float* db2_part, int np2, float* dP, float* db1,
+                                     float* db2, hipStream_t st, bool pm_ready);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,
