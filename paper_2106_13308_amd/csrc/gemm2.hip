@@ -10,8 +10,8 @@
 // copy of P^T (W1 entries zeroed); the second's masks select output elements.
 //
 // Engine: a BM x BN tile per workgroup of WGM x WGN waves (each BM/WGM x BN/WGN as 16x16 MFMA
-// blocks, v_mfma_f32_16x16x32_bf16, FP32 accumulation; eight waves, two per SIMD, so one wave's
-// loads and barrier waits overlap the other's products).  K advances 64 elements (one 128-byte
+// blocks, v_mfma_f32_16x16x32_bf16, FP32 accumulation; eight or sixteen waves, two or four per
+// SIMD, so one wave's loads and barrier waits overlap the others' products).  K advances 64 elements (one 128-byte
 // row segment) per stage; three (or four) stages rotate through separate LDS buffers.  Each
 // stage is brought in by global_load_lds_dwordx4 (16 bytes per lane straight into LDS, no
 // registers): a wave instruction fills 8 rows, lane l the 16-byte chunk l % 8 of row l / 8, from

@@ -28,14 +28,14 @@
 // and the block after (all using it), so the sweep itself finishes both products that
 // depend on the block it has just drawn, and one barrier per block suffices.
 //
-// Workgroup = 8 samples, 8 waves.  Waves 0-1 sweep block b, four samples each, lane
+// Workgroup = 8 samples, 12 waves.  Waves 0-1 sweep block b, four samples each, lane
 // (sample s, group g) holding sites 4g..4g+3 of sample s (and of the next block) in
-// registers; a unit's dot product is a 16-lane DPP reduction.  Waves 2-7 meanwhile push
-// block b-1's spins into the units completing after block b, compute the part of block
-// b+1's logits that only needs units complete before block b, draw block b+1's uniforms,
-// and write out block b-1's spins and log-probabilities.  Two waves per SIMD let the
-// helpers' memory latency overlap; the two roles run separate loops with one barrier per
-// block each.
+// registers; a unit's dot product is a 16-lane DPP reduction.  The ten helper waves 2-11
+// meanwhile push block b-1's spins into the units completing after block b, compute the
+// part of block b+1's logits that only needs units complete before block b, draw block
+// b+1's uniforms (helpers 0-1) and write out block b-1's spins and log-probabilities
+// (helpers 2-3).  Three waves per SIMD let the helpers' memory latency overlap; the two
+// roles run separate loops with one barrier per block each.
 //
 // Arithmetic: FP32 state and logits.  BF16 weights: the products run on
 // v_mfma_f32_16x16x32_bf16, exact for the +-1 spins of the push and with every FP32
