@@ -60,6 +60,7 @@ __host__ __device__ inline int sp_plda(int h) { return (int)round_up(h, 32) + 8;
 constexpr int SP_NSW = 2;          // sweep waves (four samples each)
 constexpr int SP_RS = SP_T + 4;    // row stride of the helpers' partial logits: samples on distinct banks
 constexpr int SP_NHW = 10;         // helper waves
+constexpr int SP_ZH0 = 4;          // first helper that takes logit tiles
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
 __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
@@ -396,12 +397,16 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       }
       return c;
     };
+    // logit tiles go to the helpers from SP_ZH0 on (the first ones draw the thresholds and
+    // write out the swept block); the others hold no logit item
+    const int zh = hw - SP_ZH0;
     auto next_z = [&](It c, int& lim) {  // lim: chunk count of the cursor's block
-      c.i += SP_NHW;
+      if (zh < 0) return It{nb, 0};
+      c.i += SP_NHW - SP_ZH0;
       while (c.i >= lim) {
         if (++c.bb + 1 >= nb) return It{nb, 0};
         lim = 1 + (fbs(c.bb) + KC - 1) / KC;  // the bias tile and the chunks of [0, f_{bb-1})
-        c.i = hw;
+        c.i = zh;
       }
       return c;
     };
