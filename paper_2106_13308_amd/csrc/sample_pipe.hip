@@ -61,13 +61,14 @@ constexpr int SP_NSW = 2;          // sweep waves (four samples each)
 constexpr int SP_RS = SP_T + 4;    // row stride of the helpers' partial logits: samples on distinct banks
 constexpr int SP_NHW = 10;         // helper waves
 constexpr int SP_ZH0 = 4;          // first helper that takes logit tiles
+constexpr int SP_NZ = SP_NHW - SP_ZH0;  // helpers with partial logits
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
 __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
   const size_t st = (size_t)(SP_MS + 1) * sp_lda(h) * 4;   // + a spare row of zeros
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
-  return st + 2 * SP_NHW * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
+  return st + 2 * SP_NZ * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
          2 * SP_MS * SP_T * 2 /*sbf*/ +
          round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? (3 * (size_t)SP_MS + 1) * sp_plda(h) * 2 : 0);
 }
@@ -191,8 +192,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
                                    // row 8: zeros, the rows of the products' unused columns
   constexpr int RB = SP_MS * SP_RS;
-  float* red = st + (SP_MS + 1) * LDA;  // [2][10][8][68] helpers' partial logits of a block (+ b2)
-  float* th = red + 2 * SP_NHW * RB;   // [2][8][64] -logit(u) * 2^100
+  float* red = st + (SP_MS + 1) * LDA;  // [2][SP_NZ][8][68] logit helpers' partial logits of a block (+ b2)
+  float* th = red + 2 * SP_NZ * RB;    // [2][8][64] -logit(u) * 2^100
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
   int8_t* sb = (int8_t*)(zs + 2 * BLK);  // [2][8][64] spins of a swept block (0 past n)
 
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   if constexpr (PLANES) {
     for (int i = t; i < PLDA; i += SP_THREADS) pl[3 * SP_MS * PLDA + i] = 0;
   }
-  for (int i = t; i < SP_NHW * RB; i += SP_THREADS) {  // block 0's logits: b2 in helper 0's slot
+  for (int i = t; i < SP_NZ * RB; i += SP_THREADS) {  // block 0's logits: b2 in the first slot
     const int j = i % SP_RS;
     red[i] = (i < RB && j < SP_T && j < n) ? b2[j] : 0.f;
   }
@@ -272,10 +273,10 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       const int cur = b & 1;
       float zr[4], tz[4];
       {
-        const float* r0 = red + cur * SP_NHW * RB + ss * SP_RS + 4 * g;
+        const float* r0 = red + cur * SP_NZ * RB + ss * SP_RS + 4 * g;
         float4 acc4 = *(const float4*)r0;
 #pragma unroll
-        for (int q = 1; q < SP_NHW; ++q) {
+        for (int q = 1; q < SP_NZ; ++q) {
           const float4 x = *(const float4*)(r0 + q * RB);
           acc4.x += x.x; acc4.y += x.y; acc4.z += x.z; acc4.w += x.w;
         }
@@ -378,8 +379,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
     };
     // ---- work items.  Push tiles: block b pushes block b-1's spins into the 16-unit tiles
-    // hw, hw + SP_NHW, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles hw, hw + SP_NHW,
-    // ... of block b+1 to its logits: tile 0 is b2, tile t >= 1 the K chunk t-1 of the units
+    // hw, hw + SP_NHW, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles
+    // hw - SP_ZH0, hw - SP_ZH0 + SP_NZ, ... of block b+1 to its logits (helpers from SP_ZH0 on;
+    // each writes its partial logits to its own slot): tile 0 is b2, tile t >= 1 the K chunk t-1 of the units
     // [0, f_{b-1}).  An item is (block, index);
     // block nb marks "past the last item".  Their weight fragments do not depend on the
     // draws, so each kind has a ring of PD slots that runs ahead through the items of later
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 
       // block b+1's logits over the units complete before block b, [0, fprev) (the units of
       // block b are added by the sweep)
-      if (has_next) {
+      if (has_next && zh >= 0) {
         floatx4_t acc[4];
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) acc[tt] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             for (int e = 0; e < 4; ++e) acc[tt][e] += VQMC_DPP(acc[tt][e], 0x128);  // row_ror:8
         }
         if (lowcol) {
-          float* dst = red + nxt * SP_NHW * RB + hw * RB + l16 * SP_RS + 4 * g4;
+          float* dst = red + nxt * SP_NZ * RB + zh * RB + l16 * SP_RS + 4 * g4;
 #pragma unroll
           for (int tt = 0; tt < 4; ++tt)
             *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
