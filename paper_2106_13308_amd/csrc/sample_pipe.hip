@@ -31,10 +31,10 @@
 // Workgroup = 8 samples, 12 waves.  Waves 0-1 sweep block b, four samples each, lane
 // (sample s, group g) holding sites 4g..4g+3 of sample s (and of the next block) in
 // registers; a unit's dot product is a 16-lane DPP reduction.  The ten helper waves 2-11
-// meanwhile push block b-1's spins into the units completing after block b, compute the
-// part of block b+1's logits that only needs units complete before block b, draw block
-// b+1's uniforms (helpers 0-1) and write out block b-1's spins and log-probabilities
-// (helpers 2-3).  Three waves per SIMD let the helpers' memory latency overlap; the two
+// meanwhile push block b-1's spins into the units completing after block b (all helpers),
+// compute the part of block b+1's logits that only needs units complete before block b
+// (helpers 4-9), draw block b+1's uniforms (helpers 0-1) and write out block b-1's spins and
+// log-probabilities (helpers 2-3).  Three waves per SIMD let the helpers' memory latency overlap; the two
 // roles run separate loops with one barrier per block each.
 //
 // Arithmetic: FP32 state and logits.  BF16 weights: the products run on
