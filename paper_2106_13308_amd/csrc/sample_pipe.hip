@@ -60,15 +60,17 @@ __host__ __device__ inline int sp_plda(int h) { return (int)round_up(h, 32) + 8;
 constexpr int SP_NSW = 2;          // sweep waves (four samples each)
 constexpr int SP_RS = SP_T + 4;    // row stride of the helpers' partial logits: samples on distinct banks
 constexpr int SP_NHW = 10;         // helper waves
-constexpr int SP_ZH0 = 4;          // first helper that takes logit tiles
-constexpr int SP_NZ = SP_NHW - SP_ZH0;  // helpers with partial logits
+// First helper that takes logit tiles: with the activation planes in LDS (cheap logit tiles)
+// helpers 0-3 keep to their other work; without them every helper shares the logit tiles.
+__host__ __device__ constexpr int sp_zh0(bool planes) { return planes ? 4 : 0; }
+__host__ __device__ constexpr int sp_nz(bool planes) { return SP_NHW - sp_zh0(planes); }  // partial-logit slots
 constexpr int SP_THREADS = 64 * (SP_NSW + SP_NHW);
 
 __host__ inline size_t sp_smem_bytes(int n, int h, bool planes) {
   const size_t st = (size_t)(SP_MS + 1) * sp_lda(h) * 4;   // + a spare row of zeros
   const size_t blk = (size_t)SP_MS * SP_T * 4;        // one [8][64] float buffer
   const size_t nb = (size_t)(n + SP_T - 1) / SP_T;
-  return st + 2 * SP_NZ * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
+  return st + 2 * sp_nz(planes) * (size_t)SP_MS * SP_RS * 4 /*red*/ + 2 * blk /*th*/ + 2 * blk /*zs*/ + 2 * SP_MS * SP_T /*sb*/ +
          2 * SP_MS * SP_T * 2 /*sbf*/ +
          round_up((int64_t)(nb + 1) * 4, 16) /*fb*/ + (planes ? (3 * (size_t)SP_MS + 1) * sp_plda(h) * 2 : 0);
 }
@@ -192,6 +194,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   float* st = (float*)smem;        // [8][LDA]  state A; final pre-activation once complete
                                    // row 8: zeros, the rows of the products' unused columns
   constexpr int RB = SP_MS * SP_RS;
+  constexpr int SP_ZH0 = sp_zh0(PLANES), SP_NZ = sp_nz(PLANES);
   float* red = st + (SP_MS + 1) * LDA;  // [2][SP_NZ][8][68] logit helpers' partial logits of a block (+ b2)
   float* th = red + 2 * SP_NZ * RB;    // [2][8][64] -logit(u) * 2^100
   float* zs = th + 2 * BLK;        // [2][8][64] s_d z_d of a swept block
