@@ -173,6 +173,9 @@ size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype);
  *   push tiles, nb x ceil(h / 16) tiles: tile t of block q holds P[64q + d][16t + u] (the
  *     first-layer weights from the block's sites), [2 halves][64 lanes][8 sites], lane =
  *     16 g + u, sites 32 half + 8 g .. + 7.
+ * BF16 only, after the push tiles (from the next multiple of 256 bytes): the masked copy of
+ * P^T that the backward's hidden adjoint reads, h x ld(n) BF16, Pm[k][d] = P[d][k] where unit
+ * k feeds site d (k < c[d]), else 0 (also for d >= n).
  * band: vqmc_band_bytes(n, h, m->wdtype) bytes (device, 16-byte aligned), overwritten.
  * Needs m->P, m->Pt, m->b2 and m->c; m->band is ignored. */
 int vqmc_band(const vqmc_made* m, float* band, void* stream);
