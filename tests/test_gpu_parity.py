@@ -76,7 +76,10 @@ def test_cast_bf16_bits_and_transpose(n, h):
 
 # ---------------------------------------------------------------- energy and statistics
 @pytest.mark.parametrize("n,deg,B", [(20, 3, 1024), (500, 0, 4096), (10000, 10, 2048), (37, 4, 5),
-                                     (70000, 4, 11)])  # the last: sites too many for the bit-packed kernel
+                                     # byte-lane kernel with the row pointer read from global memory
+                                     (16000, 6, 9),
+                                     # too many sites for the byte lanes: the bit kernel
+                                     (70000, 4, 11)])
 def test_energy_csr_int_bit_exact(n, deg, B):
     _banner(f"energy csr int n={n} B={B}")
     edges = inputs.erdos_renyi_graph(n, 0.02, 0) if deg == 0 else inputs.random_regular_graph(n, deg, 0)
