@@ -155,7 +155,8 @@ def time_calls(made, H, B_, reps=10, seed=2, names=None):
 
 
 def algorithmic_work(w, made, H):
-    """Algorithmic flops / bytes per launch of each call."""
+    """Algorithmic flops / bytes per launch of each call: the work the method defines, not the
+    work the kernels do (masked halves and padding are not counted)."""
     c = made.c.cpu().numpy().astype(np.int64)
     n, h, B_ = w.n, w.h, w.B
     sum_c = int(c.sum())                     # sum_d c[d]: second-layer MACs per sample
@@ -289,8 +290,9 @@ def _cpu_model():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU data parallelism "
-                                   "is design-only (see DESIGN.md)", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "bench.py runs on exactly one GPU; multi-GPU data parallelism is not "
+                                   "implemented (shards would draw B/N samples each at sample_offset "
+                                   "rank * B/N and all-reduce the gradient)", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_2106_13308_amd import binding as B

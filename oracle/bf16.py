@@ -1,7 +1,7 @@
 """float32 -> bfloat16 rounding, round-to-nearest-even, written from the IEEE-754 binary32
 layout: bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits.
 
-The paper fixes no precision; BF16 weights are this build's choice (reading: the oracle
+The paper fixes no precision; the GPU kernels may run on BF16 weights (reading: the oracle
 evaluates the model on the BF16-rounded weights, widened back to float64, so that parity
 isolates arithmetic error from quantisation).  Pinned against torch's CPU cast.
 """
