@@ -29,7 +29,8 @@ import numpy as np
 __all__ = [
     "made_degrees", "made_init", "random_regular_graph", "erdos_renyi_graph",
     "cycle_graph", "complete_graph", "integer_weights", "unit_weights",
-    "sk_couplings", "random_spins", "Workload", "WORKLOADS", "make_instance",
+    "sk_couplings", "random_spins", "paper_maxcut_graph", "paper_latent_size",
+    "PAPER_MAXCUT_SIZES", "PAPER_TARGET_CUTS", "Workload", "WORKLOADS", "make_instance",
 ]
 
 
@@ -110,6 +111,35 @@ def erdos_renyi_graph(n: int, p: float, seed: int) -> np.ndarray:
     return np.stack([iu[keep], ju[keep]], axis=1).astype(np.int32)
 
 
+def paper_maxcut_graph(n: int, seed: int) -> np.ndarray:
+    """The Max-Cut instance recipe of the experimental setup (Sec. 5.1): draw an n x n
+    matrix B with i.i.d. Bernoulli(1/2) entries once, form (B + B^T)/2, round it
+    elementwise and zero the diagonal; the result is the adjacency matrix.
+
+    (B_ij + B_ji)/2 is 0, 1/2 or 1.  Rounding half to even (NumPy's and PyTorch's
+    ``round``) sends 1/2 to 0, so {i, j} is an edge exactly when B_ij = B_ji = 1: the
+    graph is G(n, 1/4) with unit weights.  Returns the canonical edge list (i < j)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    Bm = (rng.random((n, n)) < 0.5).astype(np.float64)
+    A = np.round((Bm + Bm.T) / 2.0)
+    np.fill_diagonal(A, 0.0)
+    iu, ju = np.nonzero(np.triu(A, 1))
+    return np.stack([iu, ju], axis=1).astype(np.int32)
+
+
+def paper_latent_size(n: int) -> int:
+    """The MADE hidden size of the paper's Max-Cut runs, h = 5 (log n)^2 (Sec. 5.1,
+    model architecture), with the natural logarithm, rounded to the nearest integer."""
+    return max(1, int(round(5.0 * math.log(n) ** 2)))
+
+
+# Problem sizes of the paper's Max-Cut benchmarks (Sec. 5.2) and the target cuts of its
+# time-to-target table (Table 5).  The targets belong to the paper's own instance draws;
+# on a fresh draw of the same recipe they are reference points, not guarantees.
+PAPER_MAXCUT_SIZES = (20, 50, 100, 200, 500)
+PAPER_TARGET_CUTS = {20: 41, 50: 190, 100: 730, 200: 2800, 500: 16800}
+
+
 def cycle_graph(n: int) -> np.ndarray:
     return _canonical([(i, (i + 1) % n) for i in range(n)])
 
@@ -154,7 +184,7 @@ class Workload:
     n: int
     h: int
     B: int
-    graph: str            # "regular3", "er0.02", "sk", "regular10"
+    graph: str            # "regular3", "er0.02", "sk", "regular10", "paper"
     weights: str          # "unit", "int1-5", "dense"
     wdtype: str           # arithmetic type of the network weights: "f64", "f32", "bf16"
     description: str
@@ -174,6 +204,12 @@ WORKLOADS = {
                                 "Max-Cut n=10000, random 10-regular graph, unit weights; "
                                 "MADE h=2000; B=2048"),
 }
+for _n in PAPER_MAXCUT_SIZES:
+    _h = paper_latent_size(_n)
+    WORKLOADS[f"paper_maxcut{_n}"] = Workload(
+        f"paper_maxcut{_n}", _n, _h, 1024, "paper", "unit", "f32",
+        f"Max-Cut n={_n}, the paper's instance recipe (G(n, 1/4), unit weights); "
+        f"MADE h=5(ln n)^2={_h} FP32; B=1024")
 
 
 def make_instance(w: Workload, graph_seed: int = 0, init_seed: int = 1) -> dict:
@@ -187,6 +223,8 @@ def make_instance(w: Workload, graph_seed: int = 0, init_seed: int = 1) -> dict:
         edges = random_regular_graph(w.n, 3, graph_seed)
     elif w.graph == "regular10":
         edges = random_regular_graph(w.n, 10, graph_seed)
+    elif w.graph == "paper":
+        edges = paper_maxcut_graph(w.n, graph_seed)
     elif w.graph.startswith("er"):
         edges = erdos_renyi_graph(w.n, float(w.graph[2:]), graph_seed)
     elif w.graph == "sk":

@@ -1,0 +1,128 @@
+"""The paper's Max-Cut evaluation protocol on instances drawn with its recipe.
+
+Setup (Sec. 5.1): one instance per size n in {20, 50, 100, 200, 500}, built as
+G(n, 1/4) with unit weights (``inputs.paper_maxcut_graph``); a MADE with
+h = 5 (ln n)^2 hidden units; Adam with learning rate 0.01; 1024 training samples per
+iteration; 300 iterations; several training seeds per instance.  After every update a
+fresh batch of 1024 evaluation samples is drawn (its own Philox stream) and its mean
+cut is the evaluation score; evaluation time is excluded from the wall clock
+(time-to-target protocol of Table 5).
+
+Reported per size, averaged over the seeds:
+* ``final_eval_mean_cut`` -- the evaluation score after the last iteration (the
+  quantity behind the converged energies of Tables 2 and 3, expressed as a cut);
+* ``train_s`` -- wall time of all iterations;
+* time to target for two targets: the paper's own target cut (Table 5), which
+  belongs to its instance draw, and that target scaled by (edges of this draw) /
+  (expected edges n(n-1)/8), the like-for-like target on a fresh draw.  A run that
+  never reaches a target reports ``null``; the mean is then over the runs that did.
+
+    python -m paper_2106_13308_amd.protocol --sizes 20 50 100 200 500 --seeds 5
+
+Prints one JSON object per size and a final summary object.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import torch
+
+from . import binding as B
+from . import inputs
+from .vqmc import Trainer
+
+DTYPES = {"f32": B.F32, "bf16": B.BF16, "f64": B.F64}
+
+
+def make_trainer(n: int, seed: int, wdtype: int, lr: float = 0.01, batch: int = 1024,
+                 graph_seed: int = 0):
+    w = inputs.WORKLOADS[f"paper_maxcut{n}"]
+    inst = inputs.make_instance(w, graph_seed=graph_seed, init_seed=1000 + seed)
+    made = B.Made.from_dense(inst["W1"], inst["b1"], inst["W2"], inst["b2"], inst["degrees"], wdtype=wdtype)
+    H = B.Hamiltonian.from_edges(n, inst["edges"], inst["weights"])
+    return Trainer(made, H, batch, seed=seed, lr=lr), inst
+
+
+def run_one(trainer: Trainer, iters: int, targets: dict, eval_batch: int = 1024) -> dict:
+    """Train for ``iters`` iterations, scoring each update on a fresh evaluation batch."""
+    wall = 0.0
+    hit = {k: None for k in targets}
+    hit_best = {k: None for k in targets}
+    ev = None
+    for i in range(iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trainer.step(log=False)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        ev = trainer.evaluate(eval_batch)                       # not timed
+        for k, tgt in targets.items():
+            if hit[k] is None and ev["mean_cut"] >= tgt:
+                hit[k] = {"iter": i + 1, "s": wall}
+            if hit_best[k] is None and ev["best_cut"] >= tgt:
+                hit_best[k] = {"iter": i + 1, "s": wall}
+    return {"final_eval_mean_cut": ev["mean_cut"], "final_eval_best_cut": ev["best_cut"],
+            "train_s": wall, "ms_per_iter": 1e3 * wall / iters, "hit_mean": hit, "hit_best": hit_best}
+
+
+def _mean(xs):
+    xs = [x for x in xs if x is not None]
+    return sum(xs) / len(xs) if xs else None
+
+
+def run_size(n: int, seeds: int, iters: int, wdtype: int, lr: float) -> dict:
+    edges = inputs.paper_maxcut_graph(n, 0)
+    m = len(edges)
+    paper_t = inputs.PAPER_TARGET_CUTS[n]
+    targets = {"paper": paper_t, "scaled": round(paper_t * m / (n * (n - 1) / 8))}
+    runs = []
+    for s in range(seeds):
+        tr, _ = make_trainer(n, s, wdtype, lr)
+        r = run_one(tr, iters, targets)
+        runs.append(r)
+        print(f"[protocol] n={n} seed={s}: eval mean cut {r['final_eval_mean_cut']:.2f} "
+              f"best {r['final_eval_best_cut']:.0f} train {r['train_s']:.2f}s hits {r['hit_mean']}",
+              file=sys.stderr, flush=True)
+        del tr
+    out = {"n": n, "h": inputs.paper_latent_size(n), "edges": m, "seeds": seeds, "iters": iters,
+           "targets": targets,
+           "final_eval_mean_cut": _mean([r["final_eval_mean_cut"] for r in runs]),
+           "final_eval_best_cut": max(r["final_eval_best_cut"] for r in runs),
+           "train_s": _mean([r["train_s"] for r in runs]),
+           "ms_per_iter": _mean([r["ms_per_iter"] for r in runs])}
+    for k in targets:
+        hs = [r["hit_mean"][k] for r in runs]
+        out[f"time_to_{k}_s"] = _mean([h["s"] if h else None for h in hs])
+        out[f"reached_{k}"] = sum(h is not None for h in hs)
+        hb = [r["hit_best"][k] for r in runs]
+        out[f"time_to_{k}_best_s"] = _mean([h["s"] if h else None for h in hb])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", type=int, nargs="+", default=list(inputs.PAPER_MAXCUT_SIZES))
+    ap.add_argument("--seeds", type=int, default=5)
+    ap.add_argument("--iters", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=0.01)
+    ap.add_argument("--wdtype", choices=sorted(DTYPES), default="f32")
+    a = ap.parse_args()
+    if not torch.cuda.is_available():
+        sys.exit("protocol: needs a GPU (the library runs every step on the device)")
+    res = []
+    for n in a.sizes:
+        if n not in inputs.PAPER_TARGET_CUTS:
+            sys.exit(f"protocol: n={n} is not one of the paper's sizes {inputs.PAPER_MAXCUT_SIZES}")
+        r = run_size(n, a.seeds, a.iters, DTYPES[a.wdtype], a.lr)
+        r["wdtype"] = a.wdtype
+        print(json.dumps(r), flush=True)
+        res.append(r)
+    print(json.dumps({"summary": [{k: r[k] for k in ("n", "edges", "final_eval_mean_cut", "time_to_paper_s",
+                                                      "time_to_scaled_s", "train_s")} for r in res]}))
+
+
+if __name__ == "__main__":
+    main()
