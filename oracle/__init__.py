@@ -21,6 +21,8 @@ sampling   Algorithm 1 (autoregressive sampling), two independent forms.
 energy     Diagonal local energy of eq. (hamiltonian) / eq. (e:tim) with alpha = beta_i = 0.
 estimator  Batch statistics, score-function gradient (Sec. 2.1, gradient population form),
            analytic gradient of log pi through MADE, central finite differences.
+sr         Per-sample scores, Fisher matrix, sample-space Gram and the SR direction
+           (Sec. 2.1 Fisher information with the ridge of Sec. 5.1), direct and Woodbury.
 exact      Brute-force enumeration of all 2^n strings (normalisation, exact objective and
            gradient, Max-Cut optimum) for small n.
 
@@ -38,6 +40,8 @@ R7  variance is the population form sum (E - mean)^2 / B.
 R8  s_d = +1 iff u < p_d with u the 24-bit uniform of :mod:`oracle.philox`.
 R9  log sigma(t) = min(t, 0) - log1p(exp(-|t|)).
 R10 ReLU'(0) = 0.
+R19 the Fisher matrix is estimated uncentred, as printed: O^T O / B over the per-sample
+    scores; SR solves (O^T O / B + lambda I) x = g.
 
 Parity status: every function here is pinned by a CPU test against a fact that does not
 come from the oracle itself (known-answer vectors, closed forms, brute force, finite
