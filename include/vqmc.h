@@ -115,7 +115,8 @@ enum {
   VQMC_WS_BACKWARD = 1,
   VQMC_WS_SAMPLE_PLAIN = 2,
   VQMC_WS_STEP = 3,
-  VQMC_WS_BACKWARD_SAMPLED = 4
+  VQMC_WS_BACKWARD_SAMPLED = 4,
+  VQMC_WS_SR_GRAM = 5
 };
 /* Workspace bytes needed by a call (host function, no device access). */
 size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
@@ -245,6 +246,19 @@ int vqmc_logprob(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, fl
 int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef,
                           float* dP, float* db1, float* db2, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* Sample-space Gram of the per-sample scores for stochastic reconfiguration (Sec. 2.1:
+ * the Fisher information is the expectation of the outer product of grad log pi;
+ * Sec. 5.1: SR with a ridge).  With O the B x (nh + h + n) matrix whose row b is
+ * grad log pi(s_b) over every unmasked parameter (packed P, b1, b2), writes
+ *   K = O O^T,   K[b][b'] = <grad log pi(s_b), grad log pi(s_b')>,
+ * the matrix of the Woodbury form (lambda B I + K)^{-1} of the SR solve.  O is never
+ * formed: the forward pass is recomputed and two staircase prefix sweeps build K in FP32.
+ * S: B x ld(n) int8 spins (device).  K: B x B float, row-major, leading dimension B
+ * (device, caller-owned, overwritten; symmetric).  1 <= B <= 65536, else EINVAL.  Needs
+ * VQMC_WS_SR_GRAM workspace (it holds two B x B partial sums). */
+int vqmc_sr_gram(const vqmc_made* m, const int8_t* S, int64_t B, float* K, void* ws, size_t ws_bytes,
+                 void* stream);
 
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,

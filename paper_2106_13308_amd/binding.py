@@ -24,7 +24,7 @@ PAD = 64
 F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
-WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED = 0, 1, 2, 3, 4
+WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM = 0, 1, 2, 3, 4, 5
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
@@ -73,6 +73,7 @@ _SIGS = {
     "vqmc_logprob": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                              _sz, _vp]),
+    "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
     "vqmc_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(HamC), _i64, _u64, _u64, _i64, _i32,
                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_csr_from_edges": (ctypes.c_int, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp]),
@@ -347,6 +348,18 @@ def logprob_backward(made: Made, S: torch.Tensor, coef: torch.Tensor, B: int | N
         ctypes.byref(m), _dev(S).data_ptr(), B, _dev(coef).data_ptr(), dP.data_ptr(), db1.data_ptr(),
         db2.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
     return dP, db1, db2
+
+
+def sr_gram(made: Made, S: torch.Tensor, B: int | None = None, ws: torch.Tensor | None = None,
+            K: torch.Tensor | None = None) -> torch.Tensor:
+    """K = O O^T (B x B float), the sample-space Gram of the per-sample scores."""
+    B = S.shape[0] if B is None else B
+    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _dev(K)
+    ws = workspace(WS_SR_GRAM, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_sr_gram", _lib.vqmc_sr_gram(ctypes.byref(m), _dev(S).data_ptr(), B, K.data_ptr(), ws.data_ptr(),
+                                              ws.numel(), _stream()))
+    return K
 
 
 @dataclass

@@ -815,6 +815,56 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
   return hipGetLastError();
 }
 
+// Factors of the per-sample scores for the SR Gram: the recompute path of backward_t with
+// coef = 1 leaves Rt = relu(A), Gt = s sigma(-s z), St = s and Dt = dlogp/dA in the
+// workspace, batch-contiguous; sr.hip turns them into K.  Workspace: the backward layout,
+// then B ones, then the two B x B partial sums.
+static size_t sr_extra_offset(int n, int h, int64_t B, int dtype) {
+  return (size_t)round_up((int64_t)layout(n, h, B, dtype, 1).total, 256);
+}
+size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype) {
+  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + 2 * (size_t)round_up(B * B * 4, 256);
+}
+
+template <typename T>
+static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
+  uint8_t* w = (uint8_t*)ws;
+  T* R = (T*)(w + L.R);
+  T* Rt = (T*)(w + L.Rt);
+  T* G = (T*)(w + L.G);
+  T* Gt = (T*)(w + L.Gt);
+  T* St = (T*)(w + L.St);
+  T* Dt = (T*)(w + L.Dt);
+  float* lp_part = (float*)(w + L.lp_part);
+  float* db2_part = (float*)(w + L.db2_part);
+  float* db1_part = (float*)(w + L.db1_part);
+  const size_t xo = sr_extra_offset(m.n, m.h, B, m.wdtype);
+  float* ones = (float*)(w + xo);
+  float* P0 = (float*)(w + xo + round_up(B * 4, 256));
+  float* P1 = (float*)((uint8_t*)P0 + round_up(B * B * 4, 256));
+  hipError_t e;
+  fill_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ones, B, 1.f);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  fwd_hidden_kernel<T, true><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c,
+                                                                    m.n, m.h, B, R, g.ldh, Rt, g.ldB);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  fwd_out_kernel<T, 1><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, nullptr, ones, G, Gt,
+      St, g.ldB, db2_part, 0, 0, 0, 0, 0, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, P0, P1, K, st);
+}
+
+hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return sr_gram_t<bf16_t>(m, S, B, K, ws, st);
+  return sr_gram_t<float>(m, S, B, K, ws, st);
+}
+
 // Backward from the incremental sampler's byproducts: Rt (relu(A), batch-contiguous, in
 // the workspace's Rt slot) and Zs (s_d z_d): the two forward products are not recomputed.
 template <typename T>

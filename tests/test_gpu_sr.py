@@ -1,0 +1,58 @@
+"""SR Gram (vqmc_sr_gram) against the oracle's explicit score matrix: K = O O^T over every
+unmasked parameter (Sec. 2.1 Fisher information; SR of Sec. 5.1, reading R19).
+
+Tolerance: each entry within rtol * sqrt(K_bb K_b'b') of the FP64 value (the
+Cauchy-Schwarz bound on |K_bb'|).  FP32: rtol 2e-4 -- the factors G, R, D are FP32
+(relative error ~1e-6) and every entry accumulates 3 (n + h) products in FP32.  BF16: rtol
+2e-2 -- the factors are stored in BF16 (relative rounding 2^-9 each)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sr as osr
+from paper_2106_13308_amd import inputs
+
+from gpu_util import DEV, build_made, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"f32": 2e-4, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(20, 40, 64), (67, 33, 100), (130, 70, 200), (300, 200, 70), (9, 3, 1)])
+def test_sr_gram_matches_oracle(wd, n, h, B):
+    from paper_2106_13308_amd import binding as Bd
+    wdt = Bd.F32 if wd == "f32" else Bd.BF16
+    print(f"[sr-gram] wd={wd} n={n} h={h} B={B}", flush=True)
+    p = inputs.made_init(n, h, 61)
+    S = inputs.random_spins(B, n, 62)
+    made = build_made(p, wdt)
+    Sd = torch.zeros((B, Bd.ld(n)), dtype=torch.int8, device=DEV)
+    Sd[:, :n] = torch.from_numpy(S).to(DEV)
+    K = Bd.sr_gram(made, Sd, B).double().cpu().numpy()
+    torch.cuda.synchronize()
+    Kref = osr.gram(oracle_params(p, wdt), S)
+    scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
+    err = np.abs(K - Kref) / np.maximum(scale, 1e-30)
+    assert np.isfinite(K).all()
+    assert np.array_equal(K, K.T)                            # mirrored, not recomputed
+    assert err.max() <= RTOL[wd], f"max normalised error {err.max():.3g}"
+
+
+def test_sr_gram_two_calls_and_tile_edges():
+    """A second call with a smaller batch overwrites only its own B x B block; the entries
+    next to the diagonal tiles (b, b' in different 64-sample tiles) match too."""
+    from paper_2106_13308_amd import binding as Bd
+    n, h = 90, 70
+    p = inputs.made_init(n, h, 71)
+    made = build_made(p, Bd.F32)
+    for B in (150, 65):
+        S = inputs.random_spins(B, n, 72 + B)
+        Sd = torch.zeros((B, Bd.ld(n)), dtype=torch.int8, device=DEV)
+        Sd[:, :n] = torch.from_numpy(S).to(DEV)
+        K = Bd.sr_gram(made, Sd, B).double().cpu().numpy()
+        Kref = osr.gram(oracle_params(p, Bd.F32), S)
+        scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
+        assert (np.abs(K - Kref) / scale).max() <= RTOL["f32"]
+        assert abs(K[63, 64] - Kref[63, 64]) <= RTOL["f32"] * scale[63, 64]
