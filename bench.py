@@ -54,6 +54,8 @@ def parse():
                     help="run warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--profile-call", default="sample",
+                    help="library call timed by --profile-only after the steps (sample, sr_gram, ...)")
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp32", "fp32_plain"],
                     help="step form timed by --profile-only")
     return ap.parse_args()
@@ -109,6 +111,8 @@ def time_calls(made, H, B_, reps=10, seed=2, names=None):
     bufs = B.StepBuffers.allocate(made, H, B_)
     B.step(made, H, B_, seed, 0, bufs)
     ws_bw = B.workspace(B.WS_BACKWARD, made, B_)
+    ws_sr = B.workspace(B.WS_SR_GRAM, made, B_) if names is None or "sr_gram" in names else None
+    K = torch.empty((B_, B_), dtype=torch.float32, device="cuda") if ws_sr is not None else None
     calls = {"refresh": made.refresh}
     if made.band is not None:
         # the calls vqmc_step makes: sampling with the forward byproducts, energy, statistics,
@@ -124,6 +128,8 @@ def time_calls(made, H, B_, reps=10, seed=2, names=None):
         "stats": lambda: B.batch_stats(bufs.E),
         "logprob_backward": lambda: B.logprob_backward(made, bufs.S, bufs.coef, ws=ws_bw),
         "logprob": lambda: B.logprob(made, bufs.S),
+        # not part of the step: the sample-space Gram of the scores that an SR update solves with
+        "sr_gram": lambda: B.sr_gram(made, bufs.S, B_, ws=ws_sr, K=K),
     })
     out = {}
     for name, fn in calls.items():
@@ -173,6 +179,10 @@ def algorithmic_work(w, made, H):
         "logprob": {"flops": 2.0 * nh * B_},
         # backward: forward recompute (n*h) + hidden adjoint (sum_c) + weight gradient (n*h)
         "logprob_backward": {"flops": 2.0 * (2 * nh + sum_c) * B_},
+        # SR Gram: forward recompute (n*h MACs) + hidden adjoint (sum_c) per sample, then per
+        # unique Gram entry (B(B+1)/2 of them) n + h prefix multiply-adds (2 flops) and n + h
+        # outer rows (a multiply and a multiply-add: 3 flops)
+        "sr_gram": {"flops": 2.0 * (nh + sum_c) * B_ + 5.0 * (n + h) * B_ * (B_ + 1) / 2},
         # backward from the sampler's byproducts: hidden adjoint (sum_c) + weight gradient (n*h)
         "backward_sampled": {"flops": 2.0 * (nh + sum_c) * B_},
     }
@@ -316,9 +326,9 @@ def main():
     ms, wall_ms, bufs = time_steps(made, H, w.B, a.steps, a.warmup)
     log(f"bf16 incremental step: {ms:.3f} ms (event), {wall_ms * 1e3:.3f} ms (wall)")
     if a.profile_only:
-        # then the sampling call as the roofline times it (one untimed launch, then five
-        # launches each right after a refresh), so that the trace holds that loop too
-        calls = time_calls(made, H, w.B, reps=5, names=("sample",))
+        # then one library call (by default the sampler as the roofline times it: one untimed
+        # launch, then five launches each right after a refresh), so that the trace holds it too
+        calls = time_calls(made, H, w.B, reps=5, names=(a.profile_call,))
         log("per-call ms (profiled loop): " + json.dumps({k: round(v, 4) for k, v in calls.items()}))
         return
     value = w.B / (ms / 1e3)

@@ -256,7 +256,7 @@ int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const 
  * formed: the forward pass is recomputed and two staircase prefix sweeps build K in FP32.
  * S: B x ld(n) int8 spins (device).  K: B x B float, row-major, leading dimension B
  * (device, caller-owned, overwritten; symmetric).  1 <= B <= 65536, else EINVAL.  Needs
- * VQMC_WS_SR_GRAM workspace (it holds two B x B partial sums). */
+ * VQMC_WS_SR_GRAM workspace (it holds three B x B partial sums). */
 int vqmc_sr_gram(const vqmc_made* m, const int8_t* S, int64_t B, float* K, void* ws, size_t ws_bytes,
                  void* stream);
 

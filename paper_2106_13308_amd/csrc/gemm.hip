@@ -818,12 +818,12 @@ static hipError_t backward_t(const vqmc_made& m, const int8_t* S, int64_t B, con
 // Factors of the per-sample scores for the SR Gram: the recompute path of backward_t with
 // coef = 1 leaves Rt = relu(A), Gt = s sigma(-s z), St = s and Dt = dlogp/dA in the
 // workspace, batch-contiguous; sr.hip turns them into K.  Workspace: the backward layout,
-// then B ones, then the two B x B partial sums.
+// then B ones, then the sweeps' B x B partial sums.
 static size_t sr_extra_offset(int n, int h, int64_t B, int dtype) {
   return (size_t)round_up((int64_t)layout(n, h, B, dtype, 1).total, 256);
 }
 size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype) {
-  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + 2 * (size_t)round_up(B * B * 4, 256);
+  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(B);
 }
 
 template <typename T>
@@ -842,8 +842,7 @@ static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
   float* db1_part = (float*)(w + L.db1_part);
   const size_t xo = sr_extra_offset(m.n, m.h, B, m.wdtype);
   float* ones = (float*)(w + xo);
-  float* P0 = (float*)(w + xo + round_up(B * 4, 256));
-  float* P1 = (float*)((uint8_t*)P0 + round_up(B * B * 4, 256));
+  float* parts = (float*)(w + xo + round_up(B * 4, 256));
   hipError_t e;
   fill_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ones, B, 1.f);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -857,7 +856,7 @@ static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
   bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
                                                              g.ldB, db1_part, g.ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, P0, P1, K, st);
+  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st);
 }
 
 hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {

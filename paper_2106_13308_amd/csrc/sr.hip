@@ -15,11 +15,11 @@
 // multiply-adds per Gram entry, without forming the B x (nh + n + h) score matrix.
 //
 // This is elementwise FP32 work, not a contraction: every Gram entry carries its own
-// running prefix.  Each workgroup owns a 64 x 64 tile of one of the two sums (tiles on or
-// above the diagonal only; K is symmetric), each thread a 4 x 4 block; the factor rows are
-// batch-contiguous (X[j][b], ld(B) columns), so a row of one factor feeds a tile with
-// two 4-element loads per thread.  A combine pass adds the two sums and mirrors the
-// upper tiles.
+// running prefix.  Each workgroup owns a 64 x 64 tile (tiles on or above the diagonal
+// only; K is symmetric) of one work item, a range of one sweep; the factor rows are
+// batch-contiguous (X[j][b], ld(B) columns), so a row of one factor feeds a tile with two
+// 4-element loads per thread.  A combine pass adds the items' partial sums in a fixed
+// order and mirrors the upper tiles.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -58,55 +58,60 @@ __device__ inline void upper_tile(int t, int nt, int& ti, int& tj) {
   tj = i + t;
 }
 
-// part == 0: sum_d GG'_d (1 + prefix_{k < c[d]} RR'_k)            -> out0
-// part == 1: sum_k DD'_k (1 + prefix_{d : c[d] <= k} ss'_d)        -> out1
-// X1 (outer rows: G or D), X2 (prefix rows: R or S), both batch-contiguous with ldb columns.
+// Work items (blockIdx.y): a sweep and a range [begin, end) of its outer rows.  The
+// longer sweep is split in two; its second half rebuilds the prefix from row 0, which
+// costs at most the prefix length again.  Each item writes its own partial sum.
+constexpr int GR_ITEMS = 3;
+struct GramItems {
+  int part[GR_ITEMS], begin[GR_ITEMS], end[GR_ITEMS];
+};
+
+// part 0: sum_d GG'_d (1 + prefix_{k < c[d]} RR'_k)
+// part 1: sum_k DD'_k (1 + prefix_{d : c[d] <= k} ss'_d)
+// A 64 x 64 tile per workgroup of four waves, a 4 x 4 block per thread.  The prefix
+// accumulator starts at 1, so an outer row costs one multiply and one multiply-add per
+// entry.
 template <typename T>
 __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, const T* __restrict__ Rt,
                                                       const T* __restrict__ Dt, const T* __restrict__ St,
                                                       int64_t ldb, const int32_t* __restrict__ c, int n, int h,
-                                                      int64_t B, int nt, float* __restrict__ out0,
-                                                      float* __restrict__ out1) {
+                                                      int64_t B, int nt, GramItems items,
+                                                      float* __restrict__ parts) {
   int ti, tj;
   upper_tile(blockIdx.x, nt, ti, tj);
-  const int part = blockIdx.y;
+  const int item = blockIdx.y;
+  const int part = items.part[item];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t br = (int64_t)ti * GR_T + 4 * ty;  // this thread's rows b
   const int64_t bc = (int64_t)tj * GR_T + 4 * tx;  // and columns b'
+  // part 0: prefix rows R (h), outer rows G (n); part 1: prefix rows S (n), outer rows D (h)
+  const T* Xp = part ? St : Rt;
+  const T* Xo = part ? Dt : Gt;
+  const int np = part ? n : h;
+  const int o0 = items.begin[item], o1 = items.end[item];
   float acc[4][4], pre[4][4];
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = pre[i][j] = 0.f;
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = 0.f;
+      pre[i][j] = 1.f;
+    }
   float a[4], b[4];
-  auto rank1 = [&](const T* X, int64_t row, float M[4][4]) {
-    load4<T>(X + row * ldb + br, a);
-    load4<T>(X + row * ldb + bc, b);
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) M[i][j] = fmaf(a[i], b[j], M[i][j]);
-  };
-  auto outer = [&](const T* X, int64_t row) {
-    load4<T>(X + row * ldb + br, a);
-    load4<T>(X + row * ldb + bc, b);
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) {
-        const float t = a[i] * b[j];
-        acc[i][j] = fmaf(t, pre[i][j], acc[i][j] + t);
-      }
-  };
-  if (part == 0) {
-    int kp = 0;
-    for (int d = 0; d < n; ++d) {
-      const int cd = c[d];
-      for (; kp < cd; ++kp) rank1(Rt, kp, pre);
-      outer(Gt, d);
+  int ip = 0;  // next prefix row
+  for (int io = o0; io < o1; ++io) {
+    // prefix rows that outer row io sees: k < c[io] (part 0), sites d with c[d] <= io (part 1)
+    const int lim = part ? np : c[io];
+    for (; ip < lim && (part == 0 || c[ip] <= io); ++ip) {
+      load4<T>(Xp + (int64_t)ip * ldb + br, a);
+      load4<T>(Xp + (int64_t)ip * ldb + bc, b);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) pre[i][j] = fmaf(a[i], b[j], pre[i][j]);
     }
-  } else {
-    int dq = 0;
-    for (int k = 0; k < h; ++k) {
-      for (; dq < n && c[dq] <= k; ++dq) rank1(St, dq, pre);
-      outer(Dt, k);
-    }
+    load4<T>(Xo + (int64_t)io * ldb + br, a);
+    load4<T>(Xo + (int64_t)io * ldb + bc, b);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i] * b[j], pre[i][j], acc[i][j]);
   }
-  float* out = part ? out1 : out0;
+  float* out = parts + (int64_t)item * B * B;
   for (int i = 0; i < 4; ++i) {
     const int64_t r = br + i;
     if (r >= B) break;
@@ -115,35 +120,61 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
   }
 }
 
-// K[b][b'] = P0[lo][hi] + P1[lo][hi] with (lo, hi) the pair ordered so that its tile lies on
-// or above the diagonal (where the sweeps wrote it).
-__global__ void sr_gram_combine_kernel(const float* __restrict__ P0, const float* __restrict__ P1, int64_t B,
+// K[b][b'] = sum over the items' partial sums at (lo, hi), the pair ordered so that its
+// tile lies on or above the diagonal (where the sweeps wrote it); fixed order.
+__global__ void sr_gram_combine_kernel(const float* __restrict__ parts, int nitems, int64_t B,
                                        float* __restrict__ K) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * B) return;
   const int64_t r = idx / B, q = idx - r * B;
   const bool upper = (r / GR_T) <= (q / GR_T);
   const int64_t src = upper ? idx : q * B + r;
-  K[idx] = P0[src] + P1[src];
+  float s = parts[src];
+  for (int i = 1; i < nitems; ++i) s += parts[(int64_t)i * B * B + src];
+  K[idx] = s;
 }
 
+// Split of the longer sweep: part 0 costs about 2n + h per entry (outer rows n, prefix h),
+// part 1 about 2h + n.  Halving the outer range of the longer one (its halves cost about
+// n + h each, the second paying its prefix again) balances the three items.
+static GramItems gram_items(int n, int h, int* count) {
+  GramItems it{};
+  const int big = (n >= h) ? 0 : 1;      // the sweep with the longer outer range
+  const int nb = big == 0 ? n : h;       // its outer rows
+  const int ns = big == 0 ? h : n;       // its prefix rows = the other sweep's outer rows
+  int k = 0;
+  if (nb > ns && nb >= 2) {
+    it.part[k] = big, it.begin[k] = 0, it.end[k] = nb / 2, ++k;
+    it.part[k] = big, it.begin[k] = nb / 2, it.end[k] = nb, ++k;
+  } else {
+    it.part[k] = big, it.begin[k] = 0, it.end[k] = nb, ++k;
+  }
+  it.part[k] = 1 - big, it.begin[k] = 0, it.end[k] = ns, ++k;
+  *count = k;
+  return it;
+}
+
+size_t sr_gram_parts_bytes(int64_t B) { return (size_t)GR_ITEMS * B * B * 4; }
+
 hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, const void* Dt, const void* St,
-                                 int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* P0, float* P1,
-                                 float* K, hipStream_t st) {
+                                 int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* parts, float* K,
+                                 hipStream_t st) {
   const int nt = (int)((B + GR_T - 1) / GR_T);
   const int64_t pairs = (int64_t)nt * (nt + 1) / 2;
   if (pairs > 0x7FFFFFFF) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)pairs, 2);
+  int nitems = 0;
+  const GramItems items = gram_items(n, h, &nitems);
+  const dim3 grid((unsigned)pairs, (unsigned)nitems);
   if (dtype == VQMC_BF16)
     sr_gram_kernel<bf16_t><<<grid, 256, 0, st>>>((const bf16_t*)Gt, (const bf16_t*)Rt, (const bf16_t*)Dt,
-                                                 (const bf16_t*)St, ldb, c, n, h, B, nt, P0, P1);
+                                                 (const bf16_t*)St, ldb, c, n, h, B, nt, items, parts);
   else
     sr_gram_kernel<float><<<grid, 256, 0, st>>>((const float*)Gt, (const float*)Rt, (const float*)Dt,
-                                                (const float*)St, ldb, c, n, h, B, nt, P0, P1);
+                                                (const float*)St, ldb, c, n, h, B, nt, items, parts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = B * B;
-  sr_gram_combine_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(P0, P1, B, K);
+  sr_gram_combine_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(parts, nitems, B, K);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ RTOL = {"f32": 2e-4, "bf16": 2e-2}
 
 
 @pytest.mark.parametrize("wd", ["f32", "bf16"])
-@pytest.mark.parametrize("n,h,B", [(20, 40, 64), (67, 33, 100), (130, 70, 200), (300, 200, 70), (9, 3, 1)])
+@pytest.mark.parametrize("n,h,B", [(20, 40, 64), (67, 33, 100), (130, 70, 200), (300, 200, 70), (9, 3, 1), (64, 64, 130)])
 def test_sr_gram_matches_oracle(wd, n, h, B):
     from paper_2106_13308_amd import binding as Bd
     wdt = Bd.F32 if wd == "f32" else Bd.BF16
