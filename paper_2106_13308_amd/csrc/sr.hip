@@ -17,8 +17,7 @@
 // This is elementwise FP32 work, not a contraction: every Gram entry carries its own
 // running prefix.  Each workgroup owns a 64 x 64 tile (tiles on or above the diagonal
 // only; K is symmetric) of one work item, a range of one sweep; the factor rows are
-// batch-contiguous (X[j][b], ld(B) columns), so a row of one factor feeds a tile with two
-// 4-element loads per thread.  A combine pass adds the items' partial sums in a fixed
+// batch-contiguous (X[j][b], ld(B) columns) and reach the tile through LDS panels of rows.  A combine pass adds the items' partial sums in a fixed
 // order and mirrors the upper tiles.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -66,9 +65,31 @@ struct GramItems {
   int part[GR_ITEMS], begin[GR_ITEMS], end[GR_ITEMS];
 };
 
+constexpr int GR_PR = 32;  // rows per LDS panel
+
+// Rows [r0, min(r0 + GR_PR, nrows)) of X, columns [c0, c0 + 64) and [c1, c1 + 64), into
+// panel[row][0..63] and panel[row][64..127] as float: eight threads per row, 16 values each.
+template <typename T>
+__device__ inline void load_panel(const T* __restrict__ X, int64_t ldb, int r0, int nrows, int64_t c0, int64_t c1,
+                                  float (*panel)[2 * GR_T]) {
+  const int r = threadIdx.x >> 3, seg = threadIdx.x & 7;
+  if (r0 + r >= nrows) return;
+  const int64_t col = (seg < 4 ? c0 : c1) + 16 * (seg & 3);
+  const T* src = X + (int64_t)(r0 + r) * ldb + col;
+  float* dst = &panel[r][16 * seg];
+  for (int q = 0; q < 4; ++q) {
+    float v[4];
+    load4<T>(src + 4 * q, v);
+    *reinterpret_cast<float4*>(dst + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
 // part 0: sum_d GG'_d (1 + prefix_{k < c[d]} RR'_k)
 // part 1: sum_k DD'_k (1 + prefix_{d : c[d] <= k} ss'_d)
-// A 64 x 64 tile per workgroup of four waves, a 4 x 4 block per thread.  The prefix
+// A 64 x 64 tile per workgroup of four waves, a 4 x 4 block per thread.  Rows of the
+// prefix factor and of the outer factor are staged through two LDS panels of GR_PR rows
+// (both 64-sample column ranges of the tile), refilled when the sweep runs past them; the
+// staircase order is the same for every thread, so the refills are uniform.  The prefix
 // accumulator starts at 1, so an outer row costs one multiply and one multiply-add per
 // entry.
 template <typename T>
@@ -77,17 +98,18 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
                                                       int64_t ldb, const int32_t* __restrict__ c, int n, int h,
                                                       int64_t B, int nt, GramItems items,
                                                       float* __restrict__ parts) {
+  __shared__ __align__(16) float pp[GR_PR][2 * GR_T];  // prefix rows
+  __shared__ __align__(16) float po[GR_PR][2 * GR_T];  // outer rows
   int ti, tj;
   upper_tile(blockIdx.x, nt, ti, tj);
   const int item = blockIdx.y;
   const int part = items.part[item];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t br = (int64_t)ti * GR_T + 4 * ty;  // this thread's rows b
-  const int64_t bc = (int64_t)tj * GR_T + 4 * tx;  // and columns b'
+  const int64_t c0 = (int64_t)ti * GR_T, c1 = (int64_t)tj * GR_T;
   // part 0: prefix rows R (h), outer rows G (n); part 1: prefix rows S (n), outer rows D (h)
   const T* Xp = part ? St : Rt;
   const T* Xo = part ? Dt : Gt;
-  const int np = part ? n : h;
+  const int np = part ? n : h, no = part ? h : n;
   const int o0 = items.begin[item], o1 = items.end[item];
   float acc[4][4], pre[4][4];
   for (int i = 0; i < 4; ++i)
@@ -95,22 +117,37 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
       acc[i][j] = 0.f;
       pre[i][j] = 1.f;
     }
-  float a[4], b[4];
-  int ip = 0;  // next prefix row
+  int ip = 0;                        // next prefix row
+  int pbase = -GR_PR, obase = -GR_PR;  // first row held by each panel
   for (int io = o0; io < o1; ++io) {
     // prefix rows that outer row io sees: k < c[io] (part 0), sites d with c[d] <= io (part 1)
     const int lim = part ? np : c[io];
     for (; ip < lim && (part == 0 || c[ip] <= io); ++ip) {
-      load4<T>(Xp + (int64_t)ip * ldb + br, a);
-      load4<T>(Xp + (int64_t)ip * ldb + bc, b);
+      if (ip >= pbase + GR_PR) {
+        __syncthreads();
+        load_panel<T>(Xp, ldb, ip, np, c0, c1, pp);
+        pbase = ip;
+        __syncthreads();
+      }
+      const float4 a = *reinterpret_cast<const float4*>(&pp[ip - pbase][4 * ty]);
+      const float4 b = *reinterpret_cast<const float4*>(&pp[ip - pbase][GR_T + 4 * tx]);
+      const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
       for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) pre[i][j] = fmaf(a[i], b[j], pre[i][j]);
+        for (int j = 0; j < 4; ++j) pre[i][j] = fmaf(av[i], bv[j], pre[i][j]);
     }
-    load4<T>(Xo + (int64_t)io * ldb + br, a);
-    load4<T>(Xo + (int64_t)io * ldb + bc, b);
+    if (io >= obase + GR_PR) {
+      __syncthreads();
+      load_panel<T>(Xo, ldb, io, no, c0, c1, po);
+      obase = io;
+      __syncthreads();
+    }
+    const float4 a = *reinterpret_cast<const float4*>(&po[io - obase][4 * ty]);
+    const float4 b = *reinterpret_cast<const float4*>(&po[io - obase][GR_T + 4 * tx]);
+    const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i] * b[j], pre[i][j], acc[i][j]);
+      for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i] * bv[j], pre[i][j], acc[i][j]);
   }
+  const int64_t br = c0 + 4 * ty, bc = c1 + 4 * tx;
   float* out = parts + (int64_t)item * B * B;
   for (int i = 0; i < 4; ++i) {
     const int64_t r = br + i;
