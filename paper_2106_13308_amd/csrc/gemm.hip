@@ -823,7 +823,7 @@ static size_t sr_extra_offset(int n, int h, int64_t B, int dtype) {
   return (size_t)round_up((int64_t)layout(n, h, B, dtype, 1).total, 256);
 }
 size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype) {
-  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(B);
+  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(B, h);
 }
 
 template <typename T>

@@ -95,11 +95,12 @@ __device__ inline void load_panel(const T* __restrict__ X, int64_t ldb, int r0, 
 template <typename T>
 __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, const T* __restrict__ Rt,
                                                       const T* __restrict__ Dt, const T* __restrict__ St,
-                                                      int64_t ldb, const int32_t* __restrict__ c, int n, int h,
-                                                      int64_t B, int nt, GramItems items,
-                                                      float* __restrict__ parts) {
+                                                      int64_t ldb, const int32_t* __restrict__ c,
+                                                      const int32_t* __restrict__ cnt, int n, int h, int64_t B,
+                                                      int nt, GramItems items, float* __restrict__ parts) {
   __shared__ __align__(16) float pp[GR_PR][2 * GR_T];  // prefix rows
   __shared__ __align__(16) float po[GR_PR][2 * GR_T];  // outer rows
+  __shared__ int plim[GR_PR];                          // prefix length of each outer row in po
   int ti, tj;
   upper_tile(blockIdx.x, nt, ti, tj);
   const int item = blockIdx.y;
@@ -110,6 +111,9 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
   const T* Xp = part ? St : Rt;
   const T* Xo = part ? Dt : Gt;
   const int np = part ? n : h, no = part ? h : n;
+  // prefix rows outer row io sees: k < c[io] (part 0); the sites d with c[d] <= io, a
+  // prefix of the sites since c is non-decreasing, cnt[io] of them (part 1)
+  const int32_t* lims = part ? cnt : c;
   const int o0 = items.begin[item], o1 = items.end[item];
   float acc[4][4], pre[4][4];
   for (int i = 0; i < 4; ++i)
@@ -120,9 +124,15 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
   int ip = 0;                        // next prefix row
   int pbase = -GR_PR, obase = -GR_PR;  // first row held by each panel
   for (int io = o0; io < o1; ++io) {
-    // prefix rows that outer row io sees: k < c[io] (part 0), sites d with c[d] <= io (part 1)
-    const int lim = part ? np : c[io];
-    for (; ip < lim && (part == 0 || c[ip] <= io); ++ip) {
+    if (io >= obase + GR_PR) {
+      __syncthreads();
+      load_panel<T>(Xo, ldb, io, no, c0, c1, po);
+      if (threadIdx.x < GR_PR && io + (int)threadIdx.x < no) plim[threadIdx.x] = lims[io + threadIdx.x];
+      obase = io;
+      __syncthreads();
+    }
+    const int lim = __builtin_amdgcn_readfirstlane(plim[io - obase]);
+    for (; ip < lim; ++ip) {
       if (ip >= pbase + GR_PR) {
         __syncthreads();
         load_panel<T>(Xp, ldb, ip, np, c0, c1, pp);
@@ -134,12 +144,6 @@ __global__ __launch_bounds__(256) void sr_gram_kernel(const T* __restrict__ Gt, 
       const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) pre[i][j] = fmaf(av[i], bv[j], pre[i][j]);
-    }
-    if (io >= obase + GR_PR) {
-      __syncthreads();
-      load_panel<T>(Xo, ldb, io, no, c0, c1, po);
-      obase = io;
-      __syncthreads();
     }
     const float4 a = *reinterpret_cast<const float4*>(&po[io - obase][4 * ty]);
     const float4 b = *reinterpret_cast<const float4*>(&po[io - obase][GR_T + 4 * tx]);
@@ -191,11 +195,33 @@ static GramItems gram_items(int n, int h, int* count) {
   return it;
 }
 
-size_t sr_gram_parts_bytes(int64_t B) { return (size_t)GR_ITEMS * B * B * 4; }
+// cnt[k] = #{d : c[d] <= k}, the number of sites feeding hidden unit k's W1 column and
+// below (c non-decreasing: an upper bound by bisection).
+__global__ void sr_limits_kernel(const int32_t* __restrict__ c, int n, int h, int32_t* __restrict__ cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= h) return;
+  int lo = 0, hi = n;  // first d with c[d] > k lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (c[mid] <= k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  cnt[k] = lo;
+}
+
+size_t sr_gram_parts_bytes(int64_t B, int h) {
+  return (size_t)GR_ITEMS * B * B * 4 + (size_t)round_up((int64_t)h * 4, 256);
+}
 
 hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, const void* Dt, const void* St,
                                  int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* parts, float* K,
                                  hipStream_t st) {
+  int32_t* cnt = (int32_t*)(parts + (int64_t)GR_ITEMS * B * B);
+  sr_limits_kernel<<<(unsigned)((h + 255) / 256), 256, 0, st>>>(c, n, h, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int nt = (int)((B + GR_T - 1) / GR_T);
   const int64_t pairs = (int64_t)nt * (nt + 1) / 2;
   if (pairs > 0x7FFFFFFF) return hipErrorInvalidValue;
@@ -204,11 +230,11 @@ hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, cons
   const dim3 grid((unsigned)pairs, (unsigned)nitems);
   if (dtype == VQMC_BF16)
     sr_gram_kernel<bf16_t><<<grid, 256, 0, st>>>((const bf16_t*)Gt, (const bf16_t*)Rt, (const bf16_t*)Dt,
-                                                 (const bf16_t*)St, ldb, c, n, h, B, nt, items, parts);
+                                                 (const bf16_t*)St, ldb, c, cnt, n, h, B, nt, items, parts);
   else
     sr_gram_kernel<float><<<grid, 256, 0, st>>>((const float*)Gt, (const float*)Rt, (const float*)Dt,
-                                                (const float*)St, ldb, c, n, h, B, nt, items, parts);
-  hipError_t e = hipGetLastError();
+                                                (const float*)St, ldb, c, cnt, n, h, B, nt, items, parts);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = B * B;
   sr_gram_combine_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(parts, nitems, B, K);
