@@ -56,3 +56,28 @@ def test_sr_gram_two_calls_and_tile_edges():
         scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
         assert (np.abs(K - Kref) / scale).max() <= RTOL["f32"]
         assert abs(K[63, 64] - Kref[63, 64]) <= RTOL["f32"] * scale[63, 64]
+
+
+def test_sr_gram_full_size_sampled_entries():
+    """At n = 10^4, h = 1000, B = 2048 (BF16 factors, the launch the bench times) the oracle
+    forms the score rows of six samples spread over the batch (different 64-sample tiles and
+    work items) and every entry of K among them is checked."""
+    from paper_2106_13308_amd import binding as Bd
+    n, h, B = 10000, 1000, 2048
+    w = inputs.WORKLOADS["maxcut10k"]
+    assert (w.n, w.h, w.B) == (n, h, B)
+    p = inputs.made_init(n, h, 1)
+    S = inputs.random_spins(B, n, 81)
+    made = build_made(p, Bd.BF16)
+    Sd = torch.zeros((B, Bd.ld(n)), dtype=torch.int8, device=DEV)
+    Sd[:, :n] = torch.from_numpy(S).to(DEV)
+    print(f"[sr-gram] full size n={n} h={h} B={B}", flush=True)
+    K = Bd.sr_gram(made, Sd, B)
+    torch.cuda.synchronize()
+    idx = np.array([0, 63, 64, 1000, 2046, 2047])
+    Ks = K[idx][:, idx].double().cpu().numpy()
+    O = osr.score_matrix(oracle_params(p, Bd.BF16), S[idx])
+    Kref = O @ O.T
+    scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
+    err = np.abs(Ks - Kref) / scale
+    assert err.max() <= RTOL["bf16"], f"max normalised error {err.max():.3g}"
