@@ -117,3 +117,20 @@ def test_validation_rejects_before_launch(B):
     assert b"not sorted" in lib.vqmc_last_error()
     deg = np.array([0, 1, 3], np.int32)   # out of range
     assert lib.vqmc_pack(8, 3, fake, fake, deg.ctypes.data_as(ctypes.c_void_p), fake, fake, None) == B.EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libvqmc.so cannot be used: importing the binding raises
+    (there is no CPU or eager fallback for any call)."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2106_13308_amd")
+    dst = tmp_path / "paper_2106_13308_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__", "csrc"))
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "try:\n    import paper_2106_13308_amd.binding\nexcept ImportError as e:\n"
+            "    print('raised', e); sys.exit(0)\nsys.exit(1)\n")
+    r = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "libvqmc.so is missing" in r.stdout
