@@ -260,6 +260,14 @@ int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const 
 int vqmc_sr_gram(const vqmc_made* m, const int8_t* S, int64_t B, float* K, void* ws, size_t ws_bytes,
                  void* stream);
 
+/* vqmc_sr_gram for the spins vqmc_sample_fwd just drew, from its byproducts (the same
+ * quantities as above, Sec. 2.1 / 5.1): Zs (B x ld(n) floats, s_d z_d) and Rt (h x ld(B)
+ * values of type m->wdtype, relu(A), batch-contiguous) as vqmc_sample_fwd wrote them, both
+ * 16-byte aligned, so the forward pass is not recomputed.  Same K, limits and
+ * VQMC_WS_SR_GRAM workspace as vqmc_sr_gram; EINVAL for a misaligned Zs or Rt. */
+int vqmc_sr_gram_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const float* Zs, const void* Rt, float* K,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,
  * E, stats, coef and the gradient (dP, db1, db2).  With algo 0 and a band this is

@@ -74,6 +74,7 @@ _SIGS = {
     "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                              _sz, _vp]),
     "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
+    "vqmc_sr_gram_sampled": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(HamC), _i64, _u64, _u64, _i64, _i32,
                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_csr_from_edges": (ctypes.c_int, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp]),
@@ -359,6 +360,19 @@ def sr_gram(made: Made, S: torch.Tensor, B: int | None = None, ws: torch.Tensor 
     m = made.cstruct()
     _check("vqmc_sr_gram", _lib.vqmc_sr_gram(ctypes.byref(m), _dev(S).data_ptr(), B, K.data_ptr(), ws.data_ptr(),
                                               ws.numel(), _stream()))
+    return K
+
+
+def sr_gram_sampled(made: Made, S: torch.Tensor, Zs: torch.Tensor, Rt: torch.Tensor, B: int | None = None,
+                    ws: torch.Tensor | None = None, K: torch.Tensor | None = None) -> torch.Tensor:
+    """sr_gram for spins drawn by sample_fwd, from its Zs and Rt (no forward recompute)."""
+    B = S.shape[0] if B is None else B
+    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _dev(K)
+    ws = workspace(WS_SR_GRAM, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_sr_gram_sampled", _lib.vqmc_sr_gram_sampled(
+        ctypes.byref(m), _dev(S).data_ptr(), B, _dev(Zs).data_ptr(), _dev(Rt).data_ptr(), K.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream()))
     return K
 
 

@@ -312,6 +312,18 @@ int vqmc_sr_gram(const vqmc_made* m, const int8_t* S, int64_t B, float* K, void*
   return hip_status(launch_sr_gram(*m, S, B, K, ws, (hipStream_t)stream), "vqmc_sr_gram");
 }
 
+int vqmc_sr_gram_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const float* Zs, const void* Rt, float* K,
+                         void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || B > 65536 || !S || !Zs || !Rt || !K || !ws)
+    return fail(VQMC_EINVAL, "bad sr_gram_sampled arguments (1 <= B <= 65536)");
+  if (((uintptr_t)Zs | (uintptr_t)Rt) & 15) return fail(VQMC_EINVAL, "Zs and Rt must be 16-byte aligned");
+  const size_t need = sr_gram_ws_bytes(m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_sr_gram_sampled(*m, S, B, Zs, Rt, K, ws, (hipStream_t)stream), "vqmc_sr_gram_sampled");
+}
+
 int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed, uint64_t step,
               int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E, vqmc_stats* stats,
               float* coef, float* dP, float* db1, float* db2, void* ws, size_t ws_bytes, void* stream) {

@@ -859,6 +859,41 @@ static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
   return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st);
 }
 
+// The same Gram from the incremental sampler's byproducts: Zs (s_d z_d) gives G through the
+// output-layer adjoint with coef = 1 and Rt (relu(A)) is used as it is, so the two
+// forward products are not recomputed.
+template <typename T>
+static hipError_t sr_gram_sampled_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const T* Rt,
+                                    float* K, void* ws, hipStream_t st) {
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
+  uint8_t* w = (uint8_t*)ws;
+  T* G = (T*)(w + L.G);
+  T* Gt = (T*)(w + L.Gt);
+  T* St = (T*)(w + L.St);
+  T* Dt = (T*)(w + L.Dt);
+  float* db2_part = (float*)(w + L.db2_part);
+  float* db1_part = (float*)(w + L.db1_part);
+  const size_t xo = sr_extra_offset(m.n, m.h, B, m.wdtype);
+  float* ones = (float*)(w + xo);
+  float* parts = (float*)(w + xo + round_up(B * 4, 256));
+  hipError_t e;
+  fill_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ones, B, 1.f);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  grad_out_kernel<T><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(Zs, S, g.ldn, ones, m.n, B, G, Gt, St, g.ldB, db2_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st);
+}
+
+hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const void* Rt,
+                                  float* K, void* ws, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return sr_gram_sampled_t<bf16_t>(m, S, B, Zs, (const bf16_t*)Rt, K, ws, st);
+  return sr_gram_sampled_t<float>(m, S, B, Zs, (const float*)Rt, K, ws, st);
+}
+
 hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {
   if (m.wdtype == VQMC_BF16) return sr_gram_t<bf16_t>(m, S, B, K, ws, st);
   return sr_gram_t<float>(m, S, B, K, ws, st);

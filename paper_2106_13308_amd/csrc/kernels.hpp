@@ -59,6 +59,8 @@ hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t 
 // SR Gram (sr.hip): the factor rows come from the backward engine with coef = 1
 size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st);
+hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const void* Rt,
+                                  float* K, void* ws, hipStream_t st);
 size_t sr_gram_parts_bytes(int64_t B, int h);  // partial sums of the sweeps' work items + prefix lengths
 hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, const void* Dt, const void* St,
                                  int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* parts, float* K,

@@ -94,6 +94,9 @@ def test_validation_rejects_before_launch(B):
     assert lib.vqmc_sr_gram(ctypes.byref(ok), fake, 0, fake, fake, 1 << 30, None) == B.EINVAL
     assert lib.vqmc_sr_gram(ctypes.byref(ok), fake, 65537, fake, fake, 1 << 40, None) == B.EINVAL
     assert lib.vqmc_sr_gram(ctypes.byref(ok), fake, 8, None, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_sr_gram_sampled(ctypes.byref(ok), fake, 8, fake, fake, fake, fake, 16, None) == B.EWORKSPACE
+    assert lib.vqmc_sr_gram_sampled(ctypes.byref(ok), fake, 8, fake + 4, fake, fake, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_sr_gram_sampled(ctypes.byref(ok), fake, 8, None, fake, fake, fake, 1 << 30, None) == B.EINVAL
     nopt = B.MadeC(8, 4, B.F32, fake, None, fake, fake, fake)
     assert lib.vqmc_logprob(ctypes.byref(nopt), fake, 8, fake, None, fake, 1 << 30, None) == B.EINVAL
     H = B.HamC(8, 9, 0, fake, fake, fake, None)

@@ -81,3 +81,24 @@ def test_sr_gram_full_size_sampled_entries():
     scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
     err = np.abs(Ks - Kref) / scale
     assert err.max() <= RTOL["bf16"], f"max normalised error {err.max():.3g}"
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(67, 33, 100), (130, 70, 200), (20, 40, 64)])
+def test_sr_gram_sampled_matches_oracle(wd, n, h, B):
+    """vqmc_sr_gram_sampled on the spins vqmc_sample_fwd drew, from its Zs and Rt, against the
+    oracle's Gram of the same spins."""
+    from paper_2106_13308_amd import binding as Bd
+    wdt = Bd.F32 if wd == "f32" else Bd.BF16
+    print(f"[sr-gram-sampled] wd={wd} n={n} h={h} B={B}", flush=True)
+    p = inputs.made_init(n, h, 91)
+    made = build_made(p, wdt)
+    S, _, Zs, Rt = Bd.sample_fwd(made, B, 5, 3)
+    K = Bd.sr_gram_sampled(made, S, Zs, Rt, B).double().cpu().numpy()
+    torch.cuda.synchronize()
+    Snp = S[:, :n].cpu().numpy()
+    Kref = osr.gram(oracle_params(p, wdt), Snp)
+    scale = np.sqrt(np.outer(np.diag(Kref), np.diag(Kref)))
+    err = np.abs(K - Kref) / np.maximum(scale, 1e-30)
+    assert np.array_equal(K, K.T)
+    assert err.max() <= RTOL[wd], f"max normalised error {err.max():.3g}"
