@@ -116,7 +116,8 @@ enum {
   VQMC_WS_SAMPLE_PLAIN = 2,
   VQMC_WS_STEP = 3,
   VQMC_WS_BACKWARD_SAMPLED = 4,
-  VQMC_WS_SR_GRAM = 5
+  VQMC_WS_SR_GRAM = 5,
+  VQMC_WS_SR_JVP = 6
 };
 /* Workspace bytes needed by a call (host function, no device access). */
 size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
@@ -267,6 +268,17 @@ int vqmc_sr_gram(const vqmc_made* m, const int8_t* S, int64_t B, float* K, void*
  * VQMC_WS_SR_GRAM workspace as vqmc_sr_gram; EINVAL for a misaligned Zs or Rt. */
 int vqmc_sr_gram_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const float* Zs, const void* Rt, float* K,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* The other product of the SR solve (Sec. 2.1 / 5.1, Woodbury form): v = O g, v[b] =
+ * <grad log pi(s_b), g>, for a direction g in parameter space given like a gradient: gP
+ * n x h float32 packed like P32 (and dP), gb1 h floats, gb2 n floats (device).  The two
+ * masked layers are applied with g in place of the weights (the first without its ReLU)
+ * and contracted with the score factors of each sample; g is rounded to the weight dtype
+ * for the products.  v: B floats (device, overwritten).  Needs VQMC_WS_SR_JVP workspace.
+ * The rest of the SR direction x = (g - O^T (lambda B I + K)^{-1} O g) / lambda is
+ * vqmc_sr_gram (K) and vqmc_logprob_backward with coef = y (O^T y). */
+int vqmc_sr_jvp(const vqmc_made* m, const int8_t* S, int64_t B, const float* gP, const float* gb1, const float* gb2,
+                float* v, void* ws, size_t ws_bytes, void* stream);
 
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,

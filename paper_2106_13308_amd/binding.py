@@ -24,7 +24,7 @@ PAD = 64
 F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
-WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM = 0, 1, 2, 3, 4, 5
+WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM, WS_SR_JVP = 0, 1, 2, 3, 4, 5, 6
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
@@ -74,6 +74,7 @@ _SIGS = {
     "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                              _sz, _vp]),
     "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
+    "vqmc_sr_jvp": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_sr_gram_sampled": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(HamC), _i64, _u64, _u64, _i64, _i32,
                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -374,6 +375,19 @@ def sr_gram_sampled(made: Made, S: torch.Tensor, Zs: torch.Tensor, Rt: torch.Ten
         ctypes.byref(m), _dev(S).data_ptr(), B, _dev(Zs).data_ptr(), _dev(Rt).data_ptr(), K.data_ptr(),
         ws.data_ptr(), ws.numel(), _stream()))
     return K
+
+
+def sr_jvp(made: Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Tensor, gb2: torch.Tensor,
+           B: int | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """v = O g (B floats): the score of every sample contracted with the direction (gP, gb1, gb2)."""
+    B = S.shape[0] if B is None else B
+    v = torch.empty(B, dtype=torch.float32, device=S.device)
+    ws = workspace(WS_SR_JVP, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_sr_jvp", _lib.vqmc_sr_jvp(ctypes.byref(m), _dev(S).data_ptr(), B, _dev(gP).data_ptr(),
+                                            _dev(gb1).data_ptr(), _dev(gb2).data_ptr(), v.data_ptr(), ws.data_ptr(),
+                                            ws.numel(), _stream()))
+    return v
 
 
 @dataclass

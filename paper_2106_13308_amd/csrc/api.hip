@@ -111,6 +111,7 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_SAMPLE_PLAIN: return sample_plain_ws_bytes(n, h, B, wdtype);
     case VQMC_WS_STEP: return step_pm_offset(n, h, B, wdtype) + mask_w2t_bytes(n, h);
     case VQMC_WS_SR_GRAM: return sr_gram_ws_bytes(n, h, B, wdtype);
+    case VQMC_WS_SR_JVP: return sr_jvp_ws_bytes(n, h, B, wdtype);
     case VQMC_WS_BACKWARD_SAMPLED:
       return (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256) + mask_w2t_bytes(n, h);
     default: return 0;
@@ -322,6 +323,16 @@ int vqmc_sr_gram_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const f
   const size_t need = sr_gram_ws_bytes(m->n, m->h, B, m->wdtype);
   if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   return hip_status(launch_sr_gram_sampled(*m, S, B, Zs, Rt, K, ws, (hipStream_t)stream), "vqmc_sr_gram_sampled");
+}
+
+int vqmc_sr_jvp(const vqmc_made* m, const int8_t* S, int64_t B, const float* gP, const float* gb1, const float* gb2,
+                float* v, void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !gP || !gb1 || !gb2 || !v || !ws) return fail(VQMC_EINVAL, "bad sr_jvp arguments");
+  const size_t need = sr_jvp_ws_bytes(m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_sr_jvp(*m, S, B, gP, gb1, gb2, v, ws, (hipStream_t)stream), "vqmc_sr_jvp");
 }
 
 int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed, uint64_t step,

@@ -274,7 +274,9 @@ constexpr int W_BM = 64, W_BN = 64;     // weight gradient (M = n, N = h)
 // A = S * P_upper + b1 ; writes R = relu(A) (B x ldh) and optionally Rt (h x ldB).
 // Unit k receives site d iff c[d] <= k, i.e. d < count_le(c, k): a prefix of Pt's row.
 // N tiles run in decreasing order of their K range (largest first).
-template <typename T, bool WRITE_T>
+// RELU = false writes the pre-activation itself (the first layer applied to a direction in
+// parameter space, for the forward-mode product of the SR update).
+template <typename T, bool WRITE_T, bool RELU = true>
 __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restrict__ S, int64_t lds,
                                                           const T* __restrict__ Pt, int64_t ldn,
                                                           const float* __restrict__ b1,
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float a = acc[i][j][e] + bias;
-        vals[e] = from_f32<T>((k < h && bb + e < B) ? fmaxf(a, 0.f) : 0.f);
+        vals[e] = from_f32<T>((k < h && bb + e < B) ? (RELU ? fmaxf(a, 0.f) : a) : 0.f);
         if (bb + e < B && k < ldh) R[(bb + e) * ldh + k] = vals[e];
       }
       if (WRITE_T && k < h && bb + 3 < ldB) store4<T>(Rt + (int64_t)k * ldB + bb, vals);
@@ -897,6 +899,92 @@ hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B
 hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {
   if (m.wdtype == VQMC_BF16) return sr_gram_t<bf16_t>(m, S, B, K, ws, st);
   return sr_gram_t<float>(m, S, B, K, ws, st);
+}
+
+// Forward-mode product of the SR update: v[b] = <grad log pi(s_b), g> for a direction
+// g = (gP, gb1, gb2) in parameter space (gP packed like P, n x h float32):
+//   v_b = sum_d G_bd (gb2_d + sum_{k < c[d]} R_bk gP[d][k]) + sum_k D_bk (gb1_k + sum_{d : c[d] <= k} s_bd gP[d][k])
+// i.e. the two masked layers applied with g in place of the weights (the first without its
+// ReLU), each contracted with the score factors G and D of the same sample.
+template <typename T>
+__global__ __launch_bounds__(256) void sr_jvp_dot_kernel(const T* __restrict__ G, const float* __restrict__ U,
+                                                         int64_t ldn, int n, const T* __restrict__ Dt,
+                                                         const T* __restrict__ Vt, int64_t ldb, int h, int64_t B,
+                                                         float* __restrict__ v) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // one wave per sample
+  if (b >= B) return;
+  float s = 0.f;
+  for (int d = lane; d < n; d += 64) s = fmaf(to_f32<T>(G[b * ldn + d]), U[b * ldn + d], s);
+  for (int k = lane; k < h; k += 64) s = fmaf(to_f32<T>(Dt[(int64_t)k * ldb + b]), to_f32<T>(Vt[(int64_t)k * ldb + b]), s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) v[b] = s;
+}
+
+size_t sr_jvp_ws_bytes(int n, int h, int64_t B, int dtype) {
+  const size_t es = (dtype == VQMC_BF16) ? 2 : 4;
+  const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad);
+  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + (size_t)round_up(n * ldh * es, 256) +
+         (size_t)round_up(h * ldn * es, 256) + (size_t)round_up(B * ldn * 4, 256);
+}
+
+template <typename T>
+static hipError_t sr_jvp_t(const vqmc_made& m, const int8_t* S, int64_t B, const float* gP, const float* gb1,
+                           const float* gb2, float* v, void* ws, hipStream_t st) {
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 1);
+  uint8_t* w = (uint8_t*)ws;
+  T* R = (T*)(w + L.R);
+  T* Rt = (T*)(w + L.Rt);
+  T* G = (T*)(w + L.G);
+  T* Gt = (T*)(w + L.Gt);
+  T* St = (T*)(w + L.St);
+  T* Dt = (T*)(w + L.Dt);
+  float* lp_part = (float*)(w + L.lp_part);
+  float* db2_part = (float*)(w + L.db2_part);
+  float* db1_part = (float*)(w + L.db1_part);
+  const size_t es = sizeof(T);
+  size_t off = sr_extra_offset(m.n, m.h, B, m.wdtype);
+  float* ones = (float*)(w + off);
+  off += round_up(B * 4, 256);
+  T* gPw = (T*)(w + off);
+  off += round_up(m.n * g.ldh * (int64_t)es, 256);
+  T* gPtw = (T*)(w + off);
+  off += round_up(m.h * g.ldn * (int64_t)es, 256);
+  float* U = (float*)(w + off);
+  hipError_t e;
+  fill_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ones, B, 1.f);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // score factors: R (and Rt), G with coef = 1, D
+  fwd_hidden_kernel<T, true><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c,
+                                                                    m.n, m.h, B, R, g.ldh, Rt, g.ldB);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  fwd_out_kernel<T, 1><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, nullptr, ones, G, Gt,
+      St, g.ldB, db2_part, 0, 0, 0, 0, 0, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the direction in the kernels' layouts
+  if ((e = launch_cast(m.n, m.h, gP, m.wdtype, gPw, gPtw, st)) != hipSuccess) return e;
+  // U = gb2 + R (masked gW2)^T
+  fwd_out_kernel<T, 0><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, gPw, gb2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, U, nullptr, nullptr, nullptr,
+      nullptr, g.ldB, nullptr, 0, 0, 0, 0, 0, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // V = gb1 + S (masked gW1)^T without the ReLU, batch-contiguous in the Rt slot (R no longer needed)
+  fwd_hidden_kernel<T, true, false><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, gPtw, g.ldn, gb1, m.c, m.n,
+                                                                           m.h, B, R, g.ldh, Rt, g.ldB);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  sr_jvp_dot_kernel<T><<<(unsigned)((B + 3) / 4), 256, 0, st>>>(G, U, g.ldn, m.n, Dt, Rt, g.ldB, m.h, B, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sr_jvp(const vqmc_made& m, const int8_t* S, int64_t B, const float* gP, const float* gb1,
+                         const float* gb2, float* v, void* ws, hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return sr_jvp_t<bf16_t>(m, S, B, gP, gb1, gb2, v, ws, st);
+  return sr_jvp_t<float>(m, S, B, gP, gb1, gb2, v, ws, st);
 }
 
 // Backward from the incremental sampler's byproducts: Rt (relu(A), batch-contiguous, in

@@ -59,6 +59,9 @@ hipError_t launch_backward_sampled(const vqmc_made& m, const int8_t* S, int64_t 
 // SR Gram (sr.hip): the factor rows come from the backward engine with coef = 1
 size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sr_gram(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st);
+size_t sr_jvp_ws_bytes(int n, int h, int64_t B, int dtype);
+hipError_t launch_sr_jvp(const vqmc_made& m, const int8_t* S, int64_t B, const float* gP, const float* gb1,
+                         const float* gb2, float* v, void* ws, hipStream_t st);
 hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const void* Rt,
                                   float* K, void* ws, hipStream_t st);
 size_t sr_gram_parts_bytes(int64_t B, int h);  // partial sums of the sweeps' work items + prefix lengths

@@ -122,3 +122,23 @@ def train(trainer: Trainer, steps: int, jsonl: str | None = None, target_cut=Non
     if f:
         f.close()
     return rec, hit
+
+
+def sr_direction(made: B.Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Tensor, gb2: torch.Tensor,
+                 lam: float, n_samples: int | None = None):
+    """Stochastic-reconfiguration (natural-gradient) direction x = (I_hat + lam I)^{-1} g, with
+    I_hat = O^T O / B the batch Fisher matrix of the per-sample scores (Sec. 2.1) and the ridge
+    lam of Sec. 5.1, through the sample-space Gram (Woodbury identity):
+
+        x = (g - O^T (lam B I + K)^{-1} O g) / lam,   K = O O^T.
+
+    K, O g and O^T y are library calls (vqmc_sr_gram, vqmc_sr_jvp, vqmc_logprob_backward with
+    coef = y); the B x B solve is the optimiser's own step, in float64 torch like the Adam
+    update.  g and x are packed like the gradient (n x h, h, n)."""
+    nb = S.shape[0] if n_samples is None else n_samples
+    K = B.sr_gram(made, S, nb)
+    v = B.sr_jvp(made, S, gP, gb1, gb2, nb)
+    A = K.double() + lam * nb * torch.eye(nb, dtype=torch.float64, device=K.device)
+    y = torch.linalg.solve(A, v.double().unsqueeze(1)).squeeze(1).float().contiguous()
+    dP, db1, db2 = B.logprob_backward(made, S, y, nb)
+    return (gP - dP) / lam, (gb1 - db1) / lam, (gb2 - db2) / lam

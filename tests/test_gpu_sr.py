@@ -102,3 +102,68 @@ def test_sr_gram_sampled_matches_oracle(wd, n, h, B):
     err = np.abs(K - Kref) / np.maximum(scale, 1e-30)
     assert np.array_equal(K, K.T)
     assert err.max() <= RTOL[wd], f"max normalised error {err.max():.3g}"
+
+
+def _packed_direction(p, seed):
+    """A random direction g in the oracle's form and packed like P (n x h): P[d][k] = gW2[d][k]
+    where unit k feeds site d (degree m(k) <= d, 0-based d), else gW1[k][d]."""
+    from oracle import made as omade
+    n, h = p["W2"].shape
+    rng = np.random.default_rng(seed)
+    M1, M2 = omade.masks(n, p["degrees"])
+    g = {"W1": rng.standard_normal((h, n)) * M1, "b1": rng.standard_normal(h),
+         "W2": rng.standard_normal((n, h)) * M2, "b2": rng.standard_normal(n)}
+    gP = np.where(M2 > 0, g["W2"], g["W1"].T)
+    return g, gP, M1, M2
+
+
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(20, 40, 64), (67, 33, 100), (130, 70, 200)])
+def test_sr_jvp_matches_oracle(wd, n, h, B):
+    """v = O g against the oracle's explicit score matrix; each v_b within rtol of
+    sum_p |O_bp g_p| (FP32 1e-4; BF16 3e-2: g and the factors are rounded to BF16)."""
+    from paper_2106_13308_amd import binding as Bd
+    from oracle import bf16 as obf16
+    wdt = Bd.F32 if wd == "f32" else Bd.BF16
+    print(f"[sr-jvp] wd={wd} n={n} h={h} B={B}", flush=True)
+    p = inputs.made_init(n, h, 101)
+    S = inputs.random_spins(B, n, 102)
+    made = build_made(p, wdt)
+    Sd = torch.zeros((B, Bd.ld(n)), dtype=torch.int8, device=DEV)
+    Sd[:, :n] = torch.from_numpy(S).to(DEV)
+    g, gP, M1, M2 = _packed_direction(p, 103)
+    gPd = torch.from_numpy(gP.astype(np.float32)).to(DEV).contiguous()
+    v = Bd.sr_jvp(made, Sd, gPd, torch.from_numpy(g["b1"].astype(np.float32)).to(DEV),
+                  torch.from_numpy(g["b2"].astype(np.float32)).to(DEV), B).double().cpu().numpy()
+    q = oracle_params(p, wdt)
+    O = osr.score_matrix(q, S)
+    gv = osr.flatten(q, g)
+    ref = O @ gv
+    scale = np.abs(O) @ np.abs(gv)
+    rtol = 1e-4 if wd == "f32" else 3e-2
+    assert (np.abs(v - ref) <= rtol * scale).all(), float((np.abs(v - ref) / scale).max())
+
+
+@pytest.mark.parametrize("lam", [0.1, 1e-3])
+def test_sr_direction_matches_oracle(lam):
+    """The whole SR direction (library K, O g, O^T y; B x B solve in torch) against the
+    oracle's d x d solve, FP32 weights: max |x - x_ref| <= 2e-3 max |x_ref|."""
+    from paper_2106_13308_amd import binding as Bd
+    from paper_2106_13308_amd.vqmc import sr_direction
+    n, h, B = 20, 40, 64
+    print(f"[sr-direction] lam={lam} n={n} h={h} B={B}", flush=True)
+    p = inputs.made_init(n, h, 111)
+    S = inputs.random_spins(B, n, 112)
+    made = build_made(p, Bd.F32)
+    Sd = torch.zeros((B, Bd.ld(n)), dtype=torch.int8, device=DEV)
+    Sd[:, :n] = torch.from_numpy(S).to(DEV)
+    g, gP, M1, M2 = _packed_direction(p, 113)
+    xP, xb1, xb2 = sr_direction(made, Sd, torch.from_numpy(gP.astype(np.float32)).to(DEV).contiguous(),
+                                torch.from_numpy(g["b1"].astype(np.float32)).to(DEV),
+                                torch.from_numpy(g["b2"].astype(np.float32)).to(DEV), lam)
+    xP = xP.double().cpu().numpy()
+    x = {"W1": (xP.T) * M1, "b1": xb1.double().cpu().numpy(), "W2": xP * M2, "b2": xb2.double().cpu().numpy()}
+    q = oracle_params(p, Bd.F32)
+    ref = osr.sr_direction(q, S, osr.flatten(q, g), lam)
+    got = osr.flatten(q, x)
+    assert np.abs(got - ref).max() <= 2e-3 * np.abs(ref).max(), float(np.abs(got - ref).max() / np.abs(ref).max())
