@@ -2,7 +2,8 @@
 
 Setup (Sec. 5.1): one instance per size n in {20, 50, 100, 200, 500}, built as
 G(n, 1/4) with unit weights (``inputs.paper_maxcut_graph``); a MADE with
-h = 5 (ln n)^2 hidden units; Adam with learning rate 0.01; 1024 training samples per
+h = 5 (ln n)^2 hidden units; Adam with learning rate 0.01 (or, with ``--optimizer sr``,
+SGD on the SR direction with learning rate 0.1 and lambda = 0.001); 1024 training samples per
 iteration; 300 iterations; several training seeds per instance.  After every update a
 fresh batch of 1024 evaluation samples is drawn (its own Philox stream) and its mean
 cut is the evaluation score; evaluation time is excluded from the wall clock
@@ -32,17 +33,19 @@ import torch
 
 from . import binding as B
 from . import inputs
-from .vqmc import Trainer
+from .vqmc import SRTrainer, Trainer
 
 DTYPES = {"f32": B.F32, "bf16": B.BF16, "f64": B.F64}
 
 
 def make_trainer(n: int, seed: int, wdtype: int, lr: float = 0.01, batch: int = 1024,
-                 graph_seed: int = 0):
+                 graph_seed: int = 0, optimizer: str = "adam"):
     w = inputs.WORKLOADS[f"paper_maxcut{n}"]
     inst = inputs.make_instance(w, graph_seed=graph_seed, init_seed=1000 + seed)
     made = B.Made.from_dense(inst["W1"], inst["b1"], inst["W2"], inst["b2"], inst["degrees"], wdtype=wdtype)
     H = B.Hamiltonian.from_edges(n, inst["edges"], inst["weights"])
+    if optimizer == "sr":
+        return SRTrainer(made, H, batch, seed=seed, lr=lr), inst
     return Trainer(made, H, batch, seed=seed, lr=lr), inst
 
 
@@ -73,14 +76,14 @@ def _mean(xs):
     return sum(xs) / len(xs) if xs else None
 
 
-def run_size(n: int, seeds: int, iters: int, wdtype: int, lr: float) -> dict:
+def run_size(n: int, seeds: int, iters: int, wdtype: int, lr: float, optimizer: str = "adam") -> dict:
     edges = inputs.paper_maxcut_graph(n, 0)
     m = len(edges)
     paper_t = inputs.PAPER_TARGET_CUTS[n]
     targets = {"paper": paper_t, "scaled": round(paper_t * m / (n * (n - 1) / 8))}
     runs = []
     for s in range(seeds):
-        tr, _ = make_trainer(n, s, wdtype, lr)
+        tr, _ = make_trainer(n, s, wdtype, lr, optimizer=optimizer)
         r = run_one(tr, iters, targets)
         runs.append(r)
         print(f"[protocol] n={n} seed={s}: eval mean cut {r['final_eval_mean_cut']:.2f} "
@@ -107,7 +110,9 @@ def main():
     ap.add_argument("--sizes", type=int, nargs="+", default=list(inputs.PAPER_MAXCUT_SIZES))
     ap.add_argument("--seeds", type=int, default=5)
     ap.add_argument("--iters", type=int, default=300)
-    ap.add_argument("--lr", type=float, default=0.01)
+    ap.add_argument("--optimizer", choices=["adam", "sr"], default="adam",
+                    help="Adam (lr 0.01) or SGD on the SR direction (lr 0.1, lambda 1e-3), Sec. 5.1")
+    ap.add_argument("--lr", type=float, default=None, help="default 0.01 for Adam, 0.1 for SR")
     ap.add_argument("--wdtype", choices=sorted(DTYPES), default="f32")
     a = ap.parse_args()
     if not torch.cuda.is_available():
@@ -116,8 +121,9 @@ def main():
     for n in a.sizes:
         if n not in inputs.PAPER_TARGET_CUTS:
             sys.exit(f"protocol: n={n} is not one of the paper's sizes {inputs.PAPER_MAXCUT_SIZES}")
-        r = run_size(n, a.seeds, a.iters, DTYPES[a.wdtype], a.lr)
-        r["wdtype"] = a.wdtype
+        lr = a.lr if a.lr is not None else (0.1 if a.optimizer == "sr" else 0.01)
+        r = run_size(n, a.seeds, a.iters, DTYPES[a.wdtype], lr, a.optimizer)
+        r["wdtype"], r["optimizer"], r["lr"] = a.wdtype, a.optimizer, lr
         print(json.dumps(r), flush=True)
         res.append(r)
     print(json.dumps({"summary": [{k: r[k] for k in ("n", "edges", "final_eval_mean_cut", "time_to_paper_s",

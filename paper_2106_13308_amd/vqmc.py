@@ -142,3 +142,36 @@ def sr_direction(made: B.Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Ten
     y = torch.linalg.solve(A, v.double().unsqueeze(1)).squeeze(1).float().contiguous()
     dP, db1, db2 = B.logprob_backward(made, S, y, nb)
     return (gP - dP) / lam, (gb1 - db1) / lam, (gb2 - db2) / lam
+
+
+class SRTrainer(Trainer):
+    """VQMC with stochastic reconfiguration (Sec. 2.1 natural gradient; Sec. 5.1: SGD on the SR
+    direction, learning rate 0.1, ridge lambda = 0.001).  Each step is ``vqmc_step`` (samples,
+    energies, the gradient g) followed by ``sr_direction`` on the same samples and the update
+    theta -= lr x on the FP32 master parameters, then a refresh of the working copies."""
+
+    def __init__(self, made: B.Made, H: B.Hamiltonian, batch: int, seed: int = 2, lr: float = 0.1,
+                 lam: float = 1e-3, algo: int = 0):
+        super().__init__(made, H, batch, seed=seed, lr=lr, algo=algo)
+        self.lr, self.lam = lr, lam
+
+    def step(self, log: bool = True) -> dict | None:
+        with torch.no_grad():
+            B.step(self.made, self.H, self.batch, self.seed, self.t, self.bufs, algo=self.algo)
+            xP, xb1, xb2 = sr_direction(self.made, self.bufs.S, self.bufs.dP, self.bufs.db1, self.bufs.db2,
+                                        self.lam, self.batch)
+            self.made.P32.sub_(self.lr * xP)
+            self.made.b1.sub_(self.lr * xb1)
+            self.made.b2.sub_(self.lr * xb2)
+            self.made.refresh()
+        self.t += 1
+        if not log:
+            return None
+        st = B.stats_to_dict(self.bufs.stats)
+        if self.best_E is None or st["min"] < self.best_E:
+            self.best_E = st["min"]
+        out = {"step": self.t, "mean_E": st["mean"], "var_E": st["var"], "min_E": st["min"], "best_E": self.best_E}
+        if self.H.W_tot is not None:
+            out["best_cut"] = (self.H.W_tot - self.best_E) / 2
+            out["mean_cut"] = (self.H.W_tot - st["mean"]) / 2
+        return out
