@@ -138,8 +138,10 @@ def sr_direction(made: B.Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Ten
     nb = S.shape[0] if n_samples is None else n_samples
     K = B.sr_gram(made, S, nb)
     v = B.sr_jvp(made, S, gP, gb1, gb2, nb)
+    # lam B I + K is symmetric positive definite (K is a Gram matrix): Cholesky, in float64
     A = K.double() + lam * nb * torch.eye(nb, dtype=torch.float64, device=K.device)
-    y = torch.linalg.solve(A, v.double().unsqueeze(1)).squeeze(1).float().contiguous()
+    Lc = torch.linalg.cholesky(A)
+    y = torch.cholesky_solve(v.double().unsqueeze(1), Lc).squeeze(1).float().contiguous()
     dP, db1, db2 = B.logprob_backward(made, S, y, nb)
     return (gP - dP) / lam, (gb1 - db1) / lam, (gb2 - db2) / lam
 
