@@ -32,7 +32,7 @@ def batch_stats(E, W_tot=None) -> dict:
     return out
 
 
-def logp_grad(params: dict, S, coef) -> dict:
+def logp_grad(params: dict, S, coef, active=None) -> dict:
     """Gradient of F(theta) = sum_b coef_b log pi(s_b) with respect to W1, b1, W2, b2.
 
     Chain rule through the MADE forward pass:
@@ -40,7 +40,13 @@ def logp_grad(params: dict, S, coef) -> dict:
         dF/dW2    = M2 . (G^T R),          dF/db2 = sum_b G
         dF/da_bk  = [a_bk > 0] (G (M2.W2))_bk                (reading R10 at a = 0)
         dF/dW1    = M1 . (Ga^T S),         dF/db1 = sum_b Ga
-    Masked entries of dW1/dW2 are exactly zero."""
+    Masked entries of dW1/dW2 are exactly zero.
+
+    ``active`` (optional, B x h booleans) replaces the ReLU gate [a_bk > 0] where a caller
+    has to take a pre-activation's side from elsewhere: a pre-activation within rounding of
+    0 has no well-defined side in finite precision, so a parity test takes the side the
+    evaluated path took there (as the sampled spins are teacher-forced) and the oracle's
+    own sign everywhere else."""
     p = made.as_f64(params)
     S = np.asarray(S, dtype=np.float64)
     coef = np.asarray(coef, dtype=np.float64)
@@ -50,7 +56,8 @@ def logp_grad(params: dict, S, coef) -> dict:
     G = coef[:, None] * S * made.sigmoid(-S * f["Z"])
     dW2 = M2 * (G.T @ f["R"])
     db2 = G.sum(axis=0)
-    Ga = (G @ (M2 * p["W2"])) * (f["A"] > 0)
+    gate = f["A"] > 0 if active is None else np.asarray(active, dtype=bool)
+    Ga = (G @ (M2 * p["W2"])) * gate
     dW1 = M1 * (Ga.T @ S)
     db1 = Ga.sum(axis=0)
     return {"W1": dW1, "b1": db1, "W2": dW2, "b2": db2}

@@ -12,8 +12,14 @@ rows of O (B x d, over every unmasked parameter: W1 and W2 inside their masks, b
     x     = (I_hat + lambda I_d)^{-1} g                 (the SR direction for a gradient g)
           = (g - O^T (lambda B I_B + K)^{-1} O g) / lambda     (Woodbury identity)
 
+When g is the batch gradient itself, g = O^T c with the coefficients c_b of Sec. 2.1
+(reading R6), the push-through identity (O^T O / B + lambda I) O^T = O^T (K / B + lambda I)
+gives the direction without any d-dimensional solve or division by lambda:
+
+    x = O^T y,   (K + lambda B I_B) y = B c.
+
 ``sr_direction`` solves the d x d system as written; ``sr_direction_woodbury`` goes
-through K.  Nothing here is blocked or fused: O is formed explicitly, one sample at a
+through K for any g; ``sr_direction_coef`` takes c and uses the push-through form.  Nothing here is blocked or fused: O is formed explicitly, one sample at a
 time, from :func:`oracle.estimator.logp_grad`.
 """
 from __future__ import annotations
@@ -65,3 +71,12 @@ def sr_direction_woodbury(params: dict, S, g, lam: float) -> np.ndarray:
     g = np.asarray(g, np.float64)
     y = np.linalg.solve(lam * B * np.eye(B) + O @ O.T, O @ g)
     return (g - O.T @ y) / lam
+
+
+def sr_direction_coef(params: dict, S, coef, lam: float) -> np.ndarray:
+    """x for g = O^T c (the batch gradient of Sec. 2.1 with coefficients c): y solves
+    (K + lambda B I) y = B c and x = O^T y."""
+    O = score_matrix(params, S)
+    B = O.shape[0]
+    y = np.linalg.solve(O @ O.T + lam * B * np.eye(B), B * np.asarray(coef, np.float64))
+    return O.T @ y

@@ -63,3 +63,21 @@ def instance(n, h, seed=1, graph="regular", deg=3, gseed=0, scale=1.0):
     else:
         edges = None
     return p, edges
+
+
+def relu_gates(p: dict, S, Rt: torch.Tensor, tau: float = 1e-5):
+    """The ReLU gate for the oracle's gradient, teacher-forced where the pre-activation is
+    within rounding of 0.
+
+    Rt is the evaluated path's relu(A), h x ld(B) (as vqmc_sample_fwd writes it); its gate
+    is Rt > 0.  Where |a_ref| <= tau * (sum of |summands| of a) the oracle takes that side,
+    elsewhere its own sign.  Returns (gate B x h, number of teacher-forced entries, number
+    of those where the two sides differ)."""
+    f, sc = logit_scale(p, S)
+    B = S.shape[0]
+    gpu = (Rt[:, :B].float().cpu().numpy().T > 0)
+    amb = np.abs(f["A"]) <= tau * sc["a"]
+    gate = np.where(amb, gpu, f["A"] > 0)
+    # outside the ambiguous band the evaluated path must agree with the oracle's sign
+    assert np.array_equal(gpu[~amb], (f["A"] > 0)[~amb]), "ReLU side differs away from 0"
+    return gate, int(amb.sum()), int((gpu != (f["A"] > 0))[amb].sum())

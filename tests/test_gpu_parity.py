@@ -19,7 +19,7 @@ from oracle import philox as oph
 from oracle import sampling as osmp
 from paper_2106_13308_amd import inputs
 
-from gpu_util import DEV, build_made, instance, logit_scale, logp_bound, oracle_params, spins_np
+from gpu_util import DEV, build_made, instance, logit_scale, logp_bound, oracle_params, relu_gates, spins_np
 
 pytestmark = pytest.mark.gpu
 
@@ -514,7 +514,9 @@ def test_sample_deterministic():
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("n,h,B", [(20, 40, 128), (67, 33, 70), (130, 130, 64)])
+@pytest.mark.parametrize("n,h,B", [(20, 40, 128), (67, 33, 70), (130, 130, 64),
+                                   # the n = h = 500, B = 4096 workload, and several hidden tiles
+                                   (500, 500, 4096), (1000, 2000, 64)])
 def test_sample_plain_matches_incremental(n, h, B):
     _banner(f"plain sampler n={n} h={h} B={B}")
     p, _ = instance(n, h, seed=12, graph=None, scale=3.0)
@@ -533,7 +535,9 @@ def test_sample_plain_matches_incremental(n, h, B):
 @pytest.mark.parametrize("wd", ["bf16", "f32"])
 def test_gradient_error_full_size_subset(wd):
     """n = 10^4, h = 2000, B = 2048: the score gradient of a 256-sample subset (with c_b
-    from the whole batch) against the FP64 oracle."""
+    from the whole batch) against the FP64 oracle, computed by the kernels vqmc_step runs
+    (vqmc_backward_sampled on the sampler's own byproducts), with the ReLU side
+    teacher-forced where a pre-activation lies within rounding of 0."""
     _banner(f"gradient error n=10000 h=2000 subset=256 {wd}")
     wdtype = B_.F32 if wd == "f32" else B_.BF16
     w = inputs.WORKLOADS["maxcut10k_h2000"]
@@ -542,16 +546,20 @@ def test_gradient_error_full_size_subset(wd):
     H = B_.Hamiltonian.from_edges(w.n, inst["edges"], inst["weights"], device=DEV)
     bufs = B_.StepBuffers.allocate(M, H, w.B)
     B_.step(M, H, w.B, 2, 0, bufs)
+    S, _, Zs, Rt = B_.sample_fwd(M, w.B, 2, 0)
+    assert torch.equal(S, bufs.S)
     sub = np.arange(0, w.B, w.B // 256)
     coef = bufs.coef.cpu().numpy()
     mask = np.zeros(w.B, np.float32)
     mask[sub] = 1
     coef_sub = torch.from_numpy(coef * mask).to(DEV)
-    dP, db1, db2 = B_.logprob_backward(M, bufs.S, coef_sub)
+    dP, db1, db2 = B_.backward_sampled(M, S, coef_sub, Zs, Rt)
     dW1, dW2 = M.unpack(dP)
     S_np = spins_np(bufs.S, w.n)
     q = oracle_params(inst, wdtype)
-    g = oest.logp_grad(q, S_np[sub], coef[sub].astype(np.float64))
+    gate, n_forced, n_flip = relu_gates(q, S_np[sub], Rt[:, sub].contiguous())
+    print(f"  ReLU sides teacher-forced: {n_forced} ({n_flip} differ from the FP64 sign)")
+    g = oest.logp_grad(q, S_np[sub], coef[sub].astype(np.float64), active=gate)
     tol = 1e-4 if wd == "f32" else 3e-2
     for k, got in (("W1", dW1), ("W2", dW2), ("b1", db1), ("b2", db2)):
         got = got.cpu().numpy()
@@ -559,6 +567,37 @@ def test_gradient_error_full_size_subset(wd):
         rel = err / np.abs(g[k]).max()
         fro = np.linalg.norm(got - g[k]) / np.linalg.norm(g[k])
         print(f"  {k}: max abs err {err:.3e}, max-normalised {rel:.3e}, relative Frobenius {fro:.3e}")
+        assert rel <= tol, k
+
+
+@pytest.mark.parametrize("wd", ["bf16", "f32"])
+@pytest.mark.parametrize("n,h,B", [(2000, 500, 512), (10000, 1000, 2048)])
+def test_step_gradient_matches_oracle_full_batch(n, h, B, wd):
+    """The gradient vqmc_step returns (sampler byproducts -> the backward the bench times),
+    whole batch, against the FP64 oracle's gradient on the same spins and coefficients."""
+    _banner(f"step gradient vs oracle n={n} h={h} B={B} {wd}")
+    wdtype = B_.F32 if wd == "f32" else B_.BF16
+    p, edges = instance(n, h, seed=19, graph="regular", deg=10, scale=2.0)
+    w = inputs.integer_weights(len(edges), 1, 5, 5)
+    M = build_made(p, wdtype)
+    H = B_.Hamiltonian.from_edges(n, edges, w, device=DEV)
+    bufs = B_.StepBuffers.allocate(M, H, B)
+    B_.step(M, H, B, 3, 1, bufs)
+    S, _, _, Rt = B_.sample_fwd(M, B, 3, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(S, bufs.S)
+    S_np = spins_np(bufs.S, n)
+    q = oracle_params(p, wdtype)
+    gate, n_forced, n_flip = relu_gates(q, S_np, Rt)
+    print(f"  ReLU sides teacher-forced: {n_forced} ({n_flip} differ from the FP64 sign)")
+    g = oest.logp_grad(q, S_np, bufs.coef.cpu().numpy().astype(np.float64), active=gate)
+    dW1, dW2 = M.unpack(bufs.dP)
+    tol = 1e-4 if wd == "f32" else 3e-2
+    for k, got in (("W1", dW1), ("W2", dW2), ("b1", bufs.db1), ("b2", bufs.db2)):
+        got = got.cpu().numpy()
+        rel = np.abs(got - g[k]).max() / np.abs(g[k]).max()
+        fro = np.linalg.norm(got - g[k]) / np.linalg.norm(g[k])
+        print(f"  {k}: max-normalised {rel:.3e}, relative Frobenius {fro:.3e}")
         assert rel <= tol, k
 
 
@@ -605,20 +644,38 @@ def test_step_fused_equals_recompute(n, h, B, wd):
     dP, db1, db2 = B_.logprob_backward(M, bufs.S, bufs.coef)
     lp_ref = B_.logprob(M, bufs.S)
     torch.cuda.synchronize()
-    # Both gradients are FP32 evaluations of the same function; where a pre-activation
-    # lies within FP32 rounding of 0 the two can take different sides of the ReLU, which
-    # moves a whole column of the W1 gradient.  At small sizes no such tie occurs and the
-    # bar is the rounding level; at n = 10^4 (2 x 10^6 pre-activations) a few do, so the
-    # bar there is on the Frobenius error with a looser max-norm.
-    small = n * h * B < 1e8
-    tol_max = (1e-4 if wd == "f32" else 2e-2) if small else (1e-2 if wd == "f32" else 3e-2)
-    tol_fro = (1e-4 if wd == "f32" else 1e-2) if small else (1e-3 if wd == "f32" else 1e-2)
+    # Both gradients are FP32 evaluations of the same function; where a pre-activation lies
+    # within FP32 rounding of 0 the two can take different sides of the ReLU, which moves
+    # unit k's first-layer gradient (its column of dP on the sites feeding it, and db1_k) by
+    # the adjoint Ga_bk of that sample.  The bar is the rounding level everywhere, plus, on
+    # such a unit's W1 entries only, the sum of |Ga_bk| over its ties: so every larger
+    # difference is shown to come from a pre-activation within rounding of 0.
+    tol_max = 1e-4 if wd == "f32" else (2e-2 if n * h * B < 1e8 else 3e-2)
+    tol_fro = 1e-4 if wd == "f32" else 1e-2
+    S_np = spins_np(bufs.S, n)
+    q = oracle_params(p, wdtype)
+    f, sc = logit_scale(q, S_np)
+    ties = np.abs(f["A"]) <= 1e-5 * sc["a"]
+    allow = np.zeros(h)
+    if ties.any():
+        M1, M2 = omade.masks(n, q["degrees"])
+        Sf = S_np.astype(np.float64)
+        G = bufs.coef.cpu().numpy().astype(np.float64)[:, None] * Sf * omade.sigmoid(-Sf * f["Z"])
+        Ga = G @ (M2 * np.asarray(q["W2"], np.float64))
+        allow = (np.abs(Ga) * ties).sum(axis=0)
+    print(f"  pre-activations within rounding of 0: {int(ties.sum())}")
+    c = M.c.cpu().numpy()
+    w1_part = np.arange(h)[None, :] >= c[:, None]            # P[d][k] is a W1 weight
     for k, got, ref in (("dP", bufs.dP, dP), ("db1", bufs.db1, db1), ("db2", bufs.db2, db2)):
         got, ref = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
-        err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
-        fro = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
-        print(f"  {k}: max err / max |ref| = {err:.2e}, relative Frobenius {fro:.2e}")
-        assert err <= tol_max and fro <= tol_fro, k
+        scale = max(np.abs(ref).max(), 1e-30)
+        diff = np.abs(got - ref)
+        slack = {"dP": w1_part * allow[None, :], "db1": allow, "db2": 0.0}[k]
+        worst = float(((diff - slack) / scale).max())
+        fro = np.linalg.norm(np.maximum(diff - slack, 0)) / max(np.linalg.norm(ref), 1e-30)
+        print(f"  {k}: max err / max |ref| = {diff.max() / scale:.2e} ({worst:.2e} beyond the ties), "
+              f"relative Frobenius beyond the ties {fro:.2e}")
+        assert worst <= tol_max and fro <= tol_fro, k
     # the recomputing forward keeps relu(A) in the weight dtype for its second product; the
     # sampler's logits use the FP32 activations, so with BF16 the two differ at that level
     lp, lr = bufs.logp.cpu().numpy(), lp_ref.cpu().numpy()

@@ -197,3 +197,56 @@ def test_P9_batch_mean_baseline_bias(n, B):
     gL = np.concatenate([ex["grad"][k].ravel() for k in keys])
     assert np.abs(gL).max() > 1e-3
     assert np.allclose(expect, (1 - 1 / B) * gL, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,B", [(5, 2), (3, 3)])
+def test_P9_score_gradient_expectation(n, B):
+    """score_gradient as a whole (coefficients from batch_stats, then the gradient): its
+    expectation over B i.i.d. draws equals (1 - 1/B) grad L, with grad L from enumeration."""
+    h = 6
+    p = inputs.made_init(n, h, 14)
+    p["W1"] *= 3
+    p["W2"] *= 3
+    allS = exact.all_strings(n)
+    edges = inputs.complete_graph(n)
+    w = inputs.integer_weights(len(edges), 1, 5, 4)
+    E = energy.energy_edges(edges, w, allS)
+    ex = exact.exact_objective(p, E.astype(np.float64))
+    pi = ex["pi"]
+    N = allS.shape[0]
+    keys = ("W1", "b1", "W2", "b2")
+    expect = {k: np.zeros_like(ex["grad"][k]) for k in keys}
+    for tup in itertools.product(range(N), repeat=B):
+        idx = np.array(tup)
+        g = estimator.score_gradient(p, allS[idx], E[idx])
+        prob = np.prod(pi[idx])
+        for k in keys:
+            expect[k] += prob * g[k]
+    for k in keys:
+        assert np.allclose(expect[k], (1 - 1 / B) * ex["grad"][k], rtol=0, atol=1e-12), k
+
+
+def test_logp_grad_gate_override():
+    """The teacher-forcing gate of logp_grad: the oracle's own gate reproduces the default,
+    and flipping one (b, k) entry moves only unit k's first-layer row and b1_k, by that
+    sample's back-propagated adjoint (which the default gradient with only sample b and a
+    forced-open gate isolates)."""
+    n, h, B = 8, 6, 5
+    p = inputs.made_init(n, h, 15)
+    S = inputs.random_spins(B, n, 16)
+    coef = np.random.default_rng(17).standard_normal(B)
+    A = made.forward(p, S)["A"]
+    g0 = estimator.logp_grad(p, S, coef)
+    g1 = estimator.logp_grad(p, S, coef, active=A > 0)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+    gate = A > 0
+    b, k = 2, 3
+    gate[b, k] = ~gate[b, k]
+    g2 = estimator.logp_grad(p, S, coef, active=gate)
+    for name in ("W2", "b2"):
+        assert np.array_equal(g0[name], g2[name])
+    other = np.ones(h, bool)
+    other[k] = False
+    assert np.array_equal(g0["W1"][other], g2["W1"][other]) and np.array_equal(g0["b1"][other], g2["b1"][other])
+    assert g0["b1"][k] != g2["b1"][k]

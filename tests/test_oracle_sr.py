@@ -5,7 +5,10 @@ differences); P-SR2 per-sample scores by central differences of log pi; P-SR3 th
 score has zero mean under pi (enumeration of all 2^n strings); P-SR4 the Fisher identity
 E_pi[grad lp grad lp^T] = -E_pi[hess lp] with the Hessian by finite differences;
 P-SR5 the Woodbury form equals the d x d solve, for B < d and B > d; P-SR6 the Gram is
-symmetric positive semi-definite with the squared score norms on its diagonal."""
+symmetric positive semi-definite with the squared score norms on its diagonal; P-SR7 the
+push-through form from the coefficients equals the d x d solve with g = O^T c; P-SR8 the
+batch Fisher matrix's quadratic forms v^T I v against (1/B) sum_b (d/de log pi(s_b;
+theta + e v))^2 with the directional derivatives by central differences of log pi."""
 import numpy as np
 import pytest
 
@@ -112,3 +115,35 @@ def test_PSR6_gram_psd_with_score_norms_on_diagonal():
     assert np.array_equal(K, K.T) or np.allclose(K, K.T, rtol=0, atol=1e-13)
     assert np.allclose(np.diag(K), (O ** 2).sum(axis=1), rtol=1e-13)
     assert np.linalg.eigvalsh(K).min() > -1e-10 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("B", [5, 60])
+def test_PSR7_push_through_from_coefficients_equals_direct_solve(B):
+    n, h = 6, 4                                               # d = 34
+    p = _params(n, h, 61)
+    S = inputs.random_spins(B, n, 62)
+    coef = np.random.default_rng(63).standard_normal(B) / B
+    g = sr.flatten(p, estimator.logp_grad(p, S, coef))      # the batch gradient O^T c
+    for lam in (1e-3, 0.5):
+        x1 = sr.sr_direction(p, S, g, lam)
+        x2 = sr.sr_direction_coef(p, S, coef, lam)
+        assert np.allclose(x2, x1, rtol=0, atol=1e-8 * np.abs(x1).max())
+
+
+def test_PSR8_fisher_quadratic_forms_by_directional_differences():
+    n, h, B = 7, 5, 9
+    p = _params(n, h, 71)
+    S = inputs.random_spins(B, n, 72)
+    I = sr.fisher(p, S)
+    M1, M2 = made.masks(n, p["degrees"])
+    rng = np.random.default_rng(73)
+    eps = 1e-6
+    for _ in range(3):
+        v = {k: rng.standard_normal(np.shape(p[k])) for k in ("W1", "b1", "W2", "b2")}
+        v["W1"] *= M1
+        v["W2"] *= M2
+        up = {k: (p[k] + eps * v[k] if k in v else p[k]) for k in p}
+        dn = {k: (p[k] - eps * v[k] if k in v else p[k]) for k in p}
+        dd = (made.logp(up, S) - made.logp(dn, S)) / (2 * eps)   # one directional derivative per sample
+        vf = sr.flatten(p, v)
+        assert np.isclose(vf @ I @ vf, (dd ** 2).mean(), rtol=1e-7)
