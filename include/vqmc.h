@@ -48,6 +48,9 @@ extern "C" {
 
 #define VQMC_PAD 64
 
+/* Working precisions of the weights.  VQMC_F64 names the precision of the reference
+ * evaluation (the paper's equations in float64); no call of this library computes in it and
+ * every call given it returns VQMC_EDTYPE. */
 typedef enum { VQMC_F64 = 0, VQMC_F32 = 1, VQMC_BF16 = 2 } vqmc_dtype;
 
 typedef enum {
@@ -56,7 +59,7 @@ typedef enum {
   VQMC_EDTYPE = -2,     /* dtype not supported by this call                        */
   VQMC_EWORKSPACE = -3, /* workspace smaller than vqmc_workspace_bytes()           */
   VQMC_EHIP = -4,       /* a HIP launch or copy failed                             */
-  VQMC_ENONFINITE = -5  /* reserved: non-finite parameters                         */
+  VQMC_ENONFINITE = -5  /* a NaN or infinity among the parameters (vqmc_check_nonfinite) */
 } vqmc_status;
 
 /* MADE parameters in the kernels' working precision (produced by vqmc_cast).
@@ -117,7 +120,8 @@ enum {
   VQMC_WS_STEP = 3,
   VQMC_WS_BACKWARD_SAMPLED = 4,
   VQMC_WS_SR_GRAM = 5,
-  VQMC_WS_SR_JVP = 6
+  VQMC_WS_SR_JVP = 6,
+  VQMC_WS_SR_DIRECTION = 7
 };
 /* Workspace bytes needed by a call (host function, no device access). */
 size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
@@ -126,7 +130,9 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
 /* Pack dense float32 MADE weights into the master packed matrix (Sec. 2.3 MADE layer;
  * masks by the degree rule above).  W1: h x n, W2: n x h (row-major, device).
  * degrees: HOST array of h sorted 1-based degrees in [1, n-1] (validated: EINVAL if
- * unsorted or out of range).  Writes P32 (n x h float, unpadded) and c (n int32). */
+ * unsorted or out of range); it is read during the call (passed to the device as kernel
+ * arguments), so the caller may free it on return and the call does not synchronise.
+ * Writes P32 (n x h float, unpadded) and c (n int32). */
 int vqmc_pack(int32_t n, int32_t h, const float* W1, const float* W2, const int32_t* degrees,
               float* P32, int32_t* c, void* stream);
 
@@ -145,9 +151,17 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
  * re-derived): writes P and Pt from P32 (as vqmc_cast) and, when band is not NULL, the
  * sampler's tables for the model (P, Pt, b1, b2, c) (as vqmc_band; band of
  * vqmc_band_bytes(n, h, dtype) bytes, 16-byte aligned).  The logit and push tiles are written
- * by the same workgroups that cast P32, from the tile they hold on chip. */
+ * by the same workgroups that cast P32, from the tile they hold on chip.
+ * nonfinite (nullable, device int32): the same pass sets it to 1 if any value of P32, b1 or
+ * b2 is a NaN or an infinity (a diverged update); it is never cleared by the library, so
+ * the caller zeroes it once and reads it back when convenient (vqmc_check_nonfinite turns
+ * the value into a status).  Needs b1 and b2 when given. */
 int vqmc_refresh(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt, const float* b1,
-                 const float* b2, const int32_t* c, float* band, void* stream);
+                 const float* b2, const int32_t* c, float* band, int32_t* nonfinite, void* stream);
+
+/* Status of a non-finite flag written by vqmc_refresh, after the caller copied it to the host:
+ * VQMC_ENONFINITE (with a vqmc_last_error message) if flag != 0, else VQMC_OK. */
+int vqmc_check_nonfinite(int32_t flag);
 
 /* Size in bytes of the pipelined sampler's tables (the band) for n sites, h hidden units
  * and weights of type wdtype (VQMC_F32 or VQMC_BF16); 0 for invalid arguments. */
@@ -275,10 +289,39 @@ int vqmc_sr_gram_sampled(const vqmc_made* m, const int8_t* S, int64_t B, const f
  * masked layers are applied with g in place of the weights (the first without its ReLU)
  * and contracted with the score factors of each sample; g is rounded to the weight dtype
  * for the products.  v: B floats (device, overwritten).  Needs VQMC_WS_SR_JVP workspace.
- * The rest of the SR direction x = (g - O^T (lambda B I + K)^{-1} O g) / lambda is
- * vqmc_sr_gram (K) and vqmc_logprob_backward with coef = y (O^T y). */
+ * With it the SR direction for any g is x = (g - O^T (lambda B I + K)^{-1} O g) / lambda
+ * (Woodbury); for the batch gradient itself vqmc_sr_direction needs no O g. */
 int vqmc_sr_jvp(const vqmc_made* m, const int8_t* S, int64_t B, const float* gP, const float* gb1, const float* gb2,
                 float* v, void* ws, size_t ws_bytes, void* stream);
+
+/* The B x B linear system of stochastic reconfiguration in sample space (Sec. 2.1 Fisher
+ * information, Sec. 5.1 SR with a ridge):  (K + shift I) y = scale * rhs, solved in FP64 by a
+ * blocked Cholesky factorisation with forward and back substitution, all on the device.
+ * K: B x B float (device, row-major, leading dimension B), symmetric positive semi-definite;
+ * only its lower triangle is read.  rhs: B floats (device).  y: B floats (device, overwritten;
+ * NaN if K + shift I is not positive definite in FP64).  shift > 0 and finite, else EINVAL;
+ * 1 <= B <= 65536.  Workspace: vqmc_sr_solve_workspace_bytes(B) bytes (device, 8-byte aligned;
+ * it holds the FP64 factor, round_up(B, 64)^2 doubles). */
+int vqmc_sr_solve(int64_t B, const float* K, double shift, const float* rhs, double scale, float* y, void* ws,
+                  size_t ws_bytes, void* stream);
+size_t vqmc_sr_solve_workspace_bytes(int64_t B);
+
+/* The SR (natural-gradient) direction of the batch gradient (Sec. 2.1 gradient and Fisher
+ * information; Sec. 5.1 SR with ridge lambda): x solves (O^T O / B + lambda I) x = g with
+ * g = O^T coef the gradient vqmc_step returns for coefficients coef (O: per-sample scores over
+ * every unmasked parameter, as for vqmc_sr_gram).  By the push-through identity
+ * (O^T O / B + lambda I) O^T = O^T (O O^T / B + lambda I) this is
+ *     x = O^T y,   (K + lambda B I) y = B coef,   K = O O^T,
+ * computed as vqmc_sr_gram (or vqmc_sr_gram_sampled), vqmc_sr_solve and the gradient
+ * kernels with coef = y; no d-dimensional system and no division by lambda.
+ * S: B x ld(n) int8 spins; coef: B floats (device).  Zs, Rt (nullable together): vqmc_sample_fwd's
+ * byproducts for S (then nothing of the forward pass is recomputed), 16-byte aligned.
+ * xP (n x h float, packed like dP), xb1 (h), xb2 (n): outputs, overwritten.  K_out (nullable):
+ * B x B floats receiving K, else K stays in the workspace.  lambda > 0; 1 <= B <= 65536.
+ * Needs VQMC_WS_SR_DIRECTION workspace. */
+int vqmc_sr_direction(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, const float* Zs,
+                      const void* Rt, double lambda, float* xP, float* xb1, float* xb2, float* K_out, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* One optimisation step without the parameter update (Sec. 4): sample (algo 0 =
  * incremental, 1 = plain n-pass form), energy, statistics, gradient.  Writes S, logp,

@@ -25,6 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
 WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM, WS_SR_JVP = 0, 1, 2, 3, 4, 5, 6
+WS_SR_DIRECTION = 7
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
@@ -59,7 +60,8 @@ _SIGS = {
     "vqmc_cast": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "vqmc_band": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _vp]),
     "vqmc_band_bytes": (ctypes.c_size_t, [_i32, _i32, _i32]),
-    "vqmc_refresh": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vqmc_refresh": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vqmc_check_nonfinite": (ctypes.c_int, [_i32]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
     "vqmc_sample_fwd": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp, _vp,
                                        _vp]),
@@ -76,6 +78,10 @@ _SIGS = {
     "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
     "vqmc_sr_jvp": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_sr_gram_sampled": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vqmc_sr_solve": (ctypes.c_int, [_i64, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp, _sz, _vp]),
+    "vqmc_sr_solve_workspace_bytes": (_sz, [_i64]),
+    "vqmc_sr_direction": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, ctypes.c_double, _vp, _vp,
+                                         _vp, _vp, _vp, _sz, _vp]),
     "vqmc_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(HamC), _i64, _u64, _u64, _i64, _i32,
                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_csr_from_edges": (ctypes.c_int, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp]),
@@ -121,6 +127,34 @@ def _dev(t: torch.Tensor) -> torch.Tensor:
     return t
 
 
+def _need(t: torch.Tensor, name: str, dtype, shape) -> torch.Tensor:
+    """A contiguous device tensor of the given dtype with at least the given leading extents."""
+    _dev(t)
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.dim() != len(shape) or any(a < b for a, b in zip(t.shape, shape)):
+        raise ValueError(f"{name}: expected shape at least {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _need_spins(made, S: torch.Tensor, B: int) -> torch.Tensor:
+    _need(S, "S", torch.int8, (B, ld(made.n)))
+    if S.shape[1] != ld(made.n):
+        raise ValueError(f"S: rows must be ld(n) = {ld(made.n)} long, got {S.shape[1]}")
+    return S
+
+
+def _need_fwd(made, Zs: torch.Tensor, Rt: torch.Tensor, B: int):
+    """vqmc_sample_fwd's byproducts for B samples: Zs B x ld(n) float32, Rt h x ld(B) in the weight dtype."""
+    _need(Zs, "Zs", torch.float32, (B, ld(made.n)))
+    if Zs.shape[1] != ld(made.n):
+        raise ValueError(f"Zs: rows must be ld(n) = {ld(made.n)} long")
+    rdt = torch.bfloat16 if made.wdtype == BF16 else torch.float32
+    _need(Rt, "Rt", rdt, (made.h, ld(B)))
+    if Rt.shape[1] != ld(B):
+        raise ValueError(f"Rt: rows must be ld(B) = {ld(B)} long, got {Rt.shape[1]}")
+
+
 # ---------------------------------------------------------------- parameters
 class Made:
     """MADE parameters: the FP32 master packed matrix P32 (n x h), biases, the
@@ -138,6 +172,8 @@ class Made:
         self.Pt = torch.zeros((self.h, ld(self.n)), dtype=tdt, device=dev)
         nbytes = int(_lib.vqmc_band_bytes(self.n, self.h, self.wdtype)) if band else 0
         self.band = torch.zeros(nbytes // 4, dtype=torch.float32, device=dev) if band else None
+        # set by every refresh when a parameter is NaN or infinite (sticky until cleared)
+        self.nonfinite = torch.zeros(1, dtype=torch.int32, device=dev)
         self.refresh()
 
     @classmethod
@@ -161,7 +197,12 @@ class Made:
         _check("vqmc_refresh", _lib.vqmc_refresh(self.n, self.h, self.P32.data_ptr(), self.wdtype,
                                                  self.P.data_ptr(), self.Pt.data_ptr(), self.b1.data_ptr(),
                                                  self.b2.data_ptr(), self.c.data_ptr(), _ptr(self.band),
-                                                 _stream()))
+                                                 self.nonfinite.data_ptr(), _stream()))
+
+    def check_finite(self):
+        """Raise VqmcError (VQMC_ENONFINITE) if a refresh has seen a NaN or infinite parameter
+        (reads the device flag back: synchronises the stream)."""
+        _check("vqmc_check_nonfinite", _lib.vqmc_check_nonfinite(int(self.nonfinite.item())))
 
     def cstruct(self) -> MadeC:
         return MadeC(self.n, self.h, self.wdtype, self.P.data_ptr(), self.Pt.data_ptr(),
@@ -356,10 +397,11 @@ def sr_gram(made: Made, S: torch.Tensor, B: int | None = None, ws: torch.Tensor 
             K: torch.Tensor | None = None) -> torch.Tensor:
     """K = O O^T (B x B float), the sample-space Gram of the per-sample scores."""
     B = S.shape[0] if B is None else B
-    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _dev(K)
+    _need_spins(made, S, B)
+    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _need(K, "K", torch.float32, (B, B))
     ws = workspace(WS_SR_GRAM, made, B) if ws is None else ws
     m = made.cstruct()
-    _check("vqmc_sr_gram", _lib.vqmc_sr_gram(ctypes.byref(m), _dev(S).data_ptr(), B, K.data_ptr(), ws.data_ptr(),
+    _check("vqmc_sr_gram", _lib.vqmc_sr_gram(ctypes.byref(m), S.data_ptr(), B, K.data_ptr(), ws.data_ptr(),
                                               ws.numel(), _stream()))
     return K
 
@@ -368,11 +410,13 @@ def sr_gram_sampled(made: Made, S: torch.Tensor, Zs: torch.Tensor, Rt: torch.Ten
                     ws: torch.Tensor | None = None, K: torch.Tensor | None = None) -> torch.Tensor:
     """sr_gram for spins drawn by sample_fwd, from its Zs and Rt (no forward recompute)."""
     B = S.shape[0] if B is None else B
-    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _dev(K)
+    _need_spins(made, S, B)
+    _need_fwd(made, Zs, Rt, B)
+    K = torch.empty((B, B), dtype=torch.float32, device=S.device) if K is None else _need(K, "K", torch.float32, (B, B))
     ws = workspace(WS_SR_GRAM, made, B) if ws is None else ws
     m = made.cstruct()
     _check("vqmc_sr_gram_sampled", _lib.vqmc_sr_gram_sampled(
-        ctypes.byref(m), _dev(S).data_ptr(), B, _dev(Zs).data_ptr(), _dev(Rt).data_ptr(), K.data_ptr(),
+        ctypes.byref(m), S.data_ptr(), B, Zs.data_ptr(), Rt.data_ptr(), K.data_ptr(),
         ws.data_ptr(), ws.numel(), _stream()))
     return K
 
@@ -381,13 +425,59 @@ def sr_jvp(made: Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Tensor, gb2
            B: int | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
     """v = O g (B floats): the score of every sample contracted with the direction (gP, gb1, gb2)."""
     B = S.shape[0] if B is None else B
+    _need_spins(made, S, B)
+    _need(gP, "gP", torch.float32, (made.n, made.h))
+    if tuple(gP.shape) != (made.n, made.h):
+        raise ValueError("gP must be n x h (packed like P32)")
+    _need(gb1, "gb1", torch.float32, (made.h,))
+    _need(gb2, "gb2", torch.float32, (made.n,))
     v = torch.empty(B, dtype=torch.float32, device=S.device)
     ws = workspace(WS_SR_JVP, made, B) if ws is None else ws
     m = made.cstruct()
-    _check("vqmc_sr_jvp", _lib.vqmc_sr_jvp(ctypes.byref(m), _dev(S).data_ptr(), B, _dev(gP).data_ptr(),
-                                            _dev(gb1).data_ptr(), _dev(gb2).data_ptr(), v.data_ptr(), ws.data_ptr(),
-                                            ws.numel(), _stream()))
+    _check("vqmc_sr_jvp", _lib.vqmc_sr_jvp(ctypes.byref(m), S.data_ptr(), B, gP.data_ptr(), gb1.data_ptr(),
+                                            gb2.data_ptr(), v.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
     return v
+
+
+def sr_solve(K: torch.Tensor, shift: float, rhs: torch.Tensor, scale: float = 1.0,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+    """y = (K + shift I)^{-1} (scale rhs) by the library's FP64 Cholesky (K: B x B float32, symmetric PSD)."""
+    B = rhs.shape[0]
+    _need(K, "K", torch.float32, (B, B))
+    if tuple(K.shape) != (B, B):
+        raise ValueError("K must be B x B")
+    _need(rhs, "rhs", torch.float32, (B,))
+    y = torch.empty(B, dtype=torch.float32, device=K.device)
+    nb = int(_lib.vqmc_sr_solve_workspace_bytes(B))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=K.device) if ws is None else ws
+    _check("vqmc_sr_solve", _lib.vqmc_sr_solve(B, K.data_ptr(), float(shift), rhs.data_ptr(), float(scale),
+                                                y.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return y
+
+
+def sr_direction(made: Made, S: torch.Tensor, coef: torch.Tensor, lam: float, B: int | None = None,
+                 Zs: torch.Tensor | None = None, Rt: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                 want_K: bool = False):
+    """SR direction of the batch gradient sum_b coef_b grad log pi(s_b): x = O^T y with
+    (K + lam B I) y = B coef.  Returns (xP n x h, xb1, xb2) and, with want_K, K."""
+    B = S.shape[0] if B is None else B
+    _need_spins(made, S, B)
+    _need(coef, "coef", torch.float32, (B,))
+    if (Zs is None) != (Rt is None):
+        raise ValueError("give both Zs and Rt, or neither")
+    if Zs is not None:
+        _need_fwd(made, Zs, Rt, B)
+    dev = S.device
+    xP = torch.empty((made.n, made.h), dtype=torch.float32, device=dev)
+    xb1 = torch.empty(made.h, dtype=torch.float32, device=dev)
+    xb2 = torch.empty(made.n, dtype=torch.float32, device=dev)
+    K = torch.empty((B, B), dtype=torch.float32, device=dev) if want_K else None
+    ws = workspace(WS_SR_DIRECTION, made, B) if ws is None else ws
+    m = made.cstruct()
+    _check("vqmc_sr_direction", _lib.vqmc_sr_direction(
+        ctypes.byref(m), S.data_ptr(), B, coef.data_ptr(), _ptr(Zs), _ptr(Rt), float(lam), xP.data_ptr(),
+        xb1.data_ptr(), xb2.data_ptr(), _ptr(K), ws.data_ptr(), ws.numel(), _stream()))
+    return (xP, xb1, xb2, K) if want_K else (xP, xb1, xb2)
 
 
 @dataclass

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -74,6 +75,22 @@ hipError_t step_aux(StepAux** out) {
   return hipSuccess;
 }
 
+// SR direction workspace: [the Gram's or the backward's scratch, whichever is larger]
+// [K: B x B floats][the solve's FP64 matrix and vectors][y: B floats]
+struct SrDirLayout {
+  size_t K, solve, y, total;
+};
+SrDirLayout sr_dir_layout(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  const size_t bws = (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256) + mask_w2t_bytes(n, h);
+  const size_t r0 = (size_t)round_up((int64_t)std::max(sr_gram_ws_bytes(n, h, B, wdtype), bws), 256);
+  SrDirLayout L;
+  L.K = r0;
+  L.solve = L.K + (size_t)round_up(B * B * 4, 256);
+  L.y = L.solve + (size_t)round_up((int64_t)sr_solve_ws_bytes(B), 256);
+  L.total = L.y + (size_t)round_up(B * 4, 256);
+  return L;
+}
+
 int check_made(const vqmc_made* m, bool need_pt) {
   if (!m) return fail(VQMC_EINVAL, "made is NULL");
   if (m->n < 2 || m->h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1 (n=%d h=%d)", m->n, m->h);
@@ -114,6 +131,7 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_SR_JVP: return sr_jvp_ws_bytes(n, h, B, wdtype);
     case VQMC_WS_BACKWARD_SAMPLED:
       return (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256) + mask_w2t_bytes(n, h);
+    case VQMC_WS_SR_DIRECTION: return sr_dir_layout(n, h, B, wdtype).total;
     default: return 0;
   }
 }
@@ -127,19 +145,11 @@ int vqmc_pack(int32_t n, int32_t h, const float* W1, const float* W2, const int3
       return fail(VQMC_EINVAL, "degree[%d] = %d outside [1, n-1]", k, degrees[k]);
     if (k && degrees[k] < degrees[k - 1]) return fail(VQMC_EINVAL, "degrees not sorted at %d", k);
   }
-  // c[d] = #{k : m(k) <= d} for 0-based site d (m is 1-based)
-  std::vector<int32_t> ch(n);
-  int k = 0;
-  for (int d = 0; d < n; ++d) {
-    while (k < h && degrees[k] <= d) ++k;
-    ch[d] = k;
-  }
+  // c[d] = #{k : m(k) <= d} for 0-based site d (m is 1-based), counted on the device from
+  // the degrees passed by value, so the call stays asynchronous
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(c, ch.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_status(e, "vqmc_pack copy");
-  // the host vector must outlive the copy
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_status(e, "vqmc_pack sync");
+  hipError_t e = launch_degree_counts(n, h, degrees, c, st);
+  if (e != hipSuccess) return hip_status(e, "vqmc_pack degrees");
   return hip_status(launch_pack(n, h, W1, W2, c, P32, st), "vqmc_pack");
 }
 
@@ -158,17 +168,23 @@ int vqmc_cast(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, vo
 }
 
 int vqmc_refresh(int32_t n, int32_t h, const float* P32, int32_t dtype, void* P, void* Pt, const float* b1,
-                 const float* b2, const int32_t* c, float* band, void* stream) {
+                 const float* b2, const int32_t* c, float* band, int32_t* nonfinite, void* stream) {
   if (n < 2 || h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1");
   if (dtype != VQMC_F32 && dtype != VQMC_BF16) return fail(VQMC_EDTYPE, "cast dtype %d", dtype);
   if (!P32 || !P || !Pt) return fail(VQMC_EINVAL, "null pointer");
   if (band && (!b1 || !b2 || !c)) return fail(VQMC_EINVAL, "band needs b1, b2 and c");
+  if (nonfinite && (!b1 || !b2)) return fail(VQMC_EINVAL, "the non-finite check needs b1 and b2");
   if (band && ((uintptr_t)band & 15)) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_cast(n, h, P32, dtype, P, Pt, st, b2, c, band);
+  hipError_t e = launch_cast(n, h, P32, dtype, P, Pt, st, b2, c, band, b1, nonfinite);
   if (e != hipSuccess || !band) return hip_status(e, "vqmc_refresh");
   const vqmc_made m{n, h, dtype, P, Pt, b1, b2, c, band};
   return hip_status(launch_band(m, band, st, false), "vqmc_refresh");
+}
+
+int vqmc_check_nonfinite(int32_t flag) {
+  if (flag) return fail(VQMC_ENONFINITE, "the parameters hold a NaN or an infinity (flag set by vqmc_refresh)");
+  return VQMC_OK;
 }
 
 size_t vqmc_band_bytes(int32_t n, int32_t h, int32_t wdtype) {
@@ -333,6 +349,48 @@ int vqmc_sr_jvp(const vqmc_made* m, const int8_t* S, int64_t B, const float* gP,
   const size_t need = sr_jvp_ws_bytes(m->n, m->h, B, m->wdtype);
   if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   return hip_status(launch_sr_jvp(*m, S, B, gP, gb1, gb2, v, ws, (hipStream_t)stream), "vqmc_sr_jvp");
+}
+
+size_t vqmc_sr_solve_workspace_bytes(int64_t B) { return B < 1 ? 0 : sr_solve_ws_bytes(B); }
+
+int vqmc_sr_solve(int64_t B, const float* K, double shift, const float* rhs, double scale, float* y, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (B < 1 || B > 65536 || !K || !rhs || !y || !ws) return fail(VQMC_EINVAL, "bad sr_solve arguments (1 <= B <= 65536)");
+  if (!(shift > 0.0) || !std::isfinite(shift)) return fail(VQMC_EINVAL, "shift must be finite and > 0 (got %g)", shift);
+  if (!std::isfinite(scale)) return fail(VQMC_EINVAL, "scale must be finite");
+  const size_t need = sr_solve_ws_bytes(B);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_sr_solve(K, B, shift, rhs, scale, y, ws, (hipStream_t)stream), "vqmc_sr_solve");
+}
+
+int vqmc_sr_direction(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, const float* Zs,
+                      const void* Rt, double lambda, float* xP, float* xb1, float* xb2, float* K_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || B > 65536 || !S || !coef || !xP || !xb1 || !xb2 || !ws)
+    return fail(VQMC_EINVAL, "bad sr_direction arguments (1 <= B <= 65536)");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(VQMC_EINVAL, "lambda must be finite and > 0");
+  if ((Zs == nullptr) != (Rt == nullptr)) return fail(VQMC_EINVAL, "give both Zs and Rt, or neither");
+  if (Zs && (((uintptr_t)Zs | (uintptr_t)Rt) & 15)) return fail(VQMC_EINVAL, "Zs and Rt must be 16-byte aligned");
+  const SrDirLayout L = sr_dir_layout(m->n, m->h, B, m->wdtype);
+  if (ws_bytes < L.total) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* w = (uint8_t*)ws;
+  float* K = K_out ? K_out : (float*)(w + L.K);
+  float* y = (float*)(w + L.y);
+  hipError_t e = Zs ? launch_sr_gram_sampled(*m, S, B, Zs, Rt, K, ws, st) : launch_sr_gram(*m, S, B, K, ws, st);
+  if (e != hipSuccess) return hip_status(e, "vqmc_sr_direction gram");
+  // (K + lambda B I) y = B coef: the push-through form of (O^T O / B + lambda I) x = O^T coef
+  if ((e = launch_sr_solve(K, B, lambda * (double)B, coef, (double)B, y, w + L.solve, st)) != hipSuccess)
+    return hip_status(e, "vqmc_sr_direction solve");
+  if (Zs) {
+    void* Pm = w + round_up((int64_t)logprob_ws_bytes(m->n, m->h, B, m->wdtype, true), 256);
+    e = launch_backward_sampled(*m, S, B, y, Zs, Rt, xP, xb1, xb2, ws, Pm, st);
+  } else {
+    e = launch_backward(*m, S, B, y, xP, xb1, xb2, ws, st);
+  }
+  return hip_status(e, "vqmc_sr_direction scores");
 }
 
 int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t seed, uint64_t step,

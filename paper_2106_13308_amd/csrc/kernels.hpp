@@ -8,12 +8,21 @@
 namespace vqmc {
 
 // pack.hip
+// degrees travel to the device as kernel arguments, kDegreeChunk per launch
+constexpr int kDegreeChunk = 960;
+struct DegreeChunk {
+  int32_t count;
+  int32_t deg[kDegreeChunk];
+};
+hipError_t launch_degree_counts(int n, int h, const int32_t* degrees, int32_t* c, hipStream_t st);
 hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int32_t* c, float* P32,
                        hipStream_t st);
 hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float* W1, float* W2,
                          hipStream_t st);
+// nonfinite (nullable): set to 1 if any of P32, b1, b2 is a NaN or an infinity (never cleared)
 hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
-                       const float* b2 = nullptr, const int32_t* c = nullptr, void* tables = nullptr);
+                       const float* b2 = nullptr, const int32_t* c = nullptr, void* tables = nullptr,
+                       const float* b1 = nullptr, int32_t* nonfinite = nullptr);
 
 // energy.hip
 hipError_t launch_energy(const vqmc_hamiltonian& H, const int8_t* S, int64_t B, void* E,
@@ -68,6 +77,10 @@ size_t sr_gram_parts_bytes(int64_t B, int h);  // partial sums of the sweeps' wo
 hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, const void* Dt, const void* St,
                                  int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* parts, float* K,
                                  hipStream_t st);
+// chol.hip: (K + shift I) y = scale * rhs in FP64 (blocked Cholesky, forward and back substitution)
+size_t sr_solve_ws_bytes(int64_t B);
+hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float* rhs, double scale, float* y,
+                           void* ws, hipStream_t st);
 // gemm2.hip: BF16 backward products on the direct-to-LDS engine; Pm: h x ld(n) bf16 scratch
 size_t mask_w2t_bytes(int n, int h);
 // db1_part (np1 rows of ld(h)) and db2_part (np2 rows of ld(n)) are summed into db1 and db2

@@ -79,10 +79,12 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
                                                     T* __restrict__ P, T* __restrict__ Pt,
                                                     const float* __restrict__ b2, const int32_t* __restrict__ c,
                                                     uint8_t* __restrict__ ztab, uint8_t* __restrict__ utab,
-                                                    bf16_t* __restrict__ Pm, int nzt, int nut) {
+                                                    bf16_t* __restrict__ Pm, int nzt, int nut,
+                                                    const float* __restrict__ b1, int32_t* __restrict__ nonfinite) {
   __shared__ T tile[CT][CT + 2];  // odd row stride in dwords for either T: column reads spread
   const int d0 = blockIdx.y * CT, k0 = blockIdx.x * CT;
   const int t = threadIdx.x;
+  bool bad = false;  // a NaN or infinity among the parameters this workgroup reads
   {
     const int tx = t & 15, ty = t >> 4;  // columns 4 tx .. +3, rows ty + 16 r
     const int k = k0 + 4 * tx;
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
       T o[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        bad |= !__builtin_isfinite(v[e]);
         o[e] = convert<T>(v[e]);
         tile[ty + 16 * r][4 * tx + e] = o[e];
       }
@@ -111,6 +114,11 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
         else *(float4*)dst = *(const float4*)o;
       }
     }
+  }
+  if (nonfinite) {  // biases: b2 of the block's sites (first column of workgroups), b1 of its units (first row)
+    if (t < CT && k0 == 0 && d0 + t < n) bad |= !__builtin_isfinite(b2[d0 + t]);
+    if (t < CT && d0 == 0 && k0 + t < h) bad |= !__builtin_isfinite(b1[k0 + t]);
+    if (__ballot(bad) && (t & 63) == 0) atomicOr(nonfinite, 1);
   }
   __syncthreads();
   {
@@ -221,6 +229,35 @@ __global__ __launch_bounds__(256) void cast_kernel(int n, int h, int64_t ldh, in
   }
 }
 
+// c[d] = #{k : m(k) <= d} (0-based site d, 1-based sorted degrees m), from the degrees passed
+// by value in chunks: each launch adds its chunk's count (a bisection of the sorted chunk), so
+// no host buffer has to outlive an asynchronous copy.
+__global__ void degree_count_kernel(int n, DegreeChunk ch, int first, int32_t* __restrict__ c) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n) return;
+  int lo = 0, hi = ch.count;  // first index whose degree exceeds d
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ch.deg[mid] <= d)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  c[d] = first ? lo : c[d] + lo;
+}
+
+hipError_t launch_degree_counts(int n, int h, const int32_t* degrees, int32_t* c, hipStream_t st) {
+  for (int k0 = 0; k0 < h; k0 += kDegreeChunk) {
+    DegreeChunk ch;
+    ch.count = h - k0 < kDegreeChunk ? h - k0 : kDegreeChunk;
+    for (int i = 0; i < ch.count; ++i) ch.deg[i] = degrees[k0 + i];
+    degree_count_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, ch, k0 == 0, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_pack(int n, int h, const float* W1, const float* W2, const int32_t* c, float* P32,
                        hipStream_t st) {
   dim3 grid((h + 31) / 32, (n + 31) / 32);
@@ -236,7 +273,7 @@ hipError_t launch_unpack(int n, int h, const float* P32, const int32_t* c, float
 }
 
 hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void* Pt, hipStream_t st,
-                       const float* b2, const int32_t* c, void* tables) {
+                       const float* b2, const int32_t* c, void* tables, const float* b1, int32_t* nonfinite) {
   const int64_t ldh = round_up(h, kPad), ldn = round_up(n, kPad);
   // grid covers the padded extents so that padding is written as zero
   dim3 grid((unsigned)(ldh / CT), (unsigned)(ldn / CT));
@@ -253,17 +290,17 @@ hipError_t launch_cast(int n, int h, const float* P32, int dtype, void* P, void*
   if (dtype == VQMC_BF16) {
     if (tables)
       cast_kernel<bf16_t, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, c, zt, ut, pm,
-                                                       nzt, nut);
+                                                       nzt, nut, b1, nonfinite);
     else
       cast_kernel<bf16_t, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (bf16_t*)P, (bf16_t*)Pt, b2, c, zt, ut, pm,
-                                                        0, 0);
+                                                        0, 0, b1, nonfinite);
   } else {
     if (tables)
       cast_kernel<float, true><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, c, zt, ut, pm,
-                                                      nzt, nut);
+                                                      nzt, nut, b1, nonfinite);
     else
       cast_kernel<float, false><<<grid, 256, 0, st>>>(n, h, ldh, ldn, P32, (float*)P, (float*)Pt, b2, c, zt, ut, pm,
-                                                       0, 0);
+                                                       0, 0, b1, nonfinite);
   }
   return hipGetLastError();
 }

@@ -68,6 +68,7 @@ class Trainer:
         self.t += 1
         if not log:
             return None
+        self.made.check_finite()
         st = B.stats_to_dict(self.bufs.stats)
         if self.best_E is None or st["min"] < self.best_E:
             self.best_E = st["min"]
@@ -104,6 +105,7 @@ def train(trainer: Trainer, steps: int, jsonl: str | None = None, target_cut=Non
         trainer.step(log=False)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
+        trainer.made.check_finite()
         if (i + 1) % every == 0 or i + 1 == steps or target_cut is not None:
             st = B.stats_to_dict(trainer.bufs.stats)
             if trainer.best_E is None or st["min"] < trainer.best_E:
@@ -124,44 +126,49 @@ def train(trainer: Trainer, steps: int, jsonl: str | None = None, target_cut=Non
     return rec, hit
 
 
-def sr_direction(made: B.Made, S: torch.Tensor, gP: torch.Tensor, gb1: torch.Tensor, gb2: torch.Tensor,
-                 lam: float, n_samples: int | None = None):
-    """Stochastic-reconfiguration (natural-gradient) direction x = (I_hat + lam I)^{-1} g, with
-    I_hat = O^T O / B the batch Fisher matrix of the per-sample scores (Sec. 2.1) and the ridge
-    lam of Sec. 5.1, through the sample-space Gram (Woodbury identity):
-
-        x = (g - O^T (lam B I + K)^{-1} O g) / lam,   K = O O^T.
-
-    K, O g and O^T y are library calls (vqmc_sr_gram, vqmc_sr_jvp, vqmc_logprob_backward with
-    coef = y); the B x B solve is the optimiser's own step, in float64 torch like the Adam
-    update.  g and x are packed like the gradient (n x h, h, n)."""
-    nb = S.shape[0] if n_samples is None else n_samples
-    K = B.sr_gram(made, S, nb)
-    v = B.sr_jvp(made, S, gP, gb1, gb2, nb)
-    # lam B I + K is symmetric positive definite (K is a Gram matrix): Cholesky, in float64
-    A = K.double() + lam * nb * torch.eye(nb, dtype=torch.float64, device=K.device)
-    Lc = torch.linalg.cholesky(A)
-    y = torch.cholesky_solve(v.double().unsqueeze(1), Lc).squeeze(1).float().contiguous()
-    dP, db1, db2 = B.logprob_backward(made, S, y, nb)
-    return (gP - dP) / lam, (gb1 - db1) / lam, (gb2 - db2) / lam
+def sr_direction(made: B.Made, S: torch.Tensor, coef: torch.Tensor, lam: float, n_samples: int | None = None,
+                 Zs: torch.Tensor | None = None, Rt: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Stochastic-reconfiguration (natural-gradient) direction of the batch gradient
+    g = sum_b coef_b grad log pi(s_b): x = (I_hat + lam I)^{-1} g with I_hat = O^T O / B the batch
+    Fisher matrix of the per-sample scores (Sec. 2.1) and the ridge lam of Sec. 5.1.  One library
+    call (vqmc_sr_direction): the Gram K = O O^T, the FP64 Cholesky solve (K + lam B I) y = B coef
+    and x = O^T y, all on the device.  Returns x packed like the gradient (n x h, h, n)."""
+    return B.sr_direction(made, S, coef, lam, B=n_samples, Zs=Zs, Rt=Rt, ws=ws)
 
 
 class SRTrainer(Trainer):
     """VQMC with stochastic reconfiguration (Sec. 2.1 natural gradient; Sec. 5.1: SGD on the SR
-    direction, learning rate 0.1, ridge lambda = 0.001).  Each step is ``vqmc_step`` (samples,
-    energies, the gradient g) followed by ``sr_direction`` on the same samples and the update
-    theta -= lr x on the FP32 master parameters, then a refresh of the working copies."""
+    direction, learning rate 0.1, ridge lambda = 0.001).  Each step samples with the forward
+    byproducts (vqmc_sample_fwd), computes the energies and the coefficients c_b, takes the SR
+    direction of the batch gradient from those (vqmc_sr_direction; the gradient itself is never
+    formed) and applies theta -= lr x to the FP32 master parameters, then refreshes the working
+    copies."""
 
     def __init__(self, made: B.Made, H: B.Hamiltonian, batch: int, seed: int = 2, lr: float = 0.1,
                  lam: float = 1e-3, algo: int = 0):
         super().__init__(made, H, batch, seed=seed, lr=lr, algo=algo)
         self.lr, self.lam = lr, lam
+        dev = made.P.device
+        self.fused = made.band is not None and algo == 0
+        if self.fused:
+            self.Zs = torch.empty((batch, B.ld(made.n)), dtype=torch.float32, device=dev)
+            rdt = torch.bfloat16 if made.wdtype == B.BF16 else torch.float32
+            self.Rt = torch.empty((made.h, B.ld(batch)), dtype=rdt, device=dev)
+        self.sr_ws = B.workspace(B.WS_SR_DIRECTION, made, batch)
 
     def step(self, log: bool = True) -> dict | None:
         with torch.no_grad():
-            B.step(self.made, self.H, self.batch, self.seed, self.t, self.bufs, algo=self.algo)
-            xP, xb1, xb2 = sr_direction(self.made, self.bufs.S, self.bufs.dP, self.bufs.db1, self.bufs.db2,
-                                        self.lam, self.batch)
+            bufs = self.bufs
+            if self.fused:
+                B.sample_fwd(self.made, self.batch, self.seed, self.t, S=bufs.S, logp=bufs.logp, Zs=self.Zs,
+                             Rt=self.Rt)
+                bufs.E = B.energy(self.H, bufs.S, self.batch)
+                bufs.stats, bufs.coef = B.batch_stats(bufs.E)
+                xP, xb1, xb2 = sr_direction(self.made, bufs.S, bufs.coef, self.lam, self.batch, Zs=self.Zs,
+                                            Rt=self.Rt, ws=self.sr_ws)
+            else:
+                B.step(self.made, self.H, self.batch, self.seed, self.t, bufs, algo=self.algo)
+                xP, xb1, xb2 = sr_direction(self.made, bufs.S, bufs.coef, self.lam, self.batch, ws=self.sr_ws)
             self.made.P32.sub_(self.lr * xP)
             self.made.b1.sub_(self.lr * xb1)
             self.made.b2.sub_(self.lr * xb2)
@@ -169,6 +176,7 @@ class SRTrainer(Trainer):
         self.t += 1
         if not log:
             return None
+        self.made.check_finite()
         st = B.stats_to_dict(self.bufs.stats)
         if self.best_E is None or st["min"] < self.best_E:
             self.best_E = st["min"]

@@ -120,6 +120,25 @@ def test_validation_rejects_before_launch(B):
     assert b"not sorted" in lib.vqmc_last_error()
     deg = np.array([0, 1, 3], np.int32)   # out of range
     assert lib.vqmc_pack(8, 3, fake, fake, deg.ctypes.data_as(ctypes.c_void_p), fake, fake, None) == B.EINVAL
+    # non-finite guard: the flag value turns into a status on the host
+    assert lib.vqmc_check_nonfinite(0) == B.OK
+    assert lib.vqmc_check_nonfinite(1) == B.ENONFINITE and b"NaN" in lib.vqmc_last_error()
+    assert lib.vqmc_refresh(8, 4, fake, B.F32, fake, fake, None, None, fake, None, fake, None) == B.EINVAL
+    assert lib.vqmc_refresh(8, 4, fake, B.F64, fake, fake, fake, fake, fake, None, None, None) == B.EDTYPE
+    # SR solve and direction
+    assert lib.vqmc_sr_solve(8, fake, 0.0, fake, 1.0, fake, fake, 1 << 30, None) == B.EINVAL      # shift <= 0
+    assert lib.vqmc_sr_solve(8, fake, float("nan"), fake, 1.0, fake, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_sr_solve(0, fake, 1.0, fake, 1.0, fake, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_sr_solve(8, fake, 1.0, fake, 1.0, fake, fake, 16, None) == B.EWORKSPACE
+    assert lib.vqmc_sr_solve_workspace_bytes(65) == 128 * 128 * 8 + 2 * 1024
+    assert lib.vqmc_sr_direction(ctypes.byref(ok), fake, 8, fake, fake, None, 1e-3, fake, fake, fake, None, fake,
+                                 1 << 30, None) == B.EINVAL    # Zs without Rt
+    assert lib.vqmc_sr_direction(ctypes.byref(ok), fake, 8, fake, None, None, 0.0, fake, fake, fake, None, fake,
+                                 1 << 30, None) == B.EINVAL    # lambda
+    assert lib.vqmc_sr_direction(ctypes.byref(ok), fake, 8, fake, None, None, 1e-3, fake, fake, fake, None, fake,
+                                 16, None) == B.EWORKSPACE
+    assert lib.vqmc_workspace_bytes(B.WS_SR_DIRECTION, 8, 4, 8, B.F32) > lib.vqmc_workspace_bytes(B.WS_SR_GRAM, 8, 4,
+                                                                                                   8, B.F32)
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):
