@@ -23,6 +23,8 @@ estimator  Batch statistics, score-function gradient (Sec. 2.1, gradient populat
            analytic gradient of log pi through MADE, central finite differences.
 sr         Per-sample scores, Fisher matrix, sample-space Gram and the SR direction
            (Sec. 2.1 Fisher information with the ridge of Sec. 5.1), direct and Woodbury.
+tim        Transverse-field Ising local energy with its off-diagonal part (eq. (hamiltonian),
+           eq. (e:tim), Sec. 2.1 local energy with psi = sqrt(pi)) and H as a dense matrix.
 exact      Brute-force enumeration of all 2^n strings (normalisation, exact objective and
            gradient, Max-Cut optimum) for small n.
 
@@ -40,6 +42,8 @@ R7  variance is the population form sum (E - mean)^2 / B.
 R8  s_d = +1 iff u < p_d with u the 24-bit uniform of :mod:`oracle.philox`.
 R9  log sigma(t) = min(t, 0) - log1p(exp(-|t|)).
 R10 ReLU'(0) = 0.
+R20 the diagonal of the TIM Hamiltonian sums its couplings over i < j as eq. (hamiltonian)
+    does (the i = j terms of eq. (e:tim) would only add a constant).
 R19 the Fisher matrix is estimated uncentred, as printed: O^T O / B over the per-sample
     scores; SR solves (O^T O / B + lambda I) x = g.
 

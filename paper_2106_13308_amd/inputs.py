@@ -171,6 +171,21 @@ def sk_couplings(n: int, seed: int) -> np.ndarray:
     return J
 
 
+def tim_couplings(n: int, seed: int) -> dict:
+    """Transverse-field Ising instance (Sec. 5.1): alpha_i ~ U(0, 1), beta_i ~ U(-1, 1) and
+    beta_ij ~ U(-1, 1) for i < j, drawn once; beta_ij stored dense, symmetric, zero diagonal
+    (float32)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    alpha = rng.uniform(0.0, 1.0, size=n).astype(np.float32)
+    beta = rng.uniform(-1.0, 1.0, size=n).astype(np.float32)
+    Bm = np.zeros((n, n), dtype=np.float32)
+    iu, ju = np.triu_indices(n, 1)
+    vals = rng.uniform(-1.0, 1.0, size=iu.shape[0]).astype(np.float32)
+    Bm[iu, ju] = vals
+    Bm[ju, iu] = vals
+    return {"alpha": alpha, "beta": beta, "beta_ij": Bm}
+
+
 def random_spins(B: int, n: int, seed: int) -> np.ndarray:
     """B x n int8 spins, uniform on {-1, +1}."""
     rng = np.random.default_rng(np.random.PCG64(seed))
@@ -204,6 +219,14 @@ WORKLOADS = {
                                 "Max-Cut n=10000, random 10-regular graph, unit weights; "
                                 "MADE h=2000; B=2048"),
 }
+# transverse-field Ising model (Sec. 5.1 instance recipe; MADE h = 5 (ln n)^2 as in Sec. 5.1;
+# the samples per GPU of the paper's runs are 2^9 at n = 1000 and 4 at n = 10^4, Table 7)
+WORKLOADS["tim20"] = Workload("tim20", 20, 45, 1024, "tim", "dense", "f32",
+                              "TIM n=20, alpha ~ U(0,1), beta_i, beta_ij ~ U(-1,1); MADE h=45; B=1024")
+WORKLOADS["tim1k"] = Workload("tim1k", 1000, 239, 512, "tim", "dense", "bf16",
+                              "TIM n=1000; MADE h=5(ln n)^2=239 BF16; B=512")
+WORKLOADS["tim10k"] = Workload("tim10k", 10000, 424, 256, "tim", "dense", "bf16",
+                               "TIM n=10000; MADE h=5(ln n)^2=424 BF16; B=256")
 for _n in PAPER_MAXCUT_SIZES:
     _h = paper_latent_size(_n)
     WORKLOADS[f"paper_maxcut{_n}"] = Workload(
@@ -227,7 +250,7 @@ def make_instance(w: Workload, graph_seed: int = 0, init_seed: int = 1) -> dict:
         edges = paper_maxcut_graph(w.n, graph_seed)
     elif w.graph.startswith("er"):
         edges = erdos_renyi_graph(w.n, float(w.graph[2:]), graph_seed)
-    elif w.graph == "sk":
+    elif w.graph in ("sk", "tim"):
         edges = None
     else:
         raise ValueError(w.graph)
@@ -237,6 +260,8 @@ def make_instance(w: Workload, graph_seed: int = 0, init_seed: int = 1) -> dict:
             out["weights"] = unit_weights(len(edges))
         else:
             out["weights"] = integer_weights(len(edges), 1, 5, graph_seed + 1000)
+    elif w.graph == "tim":
+        out.update(tim_couplings(w.n, graph_seed))
     else:
         out["J"] = sk_couplings(w.n, graph_seed)
     out.update(made_init(w.n, w.h, init_seed))
