@@ -254,6 +254,20 @@ int vqmc_batch_stats(const void* E, int32_t e_is_int, int64_t B, vqmc_stats* sta
 int vqmc_logprob(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, float* Z, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* vqmc_logprob without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * kernels, arguments and results as vqmc_logprob; the call allocates nothing.  Its scratch is
+ * a fixed array of VQMC_NOALLOC_SCRATCH_BYTES in the library's own device memory: one copy per
+ * GPU the library runs on, held until the process ends.  Returns VQMC_EWORKSPACE (enqueueing
+ * nothing) when vqmc_workspace_bytes(VQMC_WS_LOGPROB, n, h, B, wdtype) exceeds that size
+ * (n = 10^4, h = 10^3, B = 2048 needs about 5 MiB, n = h = 2000, B = 8192 about 33 MiB).
+ * Every call on one GPU uses the same array and leaves its contents behind (each call
+ * overwrites all it reads, so nothing carries over): calls that may overlap on one GPU (on
+ * unordered streams, or from several host threads) race, and the caller must order them.
+ * The first call on each device looks up the array's address on that device. */
+#define VQMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int vqmc_logprob_noalloc(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, float* Z, void* stream);
+
 /* Gradient of F = sum_b coef_b log pi(s_b) (the surrogate whose gradient is the
  * score-function estimator of Sec. 2.1 when coef = c).  Recomputes the forward pass
  * (nothing is kept from vqmc_logprob).  dP: n x h float (packed like P32), db1: h,

@@ -26,6 +26,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
 WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM, WS_SR_JVP = 0, 1, 2, 3, 4, 5, 6
 WS_SR_DIRECTION = 7
+NOALLOC_SCRATCH_BYTES = 64 << 20   # VQMC_NOALLOC_SCRATCH_BYTES
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
 
@@ -73,6 +74,7 @@ _SIGS = {
     "vqmc_energy_workspace_bytes": (_sz, [ctypes.POINTER(HamC), _i64]),
     "vqmc_batch_stats": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp]),
     "vqmc_logprob": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "vqmc_logprob_noalloc": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp]),
     "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                              _sz, _vp]),
     "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -376,6 +378,28 @@ def logprob(made: Made, S: torch.Tensor, B: int | None = None, want_z: bool = Fa
     _check("vqmc_logprob", _lib.vqmc_logprob(ctypes.byref(m), _dev(S).data_ptr(), B, logp.data_ptr(),
                                              _ptr(Z), ws.data_ptr(), ws.numel(), _stream()))
     return (logp, Z) if want_z else logp
+
+
+def logprob_noalloc(made: Made, S: torch.Tensor, B: int | None = None, want_z: bool = False,
+                    logp: torch.Tensor | None = None, Z: torch.Tensor | None = None):
+    """vqmc_logprob_noalloc: log pi(S) with the library's fixed scratch instead of a workspace.
+    logp (B floats) and Z (B x ld(n) floats) may be passed in, so that the call allocates
+    nothing at all."""
+    B = S.shape[0] if B is None else B
+    dev = S.device
+    if logp is None:
+        logp = torch.empty(B, dtype=torch.float32, device=dev)
+    else:
+        logp = _need(logp, "logp", torch.float32, (B,))
+    if want_z and Z is None:
+        Z = torch.empty((B, ld(made.n)), dtype=torch.float32, device=dev)
+    elif Z is not None:
+        Z = _need(Z, "Z", torch.float32, (B, ld(made.n)))
+    _need_spins(made, S, B)
+    m = made.cstruct()
+    _check("vqmc_logprob_noalloc", _lib.vqmc_logprob_noalloc(ctypes.byref(m), _dev(S).data_ptr(), B,
+                                                             logp.data_ptr(), _ptr(Z), _stream()))
+    return (logp, Z) if Z is not None else logp
 
 
 def logprob_backward(made: Made, S: torch.Tensor, coef: torch.Tensor, B: int | None = None,

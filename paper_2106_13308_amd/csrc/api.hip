@@ -91,6 +91,32 @@ SrDirLayout sr_dir_layout(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
   return L;
 }
 
+// Scratch of vqmc_logprob_noalloc: a fixed array in the library's device memory (one copy
+// per GPU, which holds it until the process ends).  In host code the name `scratch` is only
+// a host-side stand-in; its device address on each GPU comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is ever passed on.
+static_assert(VQMC_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size must be a multiple of 256 bytes");
+static __device__ __align__(256) uint8_t scratch[VQMC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 int check_made(const vqmc_made* m, bool need_pt) {
   if (!m) return fail(VQMC_EINVAL, "made is NULL");
   if (m->n < 2 || m->h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1 (n=%d h=%d)", m->n, m->h);
@@ -306,6 +332,23 @@ int vqmc_logprob(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, fl
   const size_t need = logprob_ws_bytes(m->n, m->h, B, m->wdtype, false);
   if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   return hip_status(launch_logprob(*m, S, B, logp, Z, ws, (hipStream_t)stream), "vqmc_logprob");
+}
+
+int vqmc_logprob_noalloc(const vqmc_made* m, const int8_t* S, int64_t B, float* logp, float* Z, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !logp) return fail(VQMC_EINVAL, "bad logprob arguments");
+  // the size check comes before anything touches the device
+  const size_t need = logprob_ws_bytes(m->n, m->h, B, m->wdtype, false);
+  if (need > (size_t)VQMC_NOALLOC_SCRATCH_BYTES)
+    return fail(VQMC_EWORKSPACE,
+                "vqmc_logprob_noalloc: n=%d h=%d B=%lld needs %zu scratch bytes, more than its fixed %zu; "
+                "use vqmc_logprob with a workspace",
+                m->n, m->h, (long long)B, need, (size_t)VQMC_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  hipError_t e = noalloc_scratch(&ws);
+  if (e != hipSuccess) return hip_status(e, "vqmc_logprob_noalloc scratch address");
+  return hip_status(launch_logprob(*m, S, B, logp, Z, ws, (hipStream_t)stream), "vqmc_logprob_noalloc");
 }
 
 int vqmc_logprob_backward(const vqmc_made* m, const int8_t* S, int64_t B, const float* coef, float* dP,

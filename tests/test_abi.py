@@ -99,6 +99,13 @@ def test_validation_rejects_before_launch(B):
     assert lib.vqmc_sr_gram_sampled(ctypes.byref(ok), fake, 8, None, fake, fake, fake, 1 << 30, None) == B.EINVAL
     nopt = B.MadeC(8, 4, B.F32, fake, None, fake, fake, fake)
     assert lib.vqmc_logprob(ctypes.byref(nopt), fake, 8, fake, None, fake, 1 << 30, None) == B.EINVAL
+    # the no-allocation variant refuses a size beyond its fixed scratch before touching the device
+    wide = B.MadeC(2000, 2000, B.BF16, fake, fake, fake, fake, fake)
+    assert lib.vqmc_workspace_bytes(B.WS_LOGPROB, 2000, 2000, 20000, B.BF16) > B.NOALLOC_SCRATCH_BYTES
+    assert lib.vqmc_logprob_noalloc(ctypes.byref(wide), fake, 20000, fake, None, None) == B.EWORKSPACE
+    assert b"fixed" in lib.vqmc_last_error()
+    assert lib.vqmc_logprob_noalloc(ctypes.byref(nopt), fake, 8, fake, None, None) == B.EINVAL
+    assert lib.vqmc_logprob_noalloc(ctypes.byref(ok), fake, 8, None, None, None) == B.EINVAL
     H = B.HamC(8, 9, 0, fake, fake, fake, None)
     assert lib.vqmc_energy(ctypes.byref(H), fake, 8, fake, None, 0, None) == B.EINVAL
     Hd = B.HamC(8, B.H_DENSE_F32, 0, None, None, None, fake)
