@@ -121,6 +121,11 @@ def time_calls(made, H, B_, reps=10, seed=2, names=None):
         ws_bs = B.workspace(B.WS_BACKWARD_SAMPLED, made, B_)
         calls["sample"] = lambda: B.sample_fwd(made, B_, seed, 1, S=S, logp=lp, Zs=Zs, Rt=Rt)
         calls["backward_sampled"] = lambda: B.backward_sampled(made, S, bufs.coef, Zs, Rt, ws=ws_bs)
+        if names is None or "sr_direction" in names:
+            # not part of the step: the SR (natural-gradient) direction of the batch gradient,
+            # from the sampler's byproducts (Gram, FP64 Cholesky solve, one gradient pass)
+            ws_sd = B.workspace(B.WS_SR_DIRECTION, made, B_)
+            calls["sr_direction"] = lambda: B.sr_direction(made, S, bufs.coef, 1e-3, B=B_, Zs=Zs, Rt=Rt, ws=ws_sd)
     else:
         calls["sample"] = lambda: B.sample(made, B_, seed, 1, S=bufs.S, logp=bufs.logp)
     calls.update({
