@@ -108,6 +108,22 @@ typedef struct {
   double sum_E;
 } vqmc_stats;
 
+/* Transverse-field Ising model (eq. hamiltonian with the couplings of eq. (e:tim)):
+ *   H = -sum_i (alpha_i X_i + beta_i Z_i) - sum_{i<j} beta_ij Z_i Z_j,
+ * X_i and Z_i the Pauli matrices of site i.  In the basis of spin strings s (s_i = 1 - 2 x_i)
+ * H_ss = -sum_i beta_i s_i - sum_{i<j} beta_ij s_i s_j and H_{s, s^(i)} = -alpha_i, s^(i) being s
+ * with site i negated; every other entry is 0.
+ *   alpha : n floats (transverse fields; alpha_i >= 0 keeps the ground state non-negative, as the
+ *           trial state psi = sqrt(pi) of Sec. 2.3 assumes), beta : n floats,
+ *   J     : n x n floats beta_ij, row-major, symmetric with zero diagonal (only the strict upper
+ *           triangle is read).  All device pointers. */
+typedef struct {
+  int32_t n;
+  const float* alpha;
+  const float* beta;
+  const float* J;
+} vqmc_tim;
+
 /* ------------------------------------------------------------------ sizes, errors */
 int64_t vqmc_ld(int64_t x);
 const char* vqmc_error_string(int status);
@@ -121,7 +137,9 @@ enum {
   VQMC_WS_BACKWARD_SAMPLED = 4,
   VQMC_WS_SR_GRAM = 5,
   VQMC_WS_SR_JVP = 6,
-  VQMC_WS_SR_DIRECTION = 7
+  VQMC_WS_SR_DIRECTION = 7,
+  VQMC_WS_TIM_ENERGY = 8,
+  VQMC_WS_TIM_STEP = 9
 };
 /* Workspace bytes needed by a call (host function, no device access). */
 size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t wdtype);
@@ -348,6 +366,30 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
               uint64_t step, int64_t sample_offset, int32_t algo, int8_t* S, float* logp, void* E,
               vqmc_stats* stats, float* coef, float* dP, float* db1, float* db2, void* ws,
               size_t ws_bytes, void* stream);
+
+/* Local energy of the transverse-field Ising model for the MADE trial state psi = sqrt(pi)
+ * (Sec. 2.1 local energy l(x) = (H psi)(x) / psi(x); eq. (e:tim); Sec. 2.3 trial state):
+ *     l(s) = H_ss - sum_i alpha_i exp(D_i / 2),   D_i = log pi(s^(i)) - log pi(s),
+ * for every string of S.  The n single-flip ratios of a sample come from one forward pass: a flip
+ * at site i changes only the pre-activations of the units site i feeds, and so only the
+ * conditionals of the sites after i; their logit changes are one masked product per sample
+ * (MFMA), its epilogue the sum of log-sigmoid differences.  H_ss in FP64 (its two-site part as
+ * vqmc_energy's dense kind), the off-diagonal sum in FP64 from FP32 D_i.
+ * S: B x ld(n) int8 spins, 16-byte aligned.  E: B doubles (device, overwritten).  D (nullable):
+ * B x ld(n) floats receiving D_i (columns >= n untouched).  Needs VQMC_WS_TIM_ENERGY workspace.
+ * EINVAL for H->n != m->n or h beyond 1024 (BF16 weights) / 512 (F32). */
+int vqmc_tim_energy(const vqmc_made* m, const vqmc_tim* H, const int8_t* S, int64_t B, double* E, float* D,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* One optimisation step for the TIM (Sec. 4 iteration without the update, as vqmc_step): the
+ * pipelined incremental sampler with its forward byproducts (needs m->band), vqmc_tim_energy,
+ * the FP64 statistics with c_b = (l_b - mean) / B, and the gradient sum_b c_b grad log pi(s_b)
+ * (Sec. 2.1: 2 grad log psi = grad log pi for psi = sqrt(pi)) from the sampler's byproducts.
+ * Writes S, logp (nullable), E (B doubles), stats, coef, dP, db1, db2.  Needs VQMC_WS_TIM_STEP
+ * workspace; all work on `stream`. */
+int vqmc_tim_step(const vqmc_made* m, const vqmc_tim* H, int64_t B, uint64_t seed, uint64_t step,
+                  int64_t sample_offset, int8_t* S, float* logp, double* E, vqmc_stats* stats, float* coef,
+                  float* dP, float* db1, float* db2, void* ws, size_t ws_bytes, void* stream);
 
 /* The uniforms the samplers consume (the Bernoulli draw of Algorithm 1, "Sample y_i"):
  * u[b][d] for b < B, d < n as defined above, written to u (B x n float, unpadded).

@@ -26,6 +26,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 H_CSR_INT, H_CSR_F32, H_DENSE_F32 = 0, 1, 2
 WS_LOGPROB, WS_BACKWARD, WS_SAMPLE_PLAIN, WS_STEP, WS_BACKWARD_SAMPLED, WS_SR_GRAM, WS_SR_JVP = 0, 1, 2, 3, 4, 5, 6
 WS_SR_DIRECTION = 7
+WS_TIM_ENERGY, WS_TIM_STEP = 8, 9
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VQMC_NOALLOC_SCRATCH_BYTES
 BAND_REC = 260
 TAG_TRAIN, TAG_EVAL = 0, 1
@@ -47,6 +48,10 @@ class HamC(ctypes.Structure):
 class StatsC(ctypes.Structure):
     _fields_ = [("mean_E", ctypes.c_double), ("var_E", ctypes.c_double), ("min_E", ctypes.c_double),
                 ("argmin", _i64), ("sum_E", ctypes.c_double)]
+
+
+class TimC(ctypes.Structure):
+    _fields_ = [("n", _i32), ("alpha", _vp), ("beta", _vp), ("J", _vp)]
 
 
 STATS_BYTES = ctypes.sizeof(StatsC)
@@ -75,6 +80,10 @@ _SIGS = {
     "vqmc_batch_stats": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp]),
     "vqmc_logprob": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_logprob_noalloc": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp]),
+    "vqmc_tim_energy": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(TimC), _vp, _i64, _vp, _vp, _vp, _sz,
+                                       _vp]),
+    "vqmc_tim_step": (ctypes.c_int, [ctypes.POINTER(MadeC), ctypes.POINTER(TimC), _i64, _u64, _u64, _i64, _vp, _vp,
+                                     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vqmc_logprob_backward": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                              _sz, _vp]),
     "vqmc_sr_gram": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -261,6 +270,30 @@ class Hamiltonian:
 
     def energy_dtype(self):
         return torch.int64 if self.e_is_int else torch.float64
+
+
+class Tim:
+    """Transverse-field Ising couplings on the device: alpha (n), beta (n), beta_ij (n x n dense,
+    symmetric, zero diagonal)."""
+
+    def __init__(self, alpha, beta, J, device="cuda"):
+        self.alpha = torch.as_tensor(np.asarray(alpha, np.float32), device=device).contiguous()
+        self.beta = torch.as_tensor(np.asarray(beta, np.float32), device=device).contiguous()
+        self.J = torch.as_tensor(np.asarray(J, np.float32), device=device).contiguous()
+        self.n = int(self.alpha.numel())
+        if self.beta.numel() != self.n or tuple(self.J.shape) != (self.n, self.n):
+            raise ValueError("alpha, beta must have n entries and J must be n x n")
+        self.W_tot = None
+
+    def cstruct(self) -> TimC:
+        return TimC(self.n, self.alpha.data_ptr(), self.beta.data_ptr(), self.J.data_ptr())
+
+    @property
+    def e_is_int(self) -> bool:
+        return False
+
+    def energy_dtype(self):
+        return torch.float64
 
 
 # ---------------------------------------------------------------- calls
@@ -504,6 +537,25 @@ def sr_direction(made: Made, S: torch.Tensor, coef: torch.Tensor, lam: float, B:
     return (xP, xb1, xb2, K) if want_K else (xP, xb1, xb2)
 
 
+def tim_energy(made: Made, H: Tim, S: torch.Tensor, B: int | None = None, want_D: bool = False,
+               ws: torch.Tensor | None = None, E: torch.Tensor | None = None):
+    """TIM local energies l(s_b) (B float64) and, with want_D, D[b][i] = log pi(s_b^(i)) - log pi(s_b)
+    (B x ld(n) float32)."""
+    B = S.shape[0] if B is None else B
+    _need_spins(made, S, B)
+    if H.n != made.n:
+        raise ValueError("Hamiltonian and model sizes differ")
+    dev = S.device
+    E = torch.empty(B, dtype=torch.float64, device=dev) if E is None else _need(E, "E", torch.float64, (B,))
+    D = torch.zeros((B, ld(made.n)), dtype=torch.float32, device=dev) if want_D else None
+    ws = workspace(WS_TIM_ENERGY, made, B) if ws is None else ws
+    m = made.cstruct()
+    hc = H.cstruct()
+    _check("vqmc_tim_energy", _lib.vqmc_tim_energy(ctypes.byref(m), ctypes.byref(hc), S.data_ptr(), B, E.data_ptr(),
+                                                   _ptr(D), ws.data_ptr(), ws.numel(), _stream()))
+    return (E, D) if want_D else E
+
+
 @dataclass
 class StepBuffers:
     """Caller-owned buffers of one optimisation step (allocated once, reused)."""
@@ -529,15 +581,24 @@ class StepBuffers:
             dP=torch.empty((made.n, made.h), dtype=torch.float32, device=dev),
             db1=torch.empty(made.h, dtype=torch.float32, device=dev),
             db2=torch.empty(made.n, dtype=torch.float32, device=dev),
-            ws=workspace(WS_STEP, made, B),
+            ws=workspace(WS_TIM_STEP if isinstance(H, Tim) else WS_STEP, made, B),
         )
 
 
-def step(made: Made, H: Hamiltonian, B: int, seed: int, step_idx: int, bufs: StepBuffers,
+def step(made: Made, H, B: int, seed: int, step_idx: int, bufs: StepBuffers,
          algo: int = 0, offset: int = 0):
-    """One optimisation step (sample, energy, statistics, gradient) into ``bufs``."""
+    """One optimisation step (sample, energy, statistics, gradient) into ``bufs``: vqmc_step for
+    a diagonal Hamiltonian, vqmc_tim_step for a Tim (incremental sampler only)."""
     m = made.cstruct()
     hc = H.cstruct()
+    if isinstance(H, Tim):
+        if algo != 0:
+            raise ValueError("the TIM step runs the incremental sampler only")
+        _check("vqmc_tim_step", _lib.vqmc_tim_step(
+            ctypes.byref(m), ctypes.byref(hc), B, seed, step_idx, offset, bufs.S.data_ptr(), bufs.logp.data_ptr(),
+            bufs.E.data_ptr(), bufs.stats.data_ptr(), bufs.coef.data_ptr(), bufs.dP.data_ptr(),
+            bufs.db1.data_ptr(), bufs.db2.data_ptr(), bufs.ws.data_ptr(), bufs.ws.numel(), _stream()))
+        return bufs
     _check("vqmc_step", _lib.vqmc_step(
         ctypes.byref(m), ctypes.byref(hc), B, seed, step_idx, offset, algo, bufs.S.data_ptr(),
         bufs.logp.data_ptr(), bufs.E.data_ptr(), bufs.stats.data_ptr(), bufs.coef.data_ptr(),

@@ -117,6 +117,18 @@ hipError_t noalloc_scratch(void** out) {
   return hipSuccess;
 }
 
+// TIM step workspace: [backward region (with the Rt slot)][masked copy of P^T][Zs: B x ld(n)
+// floats][TIM local-energy workspace]
+size_t tim_step_pm_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  return (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256);
+}
+size_t tim_step_zs_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  return tim_step_pm_offset(n, h, B, wdtype) + (size_t)round_up((int64_t)mask_w2t_bytes(n, h), 256);
+}
+size_t tim_step_tim_offset(int32_t n, int32_t h, int64_t B, int32_t wdtype) {
+  return tim_step_zs_offset(n, h, B, wdtype) + (size_t)round_up(B * round_up(n, kPad) * (int64_t)sizeof(float), 256);
+}
+
 int check_made(const vqmc_made* m, bool need_pt) {
   if (!m) return fail(VQMC_EINVAL, "made is NULL");
   if (m->n < 2 || m->h < 1) return fail(VQMC_EINVAL, "need n >= 2 and h >= 1 (n=%d h=%d)", m->n, m->h);
@@ -158,6 +170,8 @@ size_t vqmc_workspace_bytes(int which, int32_t n, int32_t h, int64_t B, int32_t 
     case VQMC_WS_BACKWARD_SAMPLED:
       return (size_t)round_up((int64_t)logprob_ws_bytes(n, h, B, wdtype, true), 256) + mask_w2t_bytes(n, h);
     case VQMC_WS_SR_DIRECTION: return sr_dir_layout(n, h, B, wdtype).total;
+    case VQMC_WS_TIM_ENERGY: return tim_ws_bytes(n, h, B, wdtype);
+    case VQMC_WS_TIM_STEP: return tim_step_tim_offset(n, h, B, wdtype) + tim_ws_bytes(n, h, B, wdtype);
     default: return 0;
   }
 }
@@ -486,6 +500,58 @@ int vqmc_step(const vqmc_made* m, const vqmc_hamiltonian* H, int64_t B, uint64_t
   if ((e = hipEventRecord(aux->stats_done, aux->stream)) != hipSuccess) return hip_status(e, "vqmc_step record");
   if ((e = launch_backward(*m, S, B, coef, dP, db1, db2, ws, st, aux->stats_done)) != hipSuccess)
     return hip_status(e, "vqmc_step backward");
+  return VQMC_OK;
+}
+
+static int check_tim(const vqmc_made* m, const vqmc_tim* H) {
+  if (!H) return fail(VQMC_EINVAL, "tim hamiltonian is NULL");
+  if (H->n != m->n) return fail(VQMC_EINVAL, "tim hamiltonian n=%d != model n=%d", H->n, m->n);
+  if (!H->alpha || !H->beta || !H->J) return fail(VQMC_EINVAL, "null tim coupling pointer");
+  if (!tim_supported(m->n, m->h, m->wdtype))
+    return fail(VQMC_EINVAL, "h = %d too large for the TIM local energy (BF16: h <= 1024, F32: h <= 512)", m->h);
+  return VQMC_OK;
+}
+
+int vqmc_tim_energy(const vqmc_made* m, const vqmc_tim* H, const int8_t* S, int64_t B, double* E, float* D,
+                    void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if ((r = check_tim(m, H))) return r;
+  if (B < 1 || !S || !E || !ws) return fail(VQMC_EINVAL, "bad tim energy arguments");
+  if ((uintptr_t)S & 15) return fail(VQMC_EINVAL, "S must be 16-byte aligned");
+  const size_t need = tim_ws_bytes(m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  return hip_status(launch_tim_energy(*m, *H, S, B, E, D, ws, (hipStream_t)stream), "vqmc_tim_energy");
+}
+
+int vqmc_tim_step(const vqmc_made* m, const vqmc_tim* H, int64_t B, uint64_t seed, uint64_t step,
+                  int64_t sample_offset, int8_t* S, float* logp, double* E, vqmc_stats* stats, float* coef,
+                  float* dP, float* db1, float* db2, void* ws, size_t ws_bytes, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if ((r = check_tim(m, H))) return r;
+  if (B < 1 || !S || !E || !stats || !coef || !dP || !db1 || !db2 || !ws)
+    return fail(VQMC_EINVAL, "bad tim step arguments");
+  if ((uintptr_t)S & 15) return fail(VQMC_EINVAL, "S must be 16-byte aligned");
+  if (sample_offset < 0) return fail(VQMC_EINVAL, "sample_offset < 0");
+  if (!m->band) return fail(VQMC_EINVAL, "vqmc_tim_step needs the band (vqmc_band)");
+  if ((uintptr_t)m->band & 15) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
+  if (!sample_pipe_supported(m->n, m->h)) return fail(VQMC_EINVAL, "h = %d too large for the pipelined sampler", m->h);
+  const size_t need = vqmc_workspace_bytes(VQMC_WS_TIM_STEP, m->n, m->h, B, m->wdtype);
+  if (ws_bytes < need) return fail(VQMC_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* w = (uint8_t*)ws;
+  float* Zs = (float*)(w + tim_step_zs_offset(m->n, m->h, B, m->wdtype));
+  void* Rt = backward_rt_slot(*m, B, ws);
+  hipError_t e = launch_sample_pipe(*m, B, seed, step, sample_offset, 0, S, logp, st, Zs, Rt);
+  if (e != hipSuccess) return hip_status(e, "vqmc_tim_step sample");
+  if ((e = launch_tim_energy(*m, *H, S, B, E, nullptr, w + tim_step_tim_offset(m->n, m->h, B, m->wdtype), st)) !=
+      hipSuccess)
+    return hip_status(e, "vqmc_tim_step energy");
+  if ((e = launch_stats(E, 0, B, stats, coef, st)) != hipSuccess) return hip_status(e, "vqmc_tim_step stats");
+  void* Pm = w + tim_step_pm_offset(m->n, m->h, B, m->wdtype);
+  if ((e = launch_backward_sampled(*m, S, B, coef, Zs, Rt, dP, db1, db2, ws, Pm, st)) != hipSuccess)
+    return hip_status(e, "vqmc_tim_step backward");
   return VQMC_OK;
 }
 

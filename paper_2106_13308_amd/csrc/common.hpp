@@ -29,6 +29,9 @@ __device__ inline float bf16_to_f32(bf16_t x) { return __uint_as_float(((uint32_
 template <typename T> __device__ inline float to_f32(T x);
 template <> __device__ inline float to_f32<float>(float x) { return x; }
 template <> __device__ inline float to_f32<bf16_t>(bf16_t x) { return bf16_to_f32(x); }
+template <typename T> __device__ inline T from_f32(float x);
+template <> __device__ inline float from_f32<float>(float x) { return x; }
+template <> __device__ inline bf16_t from_f32<bf16_t>(float x) { return f32_to_bf16(x); }
 
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon et al., SC'11: 10 rounds of the 4x32 Philox bijection with Weyl key schedule.

@@ -81,12 +81,6 @@ struct Mfma<float> {
   }
 };
 
-template <typename T>
-__device__ inline T from_f32(float x);
-template <>
-__device__ inline float from_f32<float>(float x) { return x; }
-template <>
-__device__ inline bf16_t from_f32<bf16_t>(float x) { return f32_to_bf16(x); }
 
 template <typename T>
 __device__ inline T spin_val(int8_t s);  // exact +-1 / 0
@@ -275,13 +269,14 @@ constexpr int W_BM = 64, W_BN = 64;     // weight gradient (M = n, N = h)
 // Unit k receives site d iff c[d] <= k, i.e. d < count_le(c, k): a prefix of Pt's row.
 // N tiles run in decreasing order of their K range (largest first).
 // RELU = false writes the pre-activation itself (the first layer applied to a direction in
-// parameter space, for the forward-mode product of the SR update).
-template <typename T, bool WRITE_T, bool RELU = true>
+// parameter space, for the forward-mode product of the SR update; in FP32 (TR = float) for the
+// single-flip differences of the TIM local energy).
+template <typename T, bool WRITE_T, bool RELU = true, typename TR = T>
 __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restrict__ S, int64_t lds,
                                                           const T* __restrict__ Pt, int64_t ldn,
                                                           const float* __restrict__ b1,
                                                           const int32_t* __restrict__ c, int n, int h,
-                                                          int64_t B, T* __restrict__ R, int64_t ldh,
+                                                          int64_t B, TR* __restrict__ R, int64_t ldh,
                                                           T* __restrict__ Rt, int64_t ldB) {
   using E = Engine<T, H_BM, H_BN>;
   __shared__ __attribute__((aligned(16))) uint8_t smem[E::SMEM];
@@ -312,8 +307,9 @@ __global__ __launch_bounds__(256) void fwd_hidden_kernel(const int8_t* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float a = acc[i][j][e] + bias;
-        vals[e] = from_f32<T>((k < h && bb + e < B) ? (RELU ? fmaxf(a, 0.f) : a) : 0.f);
-        if (bb + e < B && k < ldh) R[(bb + e) * ldh + k] = vals[e];
+        const float v = (k < h && bb + e < B) ? (RELU ? fmaxf(a, 0.f) : a) : 0.f;
+        vals[e] = from_f32<T>(v);
+        if (bb + e < B && k < ldh) R[(bb + e) * ldh + k] = from_f32<TR>(v);
       }
       if (WRITE_T && k < h && bb + 3 < ldB) store4<T>(Rt + (int64_t)k * ldB + bb, vals);
     }
@@ -1074,6 +1070,35 @@ static hipError_t sample_plain_t(const vqmc_made& m, int64_t B, uint64_t seed, u
   }
   if (logp) return hipMemcpyAsync(logp, lp_acc, (size_t)B * 4, hipMemcpyDeviceToDevice, st);
   return hipSuccess;
+}
+
+// The forward quantities of the TIM single-flip differences: logits Z (B x ldn) and the FP32
+// pre-activations A (B x ldh); ws holds the log p forward region (R, lp_part).
+template <typename T>
+static hipError_t tim_forward_t(const vqmc_made& m, const int8_t* S, int64_t B, float* Z, float* A, void* ws,
+                                hipStream_t st) {
+  const Geom g = geom(m.n, m.h, B);
+  const WsLayout L = layout(m.n, m.h, B, m.wdtype, 0);
+  uint8_t* w = (uint8_t*)ws;
+  T* R = (T*)(w + L.R);
+  float* lp_part = (float*)(w + L.lp_part);
+  fwd_hidden_kernel<T, false><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c, m.n,
+                                                                     m.h, B, R, g.ldh, nullptr, g.ldB);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  fwd_out_kernel<T, 0><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(
+      R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, Z, nullptr, nullptr,
+      nullptr, nullptr, g.ldB, nullptr, 0, 0, 0, 0, 0, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  fwd_hidden_kernel<T, false, false, float><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(
+      S, g.ldn, (const T*)m.Pt, g.ldn, m.b1, m.c, m.n, m.h, B, A, g.ldh, (T*)nullptr, g.ldB);
+  return hipGetLastError();
+}
+
+hipError_t launch_tim_forward(const vqmc_made& m, const int8_t* S, int64_t B, float* Z, float* A, void* ws,
+                              hipStream_t st) {
+  if (m.wdtype == VQMC_BF16) return tim_forward_t<bf16_t>(m, S, B, Z, A, ws, st);
+  return tim_forward_t<float>(m, S, B, Z, A, ws, st);
 }
 
 hipError_t launch_logprob(const vqmc_made& m, const int8_t* S, int64_t B, float* logp, float* Z,

@@ -88,6 +88,14 @@ hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16
                                      const uint16_t* St, const uint16_t* Rt, uint16_t* Dt, uint16_t* Pm,
                                      float* db1_part, int np1, const float* db2_part, int np2, float* dP, float* db1,
                                      float* db2, hipStream_t st, bool pm_ready);
+// TIM local energy (tim.hip): forward quantities (gemm.hip), then the single-flip differences
+hipError_t launch_tim_forward(const vqmc_made& m, const int8_t* S, int64_t B, float* Z, float* A, void* ws,
+                              hipStream_t st);
+bool tim_supported(int n, int h, int wdtype);
+size_t tim_ws_bytes(int n, int h, int64_t B, int dtype);
+// E: B doubles; D (nullable): B x ld(n) floats, log pi(s^(i)) - log pi(s)
+hipError_t launch_tim_energy(const vqmc_made& m, const vqmc_tim& H, const int8_t* S, int64_t B, double* E, float* D,
+                             void* ws, hipStream_t st);
 size_t sample_plain_ws_bytes(int n, int h, int64_t B, int dtype);
 hipError_t launch_sample_plain(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step,
                                int64_t offset, uint32_t tag, int8_t* S, float* logp, void* ws,

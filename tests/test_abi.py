@@ -99,6 +99,21 @@ def test_validation_rejects_before_launch(B):
     assert lib.vqmc_sr_gram_sampled(ctypes.byref(ok), fake, 8, None, fake, fake, fake, 1 << 30, None) == B.EINVAL
     nopt = B.MadeC(8, 4, B.F32, fake, None, fake, fake, fake)
     assert lib.vqmc_logprob(ctypes.byref(nopt), fake, 8, fake, None, fake, 1 << 30, None) == B.EINVAL
+    # TIM local energy and step: host-side checks
+    T8 = B.TimC(8, fake, fake, fake)
+    T9 = B.TimC(9, fake, fake, fake)
+    assert lib.vqmc_tim_energy(ctypes.byref(ok), ctypes.byref(T9), fake, 8, fake, None, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_tim_energy(ctypes.byref(ok), None, fake, 8, fake, None, fake, 1 << 30, None) == B.EINVAL
+    assert lib.vqmc_tim_energy(ctypes.byref(ok), ctypes.byref(T8), fake, 8, fake, None, fake, 16, None) == B.EWORKSPACE
+    assert lib.vqmc_tim_energy(ctypes.byref(ok), ctypes.byref(T8), fake + 8, 8, fake, None, fake, 1 << 30,
+                               None) == B.EINVAL                                  # spins misaligned
+    wide_f32 = B.MadeC(8, 600, B.F32, fake, fake, fake, fake, fake)
+    assert lib.vqmc_tim_energy(ctypes.byref(wide_f32), ctypes.byref(T8), fake, 8, fake, None, fake, 1 << 30,
+                               None) == B.EINVAL and b"too large" in lib.vqmc_last_error()
+    assert lib.vqmc_tim_step(ctypes.byref(ok), ctypes.byref(T8), 8, 0, 0, 0, fake, None, fake, fake, fake, fake,
+                             fake, fake, fake, 1 << 30, None) == B.EINVAL         # no band
+    assert lib.vqmc_workspace_bytes(B.WS_TIM_STEP, 100, 50, 64, B.BF16) > \
+        lib.vqmc_workspace_bytes(B.WS_TIM_ENERGY, 100, 50, 64, B.BF16) > 0
     # the no-allocation variant refuses a size beyond its fixed scratch before touching the device
     wide = B.MadeC(2000, 2000, B.BF16, fake, fake, fake, fake, fake)
     assert lib.vqmc_workspace_bytes(B.WS_LOGPROB, 2000, 2000, 20000, B.BF16) > B.NOALLOC_SCRATCH_BYTES
