@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--workload", default="maxcut10k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 comparison forms")
+    ap.add_argument("--no-tim", action="store_true", help="skip the TIM step reported beside the headline")
     ap.add_argument("--cpu-samples", type=int, default=2048)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3)")
@@ -75,6 +76,8 @@ def setup(workload: str, wdtype):
                              wdtype=wdtype, device="cuda")
     if "edges" in inst:
         H = B.Hamiltonian.from_edges(w.n, inst["edges"], inst["weights"], device="cuda")
+    elif "alpha" in inst:
+        H = B.Tim(inst["alpha"], inst["beta"], inst["beta_ij"], device="cuda")
     else:
         H = B.Hamiltonian.dense(inst["J"], device="cuda")
     torch.cuda.synchronize()
@@ -302,6 +305,131 @@ def _cpu_model():
     return "unknown"
 
 
+def tim_work(made, B_):
+    """Algorithmic work of one vqmc_tim_energy launch: the contraction that gives the logit changes
+    (2 sum_{i<d} (c[d] - c[i]) flops per sample, on MFMA) and the B n (n - 1) / 2 log-sigmoid
+    differences, 7 flops each (the FMA forming the changed logit, one exponential, one logarithm,
+    a minimum, the difference and the accumulation)."""
+    c = made.c.cpu().numpy().astype(np.int64)
+    n = c.shape[0]
+    idx = np.arange(n, dtype=np.int64)
+    pair_units = int((c * idx).sum() - (c * (n - 1 - idx)).sum())   # sum_{i<d} (c[d] - c[i])
+    elems = B_ * n * (n - 1) // 2
+    return {"contraction_flops": 2.0 * pair_units * B_, "elements": elems, "epilogue_flops": 7.0 * elems}
+
+
+def time_tim_calls(made, H, B_, reps=10, seed=2):
+    """HIP-event durations of the calls of one TIM step (vqmc_tim_step makes the same launches)."""
+    import torch
+    from paper_2106_13308_amd import binding as B
+    S, lp, Zs, Rt = B.sample_fwd(made, B_, seed, 1)
+    ws_t = B.workspace(B.WS_TIM_ENERGY, made, B_)
+    E = torch.empty(B_, dtype=torch.float64, device="cuda")
+    st, coef = B.batch_stats(B.tim_energy(made, H, S, B_, ws=ws_t, E=E))
+    ws_bs = B.workspace(B.WS_BACKWARD_SAMPLED, made, B_)
+    calls = {"refresh": made.refresh,
+             "sample": lambda: B.sample_fwd(made, B_, seed, 1, S=S, logp=lp, Zs=Zs, Rt=Rt),
+             "tim_energy": lambda: B.tim_energy(made, H, S, B_, ws=ws_t, E=E),
+             "stats": lambda: B.batch_stats(E),
+             "backward_sampled": lambda: B.backward_sampled(made, S, coef, Zs, Rt, ws=ws_bs)}
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def tim_report(w, made, H, steps, warmup):
+    """One TIM step timed (vqmc_refresh + vqmc_tim_step), its calls, and the roofline of the local
+    energy (bound: the FP32 vector ALU of its log-sigmoid epilogue)."""
+    ms, _, bufs = time_steps(made, H, w.B, steps, warmup)
+    calls = time_tim_calls(made, H, w.B)
+    wk = tim_work(made, w.B)
+    t = calls["tim_energy"] / 1e3
+    ach = wk["epilogue_flops"] / t / 1e12
+    return bufs, {
+        "ms_per_step": ms, "samples_per_s": w.B / (ms / 1e3),
+        "calls_ms": calls,
+        "roofline": {"kernel": "tim_flip_kernel (+ forward, masked W2 copy, dense diagonal energy, combine)",
+                     "call": "vqmc_tim_energy", "bound": "alu", "achieved": ach,
+                     "peak": PEAK["fp32_vector_tflops"], "unit": "TFLOP/s", "frac": ach / PEAK["fp32_vector_tflops"],
+                     "traffic": None,
+                     "elements_per_s": wk["elements"] / t,
+                     "contraction_tflops": wk["contraction_flops"] / t / 1e12},
+    }
+
+
+def cpu_baseline_tim(w, inst, nsites=160):
+    """The FP64 oracle's TIM step on a bounded sample: one sample drawn (sample_plain), its diagonal
+    entry, its single-flip log-ratios at nsites of the n sites and the analytic gradient; the
+    flip ratios' cost is scaled to all n sites (it is linear in the number of sites)."""
+    from oracle import bf16 as obf16, estimator as oest, philox as oph, sampling as osmp, tim as otim
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    p = dict(inst)
+    if w.wdtype == "bf16":
+        p["W1"] = obf16.round_to_bf16(inst["W1"])
+        p["W2"] = obf16.round_to_bf16(inst["W2"])
+    sites = np.linspace(0, w.n - 1, nsites).astype(np.int64)
+    t0 = time.perf_counter()
+    U = oph.uniforms(2, 0, np.arange(1), w.n)
+    S, _ = osmp.sample_plain(p, U)
+    otim.diag_energy(inst["beta"], inst["beta_ij"], S)
+    oest.logp_grad(p, S, np.ones(1))
+    t_fixed = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    otim.flip_logratio(p, S, sites=sites)
+    t_flip = time.perf_counter() - t1
+    per_sample = t_fixed + t_flip * w.n / nsites
+    return {"value": 1.0 / per_sample, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 sample: sample_plain, diagonal energy, gradient ({t_fixed:.1f} s) and the single-flip "
+                      f"log-ratios at {nsites} of {w.n} sites ({t_flip:.1f} s, scaled to all sites: the cost is "
+                      f"linear in the sites and in B)", "seconds": t_fixed + t_flip, "cpu_model": _cpu_model()}
+
+
+def main_tim(a):
+    import torch
+    from paper_2106_13308_amd import binding as B
+    from paper_2106_13308_amd import inputs
+    w = inputs.WORKLOADS[a.workload]
+    wd = B.BF16 if w.wdtype == "bf16" else B.F32
+    w, inst, made, H = setup(a.workload, wd)
+    log(f"TIM setup done: n={w.n} h={w.h} B={w.B} ({w.wdtype})")
+    if a.profile_only:
+        ms, _, _ = time_steps(made, H, w.B, a.steps, a.warmup)
+        log(f"tim step: {ms:.3f} ms")
+        return
+    bufs, rep = tim_report(w, made, H, a.steps, a.warmup)
+    log(f"tim step: {rep['ms_per_step']:.3f} ms; calls " + json.dumps({k: round(v, 4) for k, v in rep['calls_ms'].items()}))
+    st = B.stats_to_dict(bufs.stats)
+    out = {
+        "metric": "samples/s per VQMC step (sample+local energy+grad), transverse-field Ising model",
+        "value": rep["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": rep["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": w.wdtype, "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "h": w.h, "global_batch": w.B,
+                   "hamiltonian": "TIM, alpha ~ U(0,1), beta_i and beta_ij ~ U(-1,1), dense",
+                   "sampler": "incremental", "weights": w.wdtype, "parallelism": "single GPU"},
+        "roofline": rep["roofline"], "calls_ms": rep["calls_ms"],
+        "step_stats": {"mean_E": st["mean"], "min_E": st["min"], "var_E": st["var"]},
+    }
+    if not a.no_cpu:
+        log("oracle CPU baseline (TIM, bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline_tim(w, inst)
+        log(f"oracle: {out['cpu_baseline']['value']:.4f} samples/s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -313,6 +441,8 @@ def main():
     from paper_2106_13308_amd import binding as B
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"device {torch.cuda.get_device_name(0)}; workload {a.workload}")
+    if a.workload.startswith("tim"):
+        return main_tim(a)
     if a.calib_copy:
         x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -375,6 +505,17 @@ def main():
         "roofline": roof, "kernels": kernels, "forms": forms,
         "step_stats": {"mean_E": st["mean"], "min_E": st["min"], "var_E": st["var"]},
     }
+    if not a.no_tim:
+        # the paper's other Hamiltonian at the same n: the TIM step (its local energy needs the
+        # n single-flip ratios of every sample), reported beside the headline
+        from paper_2106_13308_amd import inputs
+        wt = inputs.WORKLOADS["tim10k"]
+        _, _, made_t, H_t = setup("tim10k", B.BF16)
+        _, rep = tim_report(wt, made_t, H_t, max(3, a.steps // 4), 2)
+        rep["config"] = {"workload": wt.name, "n": wt.n, "h": wt.h, "global_batch": wt.B, "weights": "bf16"}
+        out["tim_step"] = rep
+        log(f"tim10k step: {rep['ms_per_step']:.3f} ms")
+        del made_t, H_t
     if not a.no_cpu:
         log(f"oracle CPU baseline on {a.cpu_samples} samples ...")
         out["cpu_baseline"] = cpu_baseline(w, inst, a.cpu_samples)

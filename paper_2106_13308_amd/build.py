@@ -28,6 +28,11 @@ FLAGS = [
 ]
 
 
+# per-file flags: the TIM flip kernel keeps its MFMA results in ordinary VGPRs (its epilogue reads
+# every accumulator; in AGPRs each would need a copy, and the guarded K steps added more)
+FILE_FLAGS = {"tim.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -41,7 +46,7 @@ def sources() -> list[str]:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (res.stderr or "").splitlines()
                     if "packed-fp32-ops' is not a recognized feature" not in l)

@@ -54,15 +54,15 @@ struct TimK {
 // LDS row stride of dR in elements: at least kw, rows 16 bytes apart modulo 256 bytes (BF16) /
 // 4 floats apart modulo 64 (F32), so the 16 rows of one fragment read fall in distinct banks.
 template <typename T>
-__host__ __device__ inline int tim_ldr(int kw) {
-  if (sizeof(T) == 2) return (int)(round_up(kw - 8, 128) + 8);
-  return (int)(round_up(kw - 4, 64) + 4);
+__host__ __device__ constexpr int tim_ldr(int kw) {
+  return sizeof(T) == 2 ? (kw - 8 + 127) / 128 * 128 + 8 : (kw - 4 + 63) / 64 * 64 + 4;
 }
 
+// dR holds K columns [kbase, kbase + kw) of the block's rows, kw <= kalloc (the plain sweep:
+// round_up(h, KS); the pipelined one: 32 NF, so that its row stride is a compile-time constant)
 template <typename T>
-__host__ __device__ inline size_t tim_lds_bytes(int h) {
-  const int kw = (int)round_up(h, TimK<T>::KS);
-  return (size_t)TIM_BM * tim_ldr<T>(kw) * sizeof(T) + (size_t)round_up(h, 4) * 4 + 4 * TIM_BM * 4 +
+__host__ __device__ inline size_t tim_lds_bytes(int h, int kalloc) {
+  return (size_t)TIM_BM * tim_ldr<T>(kalloc) * sizeof(T) + (size_t)round_up(h, 32) * 4 + 4 * TIM_BM * 4 +
          TIM_BM * 8;
 }
 
@@ -76,7 +76,41 @@ __global__ void tim_w2_kernel(const T* __restrict__ P, const int32_t* __restrict
   P2[idx] = (k < c[d]) ? P[idx] : (T)0;
 }
 
-template <typename T>
+// One site block's contribution for this lane: acc[mi][r] is dz for row 16 mi + 4 (lane >> 4) + r
+// and the lane's column (spin sd, t = sd z_d, p = e^-|t|, rd = 1 / (1 + p), nmt = -min(t, 0)).
+//   lin  += min(u, 0) - min(t, 0), as (u - |u|) / 2 - min(t, 0) (exactly 0 when dz is 0)
+//   prod *= 1 + x, x = (e^-|u| - p) rd, one rounding per element (x is exactly 0 when dz is 0)
+__device__ inline void tim_epilogue(const floatx4_t (&acc)[4], float sd, float td, float pd, float rd, float nmt,
+                                    float (&lin)[4][4], float (&prod)[4][4]) {
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float u = fmaf(sd, acc[mi][r], td);
+      lin[mi][r] += fmaf(u - fabsf(u), 0.5f, nmt);
+      const float e = __builtin_amdgcn_exp2f(-fabsf(u) * TIM_L2E);
+      prod[mi][r] = fmaf(prod[mi][r], (e - pd) * rd, prod[mi][r]);
+    }
+}
+
+// Raw buffer loads of the masked second layer: base and size in scalar registers, the lane's byte
+// offset in a vector register.  An offset at or past the size reads zeros without touching
+// memory, so the sweep issues the same loads on every path (fixed wait counts) and fetches
+// only the K steps a block needs.
+typedef __amdgpu_buffer_rsrc_t tim_rsrc_t;
+constexpr uint32_t TIM_OOB = 0x7FFFFF00u;
+__device__ inline tim_rsrc_t tim_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, (int)bytes, 0x00020000);
+}
+// voff: the lane's byte offset (or TIM_OOB), soff: a uniform byte offset added after it
+__device__ inline uint4 tim_ld16(tim_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
+// dR rows of the flip block, the per-lane running sums, and the final reduction are shared by
+// both sweeps below; NF > 0 selects the pipelined BF16 sweep (register-prefetched operands),
+// NF = 0 the plain one (FP32 weights, or K ranges too long to prefetch).
+template <typename T, int NF>
 __global__ __launch_bounds__(256) void tim_flip_kernel(
     const int8_t* __restrict__ S, int64_t lds, const float* __restrict__ A, int64_t ldh,
     const float* __restrict__ Z, int64_t ldz, const T* __restrict__ P, const T* __restrict__ P2,
@@ -85,17 +119,18 @@ __global__ __launch_bounds__(256) void tim_flip_kernel(
   constexpr int KS = TimK<T>::KS;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const int kwmax = (int)round_up(h, KS);
-  const int ldr = tim_ldr<T>(kwmax);
+  const int ldr = NF > 0 ? tim_ldr<T>(32 * NF) : tim_ldr<T>(kwmax);
   T* dR = (T*)smem;
   float* a_s = (float*)(smem + (size_t)TIM_BM * ldr * sizeof(T));
-  float* red = a_s + round_up(h, 4);                 // [4 waves][64 rows]
+  float* red = a_s + round_up(h, 32);                // [4 waves][64 rows]
   double* contrib = (double*)(red + 4 * TIM_BM);     // [64 rows]
 
   const int64_t wg = blockIdx.x;
   const int q = (int)(wg / B);
   const int64_t b = wg - (int64_t)q * B;
   const int i0 = q * TIM_BM;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int8_t* Sb = S + b * lds;
   const float* Zb = Z + b * ldz;
 
@@ -103,106 +138,194 @@ __global__ __launch_bounds__(256) void tim_flip_kernel(
   const int kbase = (c[i0] / KS) * KS;
   const int kw = kwmax - kbase;
 
-  for (int k = t; k < h; k += 256) a_s[k] = A[b * ldh + k];
+  for (int k = t; k < kwmax; k += 256) a_s[k] = k < h ? A[b * ldh + k] : 0.f;
   __syncthreads();
-  // dR rows of the block: wave wv builds rows wv, wv + 4, ...
-  for (int r = wv; r < TIM_BM; r += 4) {
-    const int i = i0 + r;
-    T* row = dR + (size_t)r * ldr;
-    if (i < n) {
-      const int ci = c[i];
-      const float two_s = 2.f * (float)Sb[i];
-      const T* Pi = P + (int64_t)i * ldh;
-      for (int kk = lane; kk < kw; kk += 64) {
-        const int k = kbase + kk;
-        float v = 0.f;
-        if (k >= ci && k < h) {
-          const float a = a_s[k];
-          v = fmaxf(a - two_s * to_f32<T>(Pi[k]), 0.f) - fmaxf(a, 0.f);
-        }
-        row[kk] = from_f32<T>(v);
+  // dR rows of the block: wave wv builds rows wv + 4 j (j < 16).  A lane covers CPL consecutive
+  // columns (16 bytes of weights) per pass; the 16 rows' weights are fetched together (buffer
+  // loads: columns past the block's K range and rows past n read zeros), then dR goes to LDS in
+  // 16-byte stores.
+  {
+    constexpr int CPL = 16 / (int)sizeof(T);
+    const tim_rsrc_t rp = tim_rsrc(P, (uint32_t)((int64_t)n * ldh * sizeof(T)));
+    for (int c0 = 0; c0 < kw; c0 += 64 * CPL) {
+      const int kk = c0 + CPL * lane;                  // first column of the lane (relative to kbase)
+      const bool col_ok = kk < kw;
+      uint4 pv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = i0 + wv + 4 * j;
+        const uint32_t off = (uint32_t)(((int64_t)i * ldh + kbase + kk) * sizeof(T));
+        pv[j] = tim_ld16(rp, (col_ok && i < n) ? off : TIM_OOB, 0);
       }
-    } else {
-      for (int kk = lane; kk < kw; kk += 64) row[kk] = (T)0;
+      if (col_ok) {
+        float av[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) av[e] = a_s[kbase + kk + e];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int r = wv + 4 * j, i = i0 + r;
+          const int ci = i < n ? c[i] : h;             // rows past n: no unit receives them
+          const float two_s = i < n ? 2.f * (float)Sb[i] : 0.f;
+          union {
+            uint4 u;
+            T e[CPL];
+          } w, o;
+          w.u = pv[j];
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            const int k = kbase + kk + e;
+            const float v = fmaxf(av[e] - two_s * to_f32<T>(w.e[e]), 0.f) - fmaxf(av[e], 0.f);
+            o.e[e] = from_f32<T>((k >= ci && k < h) ? v : 0.f);
+          }
+          *(uint4*)(dR + (size_t)r * ldr + kk) = o.u;
+        }
+      }
     }
   }
   __syncthreads();
 
   // per lane: rows 16 mi + 4 (lane >> 4) + r of the block, for the lane's column of each site block
-  float lin[4][4], comp[4][4], prod[4][4], lgs[4][4];
+  float lin[4][4], prod[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       lin[mi][r] = 0.f;
-      comp[mi][r] = 0.f;
       prod[mi][r] = 1.f;
-      lgs[mi][r] = 0.f;
     }
   const int nbd = (n + TIM_BN - 1) / TIM_BN;
   const int grow = lane >> 4, gcol = lane & 15;
   int since = 0;
-  for (int qd = q; qd < nbd; ++qd) {
-    const int dw = qd * TIM_BN + 16 * wv;   // first column of this wave
-    if (dw >= n) break;                      // wave-uniform: nothing left for this wave
-    const int d = dw + gcol;
-    const bool valid = d < n;
-    const float sd = valid ? (float)Sb[d] : 0.f;
-    const float td = valid ? sd * Zb[d] : 0.f;
-    const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
-    const float rd = 1.f / (1.f + pd);
-    const float mtd = fminf(td, 0.f);
-    // K end of the wave: the units feeding its last valid column
-    const int kd = min((int)round_up(c[min(dw + 15, n - 1)], KS), kwmax);
-    floatx4_t acc[4];
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-    const T* brow = P2 + (int64_t)(valid ? d : n - 1) * ldh;
-    if constexpr (sizeof(T) == 2) {
-      for (int k = kbase; k < kd; k += KS) {
-        const int kc = k + 8 * grow;
-        uint4 bv = *(const uint4*)(brow + kc);
-        if (!valid) bv = make_uint4(0u, 0u, 0u, 0u);
-        const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bv);
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-          const uint4 av = *(const uint4*)(dR + (size_t)(16 * mi + gcol) * ldr + (kc - kbase));
-          acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av), bf, acc[mi], 0, 0, 0);
-        }
-      }
-    } else {
-      for (int k = kbase; k < kd; k += KS) {
-        const int kc = k + grow;
-        const float bv = valid ? (float)brow[kc] : 0.f;
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-          const float av = (float)dR[(size_t)(16 * mi + gcol) * ldr + (kc - kbase)];
-          acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi], 0, 0, 0);
-        }
-      }
-    }
-    // epilogue: acc[mi][r] = dz for row 16 mi + 4 grow + r, column d
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float u = fmaf(sd, acc[mi][r], td);
-        const float e = __builtin_amdgcn_exp2f(-fabsf(u) * TIM_L2E);
-        const float x = (e - pd) * rd;
-        const float w = 1.f + x;
-        comp[mi][r] += x - (w - 1.f);
-        prod[mi][r] *= w;
-        lin[mi][r] += fminf(u, 0.f) - mtd;
-      }
+  auto renorm = [&]() {
     if (++since == TIM_RENORM) {
       since = 0;
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          lgs[mi][r] += __builtin_amdgcn_logf(prod[mi][r]);
+          lin[mi][r] -= TIM_LN2 * __builtin_amdgcn_logf(prod[mi][r]);
           prod[mi][r] = 1.f;
         }
+    }
+  };
+  if constexpr (NF > 0) {
+    // Per block: the products (B fragments already in registers, A fragments from LDS one K
+    // step ahead), then the next block's loads (its K end read a block ahead through the
+    // scalar cache, its spins and logits, only the B fragments it needs), then this block's
+    // epilogue, which covers their latency.
+    const tim_rsrc_t rs = tim_rsrc(P2, (uint32_t)((int64_t)n * ldh * 2));
+    const bf16_t* arow = (const bf16_t*)dR + (size_t)gcol * ldr + 8 * grow;
+    auto kend = [&](int qd) -> int {   // wave-uniform K end of block qd (kbase when it is past n)
+      const int dw = qd * TIM_BN + 16 * wv;
+      if (dw >= n) return kbase;
+      return min((int)round_up(c[min(dw + 15, n - 1)], 32), kwmax);
+    };
+    uint4 bfr[NF];
+    int nk = (kend(q) - kbase) / 32;
+    int dl = min(q * TIM_BN + 16 * wv + gcol, n - 1);
+    int s_raw = Sb[dl];
+    float z_raw = Zb[dl];
+    uint32_t roff = (uint32_t)(((int64_t)dl * ldh + kbase + 8 * grow) * 2);
+    // B fragments in groups of four behind a uniform branch: the out-of-range loads still pass
+    // through the address unit, so only the last group of a block carries any
+    auto fetch_b = [&](int need) {
+#pragma unroll
+      for (int g = 0; g < NF / 4; ++g) {
+        if (4 * g < need) {
+#pragma unroll
+          for (int f = 4 * g; f < 4 * g + 4; ++f) bfr[f] = tim_ld16(rs, f < need ? roff : TIM_OOB, 64u * f);
+        }
+      }
+    };
+    fetch_b(nk);
+    for (int qd = q;; ++qd) {
+      const int dw = qd * TIM_BN + 16 * wv;
+      if (dw >= n) break;
+      const int nk_next = (kend(qd + 1) - kbase) / 32;
+      floatx4_t acc[4];
+      if (nk <= 0) {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+      } else {
+        constexpr int LDR = tim_ldr<bf16_t>(32 * NF);   // == ldr: every LDS offset below is an immediate
+        uint4 a[2][4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) a[0][mi] = *(const uint4*)(arow + 16 * mi * LDR);
+        // a guarded body rather than an early exit, so that the loop unrolls fully; the next
+        // step's A fragments are read whether or not it is needed (within the row; unused)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          if (f < nk) {
+            if (f + 1 < NF) {
+#pragma unroll
+              for (int mi = 0; mi < 4; ++mi)
+                a[(f + 1) & 1][mi] = *(const uint4*)(arow + 16 * mi * LDR + 32 * (f + 1));
+            }
+            const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bfr[f]);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+              acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8_t, a[f & 1][mi]), bf,
+                  f == 0 ? (floatx4_t){0.f, 0.f, 0.f, 0.f} : acc[mi], 0, 0, 0);
+          }
+        }
+      }
+      const bool valid = dw + gcol < n;
+      const float sd = valid ? (float)s_raw : 0.f;
+      const float td = valid ? sd * z_raw : 0.f;
+      const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
+      const float rd = __builtin_amdgcn_rcpf(1.f + pd);
+      const float nmt = -0.5f * (td - fabsf(td));
+      // the next block's operands
+      dl = min(dw + TIM_BN + gcol, n - 1);
+      s_raw = Sb[dl];
+      z_raw = Zb[dl];
+      roff = (uint32_t)(((int64_t)dl * ldh + kbase + 8 * grow) * 2);
+      fetch_b(nk_next);
+      tim_epilogue(acc, sd, td, pd, rd, nmt, lin, prod);
+      renorm();
+      nk = nk_next;
+    }
+  } else {
+    for (int qd = q; qd < nbd; ++qd) {
+      const int dw = qd * TIM_BN + 16 * wv;   // first column of this wave
+      if (dw >= n) break;                      // wave-uniform: nothing left for this wave
+      const int d = dw + gcol;
+      const bool valid = d < n;
+      const float sd = valid ? (float)Sb[d] : 0.f;
+      const float td = valid ? sd * Zb[d] : 0.f;
+      const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
+      const float rd = __builtin_amdgcn_rcpf(1.f + pd);
+      const float nmt = -0.5f * (td - fabsf(td));
+      // K end of the wave: the units feeding its last valid column
+      const int kd = min((int)round_up(__builtin_amdgcn_readfirstlane(c[min(dw + 15, n - 1)]), KS), kwmax);
+      floatx4_t acc[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+      const T* brow = P2 + (int64_t)(valid ? d : n - 1) * ldh;
+      if constexpr (sizeof(T) == 2) {
+        for (int k = kbase; k < kd; k += KS) {
+          const int kc = k + 8 * grow;
+          const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, *(const uint4*)(brow + kc));
+#pragma unroll
+          for (int mi = 0; mi < 4; ++mi) {
+            const uint4 av = *(const uint4*)(dR + (size_t)(16 * mi + gcol) * ldr + (kc - kbase));
+            acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av), bf, acc[mi], 0, 0, 0);
+          }
+        }
+      } else {
+        for (int k = kbase; k < kd; k += KS) {
+          const int kc = k + grow;
+          const float bv = (float)brow[kc];
+#pragma unroll
+          for (int mi = 0; mi < 4; ++mi) {
+            const float av = (float)dR[(size_t)(16 * mi + gcol) * ldr + (kc - kbase)];
+            acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi], 0, 0, 0);
+          }
+        }
+      }
+      tim_epilogue(acc, sd, td, pd, rd, nmt, lin, prod);
+      renorm();
     }
   }
   // row values of this lane's columns, summed over the 16 columns of the wave (a DPP row)
@@ -210,7 +333,7 @@ __global__ __launch_bounds__(256) void tim_flip_kernel(
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      float v = lin[mi][r] - (TIM_LN2 * (lgs[mi][r] + __builtin_amdgcn_logf(prod[mi][r])) + comp[mi][r]);
+      float v = lin[mi][r] - TIM_LN2 * __builtin_amdgcn_logf(prod[mi][r]);
       v += VQMC_DPP(v, 0xB1);   // quad_perm [1,0,3,2]
       v += VQMC_DPP(v, 0x4E);   // quad_perm [2,3,0,1]
       v += VQMC_DPP(v, 0x141);  // row_half_mirror
@@ -249,6 +372,8 @@ __global__ void tim_combine_kernel(const double* __restrict__ Ezz, const double*
 
 bool tim_supported(int n, int h, int wdtype) {
   if (n < 2 || h < 1) return false;
+  // the kernels address P and the masked second layer (n x ld(h)) with 32-bit byte offsets
+  if ((int64_t)n * round_up(h, kPad) * 4 >= (int64_t)TIM_OOB) return false;
   return wdtype == VQMC_BF16 ? h <= 1024 : h <= 512;
 }
 
@@ -301,12 +426,24 @@ static hipError_t tim_energy_t(const vqmc_made& m, const vqmc_tim& H, const int8
   const int64_t np2 = (int64_t)n * ldh;
   tim_w2_kernel<T><<<(unsigned)((np2 + 255) / 256), 256, 0, st>>>((const T*)m.P, m.c, n, ldh, P2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds_bytes = tim_lds_bytes<T>(h);
-  if ((e = hipFuncSetAttribute((const void*)tim_flip_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes)) != hipSuccess)
+  // the pipelined sweep holds NF K steps of B fragments in registers: K ranges up to 32 NF
+  auto kern = tim_flip_kernel<T, 0>;
+  int kalloc = (int)round_up(h, TimK<T>::KS);
+  if constexpr (sizeof(T) == 2) {
+    if (kalloc <= 32 * 8) {
+      kern = tim_flip_kernel<T, 8>;
+      kalloc = 32 * 8;
+    } else if (kalloc <= 32 * 16) {
+      kern = tim_flip_kernel<T, 16>;
+      kalloc = 32 * 16;
+    }
+  }
+  const size_t lds_bytes = tim_lds_bytes<T>(h, kalloc);
+  if ((e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)) !=
+      hipSuccess)
     return e;
-  tim_flip_kernel<T><<<(unsigned)(nbi * B), 256, lds_bytes, st>>>(S, ldn, A, ldh, Z, ldn, (const T*)m.P, P2, m.c, n,
-                                                                    h, B, nbi, H.alpha, H.beta, part, D, ldn);
+  kern<<<(unsigned)(nbi * B), 256, lds_bytes, st>>>(S, ldn, A, ldh, Z, ldn, (const T*)m.P, P2, m.c, n, h, B, nbi,
+                                                    H.alpha, H.beta, part, D, ldn);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   vqmc_hamiltonian Hd{};
   Hd.n = n;
