@@ -10,8 +10,9 @@
 // factorisation, and a blocked back substitution L^T y = w.
 //
 // Launches per block column j (nb = padded B / 64 of them):
-//   chol_panel_kernel   nb - j workgroups: each factors the diagonal block A_jj in LDS (the
-//                       same arithmetic in every workgroup, so the copies agree bit for bit);
+//   chol_panel_kernel   nb - j workgroups: each factors the diagonal block A_jj, blocked by 16
+//                       columns (the same arithmetic in every workgroup, so the copies agree
+//                       bit for bit);
 //                       workgroup 0 stores L_jj and w_j, workgroup i > 0 solves its block row
 //                       L_{j+i,j} = A_{j+i,j} L_jj^-T and updates w_{j+i} -= L_{j+i,j} w_j;
 //   chol_update_kernel  one workgroup per block (i, k), j < k <= i: A_ik -= L_ij L_kj^T.
@@ -41,66 +42,144 @@ __global__ void chol_init_kernel(const float* __restrict__ K, int64_t B, int64_t
   if (idx < ld) w[idx] = (idx < B) ? scale * (double)rhs[idx] : 0.0;
 }
 
-// Unblocked right-looking Cholesky of the 64 x 64 block L (lower triangle; LDS, 256 threads)
-// together with the forward substitution of w: after step c, column c of L and w[c] are final.
-__device__ inline void factor_block(double (*L)[CB + 1], double* w) {
+// The panel is blocked again inside, by 16 columns (SB): a sub-block's columns are factored one
+// after another by the lanes that own its rows (a row per lane, at most 16 dependent updates
+// per column, in registers), then everything to its right is brought up to date by a rank-16
+// update spread over all 256 threads.  The sequential part of a 64-column panel is thus four
+// short chains instead of one long one.
+constexpr int SB = 16;
+
+// Lane-per-row solve of the 16 columns [s0, s0 + SB) of one row x against the factored
+// diagonal sub-block D (D[q][c], q >= c, of L): x[c] = (x[c] - sum_{c' < c} x[c'] D[c][c']) / D[c][c].
+__device__ inline void chol_row_solve16(double (&x)[SB], const double (*L)[CB + 1], int s0) {
+#pragma unroll
+  for (int c = 0; c < SB; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) v = fma(-x[q], L[s0 + c][s0 + q], v);
+    x[c] = v / L[s0 + c][s0 + c];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Cholesky of the diagonal block F (lower triangle, in place) with the forward substitution of
+// w (in wc) folded in; 256 threads.
+__device__ inline void chol_factor_block(double (*F)[CB + 1], double* wc) {
   const int t = threadIdx.x;
-  for (int c = 0; c < CB; ++c) {
-    const double piv = sqrt(L[c][c]);  // NaN if the block is not positive definite
-    const double inv = 1.0 / piv;
-    __syncthreads();
-    if (t < CB) {
-      if (t > c) L[t][c] *= inv;
-      else if (t == c) {
-        L[c][c] = piv;
-        w[c] *= inv;
+  for (int s0 = 0; s0 < CB; s0 += SB) {
+    // the diagonal sub-block: one lane per row, its 16 entries factored column by column
+    if (t < SB) {
+      const int r = s0 + t;
+      for (int c = 0; c < SB; ++c) {
+        const int cc = s0 + c;
+        if (t == c) {
+          double v = F[cc][cc];
+          for (int q = s0; q < cc; ++q) v = fma(-F[cc][q], F[cc][q], v);
+          F[cc][cc] = sqrt(v);  // NaN if the block is not positive definite
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        if (t > c) {
+          double v = F[r][cc];
+          for (int q = s0; q < cc; ++q) v = fma(-F[r][q], F[cc][q], v);
+          F[r][cc] = v / F[cc][cc];
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+      }
+      // forward substitution of the sub-block's part of w
+      for (int c = 0; c < SB; ++c) {
+        const int cc = s0 + c;
+        if (t == c) {
+          double v = wc[cc];
+          for (int q = s0; q < cc; ++q) v = fma(-F[cc][q], wc[q], v);
+          wc[cc] = v / F[cc][cc];
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
-    for (int e = t; e < CB * CB; e += 256) {
-      const int r = e >> 6, q = e & (CB - 1);
-      if (q > c && q <= r) L[r][q] -= L[r][c] * L[q][c];
+    // rows below the sub-block: their 16 entries of these columns, a row per thread
+    const int r = s0 + SB + t;
+    if (t < CB - s0 - SB) {
+      double x[SB];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) x[c] = F[r][s0 + c];
+      chol_row_solve16(x, F, s0);
+#pragma unroll
+      for (int c = 0; c < SB; ++c) F[r][s0 + c] = x[c];
     }
-    if (t > c && t < CB) w[t] -= L[t][c] * w[c];
+    __syncthreads();
+    // rank-16 update of the trailing lower triangle and of the rest of w
+    const int m = CB - s0 - SB;
+    for (int e = t; e < m * m; e += 256) {
+      const int rr = e / m, qq = e - rr * m;
+      if (qq <= rr) {
+        const int r2 = s0 + SB + rr, q2 = s0 + SB + qq;
+        double v = F[r2][q2];
+#pragma unroll
+        for (int c = 0; c < SB; ++c) v = fma(-F[r2][s0 + c], F[q2][s0 + c], v);
+        F[r2][q2] = v;
+      }
+    }
+    if (t < m) {
+      const int r2 = s0 + SB + t;
+      double v = wc[r2];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) v = fma(-F[r2][s0 + c], wc[s0 + c], v);
+      wc[r2] = v;
+    }
     __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int64_t ld, int j,
                                                          double* __restrict__ w) {
-  __shared__ double L[CB][CB + 1];
+  __shared__ double F[CB][CB + 1];
   __shared__ double X[CB][CB + 1];
-  __shared__ double wj[CB];
+  __shared__ double wc[CB];
   const int t = threadIdx.x;
   const int64_t j0 = (int64_t)j * CB;
   for (int e = t; e < CB * CB; e += 256) {
     const int r = e >> 6, c = e & (CB - 1);
-    L[r][c] = (c <= r) ? A[(j0 + r) * ld + j0 + c] : 0.0;
+    F[r][c] = A[(j0 + r) * ld + j0 + c];
   }
-  if (t < CB) wj[t] = w[j0 + t];
+  if (t < CB) wc[t] = w[j0 + t];
   __syncthreads();
-  factor_block(L, wj);
+  chol_factor_block(F, wc);
   if (blockIdx.x == 0) {
     for (int e = t; e < CB * CB; e += 256) {
       const int r = e >> 6, c = e & (CB - 1);
-      if (c <= r) A[(j0 + r) * ld + j0 + c] = L[r][c];
+      if (c <= r) A[(j0 + r) * ld + j0 + c] = F[r][c];
     }
-    if (t < CB) w[j0 + t] = wj[t];
+    if (t < CB) w[j0 + t] = wc[t];
     return;
   }
-  // block row i0 = j0 + 64 blockIdx.x: X L^T = A_ij, column by column
+  // block row i0 = j0 + 64 blockIdx.x: X L_jj^T = A_ij, blocked by 16 columns like the factor
   const int64_t i0 = j0 + (int64_t)blockIdx.x * CB;
   for (int e = t; e < CB * CB; e += 256) {
     const int r = e >> 6, c = e & (CB - 1);
     X[r][c] = A[(i0 + r) * ld + j0 + c];
   }
   __syncthreads();
-  for (int c = 0; c < CB; ++c) {
-    if (t < CB) X[t][c] /= L[c][c];
+  for (int s0 = 0; s0 < CB; s0 += SB) {
+    if (t < CB) {
+      double x[SB];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) x[c] = X[t][s0 + c];
+      chol_row_solve16(x, F, s0);
+#pragma unroll
+      for (int c = 0; c < SB; ++c) X[t][s0 + c] = x[c];
+    }
     __syncthreads();
-    for (int e = t; e < CB * CB; e += 256) {
-      const int r = e >> 6, q = e & (CB - 1);
-      if (q > c) X[r][q] -= X[r][c] * L[q][c];
+    const int m = CB - s0 - SB;  // X[:, later] -= X[:, sub-block] L[later, sub-block]^T
+    for (int e = t; e < CB * m; e += 256) {
+      const int r = e / m, q2 = s0 + SB + (e - (e / m) * m);
+      double v = X[r][q2];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) v = fma(-X[r][s0 + c], F[q2][s0 + c], v);
+      X[r][q2] = v;
     }
     __syncthreads();
   }
@@ -109,8 +188,8 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A,
     A[(i0 + r) * ld + j0 + c] = X[r][c];
   }
   if (t < CB) {
-    double s = 0.0;
-    for (int c = 0; c < CB; ++c) s += X[t][c] * wj[c];
+    double s = 0.0;  // (X w_j)[t], w_j the block's substituted values
+    for (int c = 0; c < CB; ++c) s = fma(X[t][c], wc[c], s);
     w[i0 + t] -= s;
   }
 }
@@ -149,36 +228,33 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A
     for (int b = 0; b < 4; ++b) A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] -= acc[a][b];
 }
 
-// Back substitution of block j: L_jj^T y_j = w_j (every workgroup solves it in LDS, the same
-// arithmetic), then workgroup i < j applies w_i -= L_ji^T y_j.
-__global__ __launch_bounds__(256) void chol_back_kernel(const double* __restrict__ A, int64_t ld, int j,
-                                                        double* __restrict__ w, double* __restrict__ y) {
-  __shared__ double L[CB][CB + 1];
-  __shared__ double wj[CB];
-  __shared__ double part[4][CB];
-  const int t = threadIdx.x;
+// Back substitution of block j: L_jj^T y_j = w_j, then workgroup i < j applies
+// w_i -= L_ji^T y_j.  Lane c holds column c of L_jj; y is found from the last row up, each new
+// y_r passed to the other lanes through LDS (every workgroup solves the block, the same
+// arithmetic, so the copies agree bit for bit).
+__global__ __launch_bounds__(64) void chol_back_kernel(const double* __restrict__ A, int64_t ld, int j,
+                                                       double* __restrict__ w, double* __restrict__ y) {
+  __shared__ double yv[CB];
+  const int c = threadIdx.x;
   const int64_t j0 = (int64_t)j * CB;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & (CB - 1);
-    L[r][c] = (c <= r) ? A[(j0 + r) * ld + j0 + c] : 0.0;
-  }
-  if (t < CB) wj[t] = w[j0 + t];
-  __syncthreads();
-  for (int c = CB - 1; c >= 0; --c) {
-    if (t == 0) wj[c] /= L[c][c];
+  double lc[CB];  // lc[r] = L[r][c] (used for r >= c)
+#pragma unroll
+  for (int r = 0; r < CB; ++r) lc[r] = A[(j0 + r) * ld + j0 + c];
+  double acc = w[j0 + c];
+#pragma unroll
+  for (int r = CB - 1; r >= 0; --r) {
+    if (c == r) yv[r] = acc / lc[r];
     __syncthreads();
-    if (t < c) wj[t] -= L[c][t] * wj[c];
-    __syncthreads();
+    if (c < r) acc = fma(-lc[r], yv[r], acc);
   }
-  if (blockIdx.x == 0 && t < CB) y[j0 + t] = wj[t];
+  if (blockIdx.x == 0) y[j0 + c] = yv[c];
   if (blockIdx.x >= j) return;
+  // (L_ji^T y_j)[q] = sum_r L[j0 + r][i0 + q] y_j[r], lane q = c
   const int64_t i0 = (int64_t)blockIdx.x * CB;
-  const int q = t & (CB - 1), g = t >> 6;  // column q of L_ji, rows 16 g .. 16 g + 15
   double s = 0.0;
-  for (int r = 16 * g; r < 16 * g + 16; ++r) s += A[(j0 + r) * ld + i0 + q] * wj[r];
-  part[g][q] = s;
-  __syncthreads();
-  if (t < CB) w[i0 + t] -= ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t]));
+#pragma unroll
+  for (int r = 0; r < CB; ++r) s = fma(A[(j0 + r) * ld + i0 + c], yv[r], s);
+  w[i0 + c] -= s;
 }
 
 __global__ void chol_out_kernel(const double* __restrict__ y, int64_t B, float* __restrict__ out) {
@@ -211,7 +287,7 @@ hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float*
     }
   }
   for (int j = nb - 1; j >= 0; --j) {
-    chol_back_kernel<<<(unsigned)(j > 0 ? j : 1), 256, 0, st>>>(A, ld, j, w, yd);
+    chol_back_kernel<<<(unsigned)(j > 0 ? j : 1), 64, 0, st>>>(A, ld, j, w, yd);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   chol_out_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(yd, B, y);

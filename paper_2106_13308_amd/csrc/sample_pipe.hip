@@ -34,7 +34,8 @@
 // meanwhile push block b-1's spins into the units completing after block b (all helpers),
 // compute the part of block b+1's logits that only needs units complete before block b
 // (helpers 4-9), draw block b+1's uniforms (helpers 0-1) and write out block b-1's spins and
-// log-probabilities (helpers 2-3).  Three waves per SIMD let the helpers' memory latency overlap; the two
+// log-probabilities (helpers 2-3).  Three waves per SIMD let the helpers' memory latency overlap (issue
+// priority: sweep, then the logit helpers, then the rest); the two
 // roles run separate loops with one barrier per block each.
 //
 // Arithmetic: FP32 state and logits.  BF16 weights: the products run on
@@ -252,6 +253,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 
   if (wv < SP_NSW) {
     // ================= sweep waves: samples 4wv..4wv+3, lane = (sample, 4-site group)
+    // issue priority: the sweep (the serial chain of each block) first, then the logit helpers
+    // (the longest helper work per block), then the rest
+    __builtin_amdgcn_s_setprio(3);
     const int ss = 4 * wv + (lane >> 4), g = lane & 15;
     SpRec ring[SP_PDS];
     auto fetch_rec = [&](SpRec& r, int u) {
@@ -366,6 +370,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   } else {
     // ================= helper waves
     const int hw = wv - SP_NSW;
+    if (hw >= SP_ZH0) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(0);
     float lp_part = 0.f;  // waves hw 2-3: log pi partial of sample 4(hw-2) + lane/16
     // spins, s*z and log pi partial of a swept block: helper hw in {2, 3}, lane =
     // (sample 4(hw-2) + lane/16, sites 4(lane%16)..+3)
