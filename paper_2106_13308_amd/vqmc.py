@@ -11,8 +11,29 @@ import json
 import time
 
 import torch
+from safetensors.torch import load_file, save_file
 
 from . import binding as B
+
+CHECKPOINT_FORMAT = "vqmc-trainer-1"
+
+
+def save_checkpoint(path: str, tensors: dict, meta: dict) -> None:
+    """Write named tensors (copied to host memory) and a JSON header to one safetensors file."""
+    host = {k: v.detach().to("cpu").contiguous() for k, v in tensors.items()}
+    save_file(host, path, metadata={"format": CHECKPOINT_FORMAT, "meta": json.dumps(meta)})
+
+
+def load_checkpoint(path: str) -> tuple[dict, dict]:
+    """Read a file written by save_checkpoint: (host tensors, JSON header).  safetensors parses
+    tensors and strings only; nothing in the file is executed."""
+    from safetensors import safe_open
+
+    with safe_open(path, framework="pt") as f:
+        hdr = f.metadata() or {}
+    if hdr.get("format") != CHECKPOINT_FORMAT:
+        raise ValueError(f"{path}: not a trainer checkpoint (format {hdr.get('format')!r})")
+    return load_file(path), json.loads(hdr["meta"])
 
 
 class LogProb(torch.autograd.Function):
@@ -78,6 +99,59 @@ class Trainer:
             out["best_cut"] = (self.H.W_tot - self.best_E) / 2
             out["mean_cut"] = (self.H.W_tot - st["mean"]) / 2
         return out
+
+    # ------------------------------------------------------------ checkpoint / resume
+    # The sampler's random numbers are Philox(seed, step, sample, site): a trainer restored from
+    # a checkpoint taken after step t draws, from step t on, exactly the strings the original run
+    # draws, so a resumed run reproduces the uninterrupted one bit for bit.
+    def state(self) -> tuple[dict, dict]:
+        m = self.made
+        tensors = {"P32": m.P32, "b1": m.b1, "b2": m.b2}
+        params = [m.P32, m.b1, m.b2]
+        for i, p in enumerate(params):
+            st = self.opt.state.get(p, {})
+            for k, v in st.items():
+                tensors[f"opt.{i}.{k}"] = v if torch.is_tensor(v) else torch.tensor(v)
+        meta = {"kind": type(self).__name__, "n": m.n, "h": m.h, "wdtype": m.wdtype, "batch": self.batch,
+                "seed": self.seed, "algo": self.algo, "t": self.t, "best_E": self.best_E,
+                "param_groups": [{k: v for k, v in g.items() if k != "params"} for g in self.opt.param_groups]}
+        return tensors, meta
+
+    def save(self, path: str) -> None:
+        """Parameters, optimiser state, step counter and seed to one file (safetensors)."""
+        tensors, meta = self.state()
+        save_checkpoint(path, tensors, meta)
+
+    def load(self, path: str) -> None:
+        """Restore what save() wrote into this trainer (same n, h, batch and kind), then refresh
+        the working-precision copies of the parameters."""
+        tensors, meta = load_checkpoint(path)
+        m = self.made
+        mine = {"kind": type(self).__name__, "n": m.n, "h": m.h, "batch": self.batch}
+        for k, v in mine.items():
+            if meta.get(k) != v:
+                raise ValueError(f"{path}: checkpoint has {k} = {meta.get(k)!r}, this trainer {v!r}")
+        params = [m.P32, m.b1, m.b2]
+        with torch.no_grad():
+            for name, p in zip(("P32", "b1", "b2"), params):
+                if tensors[name].shape != p.shape:
+                    raise ValueError(f"{path}: {name} has shape {tuple(tensors[name].shape)}")
+                p.copy_(tensors[name])
+        for i, p in enumerate(params):
+            st = {k.split(".", 2)[2]: v for k, v in tensors.items() if k.startswith(f"opt.{i}.")}
+            if st:
+                # 'step' stays a host tensor (torch.optim's default); the moments live with p
+                self.opt.state[p] = {k: (v if k == "step" else v.to(p.device)) for k, v in st.items()}
+            else:
+                self.opt.state.pop(p, None)
+        for g, saved in zip(self.opt.param_groups, meta["param_groups"]):
+            g.update({k: (tuple(v) if isinstance(v, list) else v) for k, v in saved.items()})
+        self.seed, self.algo, self.t, self.best_E = meta["seed"], meta["algo"], meta["t"], meta["best_E"]
+        self._restore(meta)
+        m.refresh()
+
+    def _restore(self, meta: dict) -> None:
+        pass
 
     def evaluate(self, batch: int = 1024) -> dict:
         """Mean energy of a fresh batch drawn with the evaluation tag (Sec. 5.1: a batch of
@@ -155,6 +229,14 @@ class SRTrainer(Trainer):
             rdt = torch.bfloat16 if made.wdtype == B.BF16 else torch.float32
             self.Rt = torch.empty((made.h, B.ld(batch)), dtype=rdt, device=dev)
         self.sr_ws = B.workspace(B.WS_SR_DIRECTION, made, batch)
+
+    def state(self) -> tuple[dict, dict]:
+        tensors, meta = super().state()
+        meta.update(sr_lr=self.lr, lam=self.lam)
+        return tensors, meta
+
+    def _restore(self, meta: dict) -> None:
+        self.lr, self.lam = meta["sr_lr"], meta["lam"]
 
     def step(self, log: bool = True) -> dict | None:
         with torch.no_grad():

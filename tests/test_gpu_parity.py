@@ -535,9 +535,9 @@ def test_sample_plain_matches_incremental(n, h, B):
 @pytest.mark.parametrize("wd", ["bf16", "f32"])
 def test_gradient_error_full_size_subset(wd):
     """n = 10^4, h = 2000, B = 2048: the score gradient of a 256-sample subset (with c_b
-    from the whole batch) against the FP64 oracle, computed by the kernels vqmc_step runs
-    (vqmc_backward_sampled on the sampler's own byproducts), with the ReLU side
-    teacher-forced where a pre-activation lies within rounding of 0."""
+    from the whole batch) against the FP64 oracle, computed by vqmc_backward_sampled on the
+    sampler's own byproducts (the kernels vqmc_step runs), with the ReLU side teacher-forced
+    where a pre-activation lies within rounding of 0."""
     _banner(f"gradient error n=10000 h=2000 subset=256 {wd}")
     wdtype = B_.F32 if wd == "f32" else B_.BF16
     w = inputs.WORKLOADS["maxcut10k_h2000"]
@@ -571,7 +571,7 @@ def test_gradient_error_full_size_subset(wd):
 
 
 @pytest.mark.parametrize("wd", ["bf16", "f32"])
-@pytest.mark.parametrize("n,h,B", [(2000, 500, 512), (10000, 1000, 2048)])
+@pytest.mark.parametrize("n,h,B", [(130, 127, 77), (200, 128, 333), (2000, 500, 512), (10000, 1000, 2048)])
 def test_step_gradient_matches_oracle_full_batch(n, h, B, wd):
     """The gradient vqmc_step returns (sampler byproducts -> the backward the bench times),
     whole batch, against the FP64 oracle's gradient on the same spins and coefficients."""
@@ -629,7 +629,8 @@ def test_step_matches_oracle(algo):
 
 
 @pytest.mark.parametrize("wd", ["f32", "bf16"])
-@pytest.mark.parametrize("n,h,B", [(60, 90, 200), (700, 350, 130), (10000, 1000, 2048)])
+@pytest.mark.parametrize("n,h,B", [(60, 90, 200), (700, 350, 130), (130, 127, 77), (200, 128, 333),
+                                   (10000, 1000, 2048)])
 def test_step_fused_equals_recompute(n, h, B, wd):
     """vqmc_step with the pipelined sampler takes relu(A) and the logits from the sampling;
     its gradient must equal the recomputing backward on the same spins and coefficients."""
