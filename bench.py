@@ -260,6 +260,26 @@ def _traffic(desc, workload):
     return tot
 
 
+def serial_chain(made, w, sample_ms):
+    """The sampler's serial chain, measured: vqmc_sample_cycles counts every wave's shader-clock
+    cycles between the barriers of the 64-site blocks.  The floor is blocks x the sweep's cycles
+    per block (the chain of Algorithm 1 that no product can shorten) at the measured clock; the
+    slowest helper's cycles per block show how far the products are from it."""
+    from paper_2106_13308_amd import binding as B
+    B.sample_cycles(made, w.B, 2, 0)
+    _, _, cyc = B.sample_cycles(made, w.B, 2, 1)
+    nb = (w.n + 63) // 64
+    cyc = cyc.astype(np.float64)
+    sweep = cyc[:, :2, 0].mean(axis=1)
+    helpers = cyc[:, 2:, 0].max(axis=1)
+    ghz = float((cyc[:, 0, 1] / (cyc[:, 0, 2] / 100e6)).mean() / 1e9)
+    floor_ms = float(sweep.mean()) / (ghz * 1e9) * 1e3  # the sweep's cycles summed over the blocks
+    return {"blocks": nb, "sweep_cycles_per_block": float(sweep.mean()) / nb,
+            "slowest_helper_cycles_per_block": float(helpers.mean()) / nb,
+            "cycles_per_block": float(cyc[:, 0, 1].mean()) / nb, "shader_clock_ghz": ghz,
+            "floor_ms": floor_ms, "kernel_ms": sample_ms, "frac": floor_ms / sample_ms}
+
+
 def roofline(call, kernels, made, H, workload):
     desc = _dominant_desc(call, made, H)
     ach = kernels[call][desc["metric"]]
@@ -484,6 +504,9 @@ def main():
     step_calls = {k: calls[k] for k in ("refresh", "sample", "energy", "stats", grad_call)}
     dom = max(step_calls, key=step_calls.get)
     roof = roofline(dom, kernels, made, H, w.name)
+    if dom == "sample" and made.band is not None:
+        roof["serial_chain"] = serial_chain(made, w, calls["sample"])
+        log("sampler serial chain: " + json.dumps({k: round(v, 4) for k, v in roof["serial_chain"].items()}))
     forms = {"bf16_incremental": {"ms_per_step": ms, "samples_per_s": value}}
     if not a.no_forms:
         made32 = B.Made(made.n, made.h, made.P32, made.b1, made.b2, made.c, wdtype=B.F32)

@@ -236,6 +236,21 @@ int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int
 int vqmc_sample_fwd(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
                     uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, void* stream);
 
+/* Measurement of the pipelined sampler (Algorithm 1 as vqmc_sample with a band, tag 0, sample
+ * offset 0; same S and logp): every wave also counts its shader-clock cycles (s_memtime)
+ * between the per-block barriers of the 64-site blocks.  *waves receives the waves per
+ * workgroup W (waves 0 and 1 run the serial sweep of each block, the others its products and
+ * I/O); workgroup g draws samples 8g .. 8g + 7.  cycles (device, ceil(B / 8) * W * 3 uint64):
+ *   cycles[(g * W + w) * 3]     = cycles wave w spent from leaving one block's barrier to
+ *                                 arriving at the next one's, summed over the blocks (its work,
+ *                                 including the issue slots it waited for),
+ *   cycles[(g * W + w) * 3 + 1] = cycles from its first departure to its last,
+ *   cycles[(g * W + w) * 3 + 2] = that span in ticks of the 100 MHz constant clock
+ *                                 (s_memrealtime), which gives the shader clock's rate.
+ * The sweep's count per block is the serial chain's critical path per block. */
+int vqmc_sample_cycles(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int8_t* S, float* logp,
+                       uint64_t* cycles, int32_t* waves, void* stream);
+
 /* Gradient of F = sum_b coef_b log pi(s_b) (as vqmc_logprob_backward) from the Zs and Rt that
  * vqmc_sample_fwd wrote for S: G = coef_b s sigma(-s z) directly from Zs, then the hidden
  * adjoint and the two weight-gradient halves.  Outputs overwritten.  Needs

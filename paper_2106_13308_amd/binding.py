@@ -69,6 +69,8 @@ _SIGS = {
     "vqmc_refresh": (ctypes.c_int, [_i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vqmc_check_nonfinite": (ctypes.c_int, [_i32]),
     "vqmc_sample": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp]),
+    "vqmc_sample_cycles": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _vp, _vp, _vp,
+                                          ctypes.POINTER(ctypes.c_int32), _vp]),
     "vqmc_sample_fwd": (ctypes.c_int, [ctypes.POINTER(MadeC), _i64, _u64, _u64, _i64, _u32, _vp, _vp, _vp, _vp,
                                        _vp]),
     "vqmc_backward_sampled": (ctypes.c_int, [ctypes.POINTER(MadeC), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -382,6 +384,25 @@ def sample_fwd(made: Made, B: int, seed: int, step: int, offset: int = 0, tag: i
                                                    _dev(logp).data_ptr(), _dev(Zs).data_ptr(), _dev(Rt).data_ptr(),
                                                    _stream()))
     return S, logp, Zs, Rt
+
+
+def sample_cycles(made: Made, B: int, seed: int, step: int):
+    """vqmc_sample_cycles: the pipelined draw with per-wave cycle counts.  Returns (S, logp,
+    cycles) with cycles a host int64 array [ceil(B / 8), waves, 3]: shader-clock cycles spent
+    working between the per-block barriers, cycles from the first departure to the last, and
+    that span in 100 MHz ticks (waves 0-1: the sweep)."""
+    dev = made.P.device
+    S = empty_spins(B, made.n, dev)
+    logp = torch.empty(B, dtype=torch.float32, device=dev)
+    groups = (B + 7) // 8
+    cyc = torch.zeros(groups * 64 * 3, dtype=torch.int64, device=dev)  # room for up to 64 waves
+    waves = ctypes.c_int32(0)
+    m = made.cstruct()
+    _check("vqmc_sample_cycles", _lib.vqmc_sample_cycles(ctypes.byref(m), B, seed, step, _dev(S).data_ptr(),
+                                                         logp.data_ptr(), cyc.data_ptr(), ctypes.byref(waves),
+                                                         _stream()))
+    W = waves.value
+    return S, logp, cyc[: groups * W * 3].view(groups, W, 3).cpu().numpy()
 
 
 def backward_sampled(made: Made, S: torch.Tensor, coef: torch.Tensor, Zs: torch.Tensor, Rt: torch.Tensor,

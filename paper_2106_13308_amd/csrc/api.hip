@@ -255,6 +255,21 @@ int vqmc_sample(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int
       "vqmc_sample");
 }
 
+int vqmc_sample_cycles(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int8_t* S, float* logp,
+                       uint64_t* cycles, int32_t* waves, void* stream) {
+  int r = check_made(m, true);
+  if (r) return r;
+  if (B < 1 || !S || !cycles || !waves) return fail(VQMC_EINVAL, "bad vqmc_sample_cycles arguments");
+  if ((uintptr_t)S & 7) return fail(VQMC_EINVAL, "S must be 8-byte aligned");
+  if (!m->band) return fail(VQMC_EINVAL, "vqmc_sample_cycles needs the band (vqmc_band)");
+  if ((uintptr_t)m->band & 15) return fail(VQMC_EINVAL, "band must be 16-byte aligned");
+  if (!sample_pipe_supported(m->n, m->h))
+    return fail(VQMC_EINVAL, "h = %d too large for the pipelined sampler", m->h);
+  *waves = sample_pipe_waves();
+  return hip_status(launch_sample_pipe_cycles(*m, B, seed, step, S, logp, cycles, (hipStream_t)stream),
+                    "vqmc_sample_cycles");
+}
+
 int vqmc_sample_fwd(const vqmc_made* m, int64_t B, uint64_t seed, uint64_t step, int64_t sample_offset,
                     uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, void* stream) {
   int r = check_made(m, true);

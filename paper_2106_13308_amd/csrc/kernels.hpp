@@ -44,6 +44,10 @@ size_t sample_tables_bytes(int n, int h, int wdtype);
 hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                               uint32_t tag, int8_t* S, float* logp, hipStream_t st, float* Zs = nullptr,
                               void* Rt = nullptr);
+// the same sampler counting each wave's cycles between its per-block barriers (vqmc_sample_cycles)
+int sample_pipe_waves();
+hipError_t launch_sample_pipe_cycles(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int8_t* S,
+                                     float* logp, uint64_t* cycles, hipStream_t st);
 hipError_t launch_band(const vqmc_made& m, float* band, hipStream_t st, bool tiles = true);
 void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int64_t* pm, int* nzt, int* nut);
 hipError_t launch_mask_w2t(const vqmc_made& m, uint16_t* Pm, hipStream_t st);

@@ -180,14 +180,18 @@ struct SpRec {
   float ns;   // minus the sum of the W1 halves
 };
 
-template <typename WT, bool PLANES>
+// TIMING: each wave also counts its cycles (s_memtime) between the per-block barriers.
+// cyc[(g * 12 + w) * 3] = cycles wave w of sample group g spent from leaving one block's barrier
+// to arriving at the next one's, summed over the blocks; [.. + 1] = cycles from the first
+// departure to the last; [.. + 2] = the same span in ticks of the 100 MHz constant clock.
+template <typename WT, bool PLANES, bool TIMING>
 __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     const uint8_t* __restrict__ ztab, const uint8_t* __restrict__ utab, int nzt, int nut,
     const float* __restrict__ band, const float* __restrict__ b1, const float* __restrict__ b2,
     const int32_t* __restrict__ c,
     int n, int h, int LDA, int64_t B, uint64_t seed, uint64_t step, int64_t offset, uint32_t tag,
     int8_t* __restrict__ S, int64_t lds, float* __restrict__ logp, float* __restrict__ Zs, WT* __restrict__ Rt,
-    int64_t ldB) {
+    int64_t ldB, uint64_t* __restrict__ cyc) {
   using F = SpFrag<WT>;
   constexpr int KC = F::KC;
   constexpr int BLK = SP_MS * SP_T;
@@ -206,6 +210,29 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
   const int l16 = lane & 15, g4 = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * SP_MS;
   const int nb = (n + SP_T - 1) / SP_T;
+  uint64_t tm_dep = 0, tm_t0 = 0, tm_busy = 0, tm_r0 = 0;
+  auto tm_start = [&]() {
+    if constexpr (TIMING) {
+      tm_r0 = __builtin_amdgcn_s_memrealtime();
+      tm_t0 = tm_dep = __builtin_amdgcn_s_memtime();
+    }
+  };
+  auto block_barrier = [&]() {
+    if constexpr (TIMING) tm_busy += __builtin_amdgcn_s_memtime() - tm_dep;
+    lds_barrier();
+    if constexpr (TIMING) tm_dep = __builtin_amdgcn_s_memtime();
+  };
+  auto tm_store = [&]() {
+    if constexpr (TIMING) {
+      if (lane == 0) {
+        const uint64_t r1 = __builtin_amdgcn_s_memrealtime();
+        uint64_t* o = cyc + ((int64_t)blockIdx.x * (SP_NSW + SP_NHW) + wv) * 3;
+        o[0] = tm_busy;
+        o[1] = tm_dep - tm_t0;
+        o[2] = r1 - tm_r0;
+      }
+    }
+  };
 
   // -logit(u) * 2^100 for a block: thread tt < 128 draws sites 4(tt&15)..+3 of sample tt>>4
   auto thresholds = [&](int blk, float* dst, int tt) {
@@ -274,6 +301,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     for (int e = 0; e < 4; ++e) zn[e] = cp[e] = 0.f;
     float* arow = st + ss * LDA;
     __syncthreads();
+    tm_start();
     for (int b = 0; b < nb; ++b) {
       const int d0 = SP_T * b, Tb = min(SP_T, n - d0);
       const int fprev = fbs(b), fcur = fbs(b + 1);
@@ -365,8 +393,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
       *(uint32_t*)(sb + cur * BLK + ss * SP_T + 4 * g) = word;
       *(uint2*)(sbf + cur * BLK + ss * SP_T + 4 * g) = make_uint2(bw[0], bw[1]);
       *(float4*)(zs + cur * BLK + ss * SP_T + 4 * g) = make_float4(zsv[0], zsv[1], zsv[2], zsv[3]);
-      lds_barrier();
+      block_barrier();
     }
+    tm_store();
   } else {
     // ================= helper waves
     const int hw = wv - SP_NSW;
@@ -527,6 +556,7 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
     typename F::Z fz[PDZ];
     It su[PDU], sz[PDZ];  // item held by each slot
     __syncthreads();      // the block bounds fb[] are written by every thread
+    tm_start();
     int zlim = 0;
     It cu = next_u(It{0, ntu});
     It cz = next_z(It{-1, 0}, zlim);
@@ -716,8 +746,9 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
             *(float4*)(dst + 16 * tt) = make_float4(acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]);
         }
       }
-      lds_barrier();
+      block_barrier();
     }
+    tm_store();
     // last block's spins and log pi, then the 16-lane log pi sum of each sample
     if (hw == 2 || hw == 3) {
       emit(nb - 1, (nb - 1) & 1);
@@ -899,12 +930,12 @@ void sample_tables_layout(int n, int h, int wdtype, int64_t* z, int64_t* u, int6
   *nut = t.nut;
 }
 
-template <typename WT, bool PLANES>
+template <typename WT, bool PLANES, bool TIMING = false>
 static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int64_t offset,
                                 uint32_t tag, int8_t* S, float* logp, float* Zs, void* Rt, int64_t ldB,
-                                hipStream_t st) {
+                                hipStream_t st, uint64_t* cyc = nullptr) {
   const size_t smem = sp_smem_bytes(m.n, m.h, PLANES);
-  hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT, PLANES>,
+  hipError_t e = hipFuncSetAttribute((const void*)sample_pipe_kernel<WT, PLANES, TIMING>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)((B + SP_MS - 1) / SP_MS);
@@ -914,9 +945,9 @@ static hipError_t launch_pipe_t(const vqmc_made& m, int64_t B, uint64_t seed, ui
   if (nbk * tb.nzt * tb.zt >= (INT64_C(1) << 32) || nbk * tb.nut * tb.ut >= (INT64_C(1) << 32))
     return hipErrorInvalidValue;
   const uint8_t* tab = (const uint8_t*)m.band;
-  sample_pipe_kernel<WT, PLANES><<<grid, SP_THREADS, smem, st>>>(
+  sample_pipe_kernel<WT, PLANES, TIMING><<<grid, SP_THREADS, smem, st>>>(
       tab + tb.z, tab + tb.u, tb.nzt, tb.nut, m.band, m.b1, m.b2, m.c, m.n, m.h,
-      sp_lda(m.h), B, seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs, (WT*)Rt, ldB);
+      sp_lda(m.h), B, seed, step, offset, tag, S, round_up(m.n, kPad), logp, Zs, (WT*)Rt, ldB, cyc);
   return hipGetLastError();
 }
 
@@ -929,6 +960,19 @@ hipError_t launch_sample_pipe(const vqmc_made& m, int64_t B, uint64_t seed, uint
     return launch_pipe_t<bf16_t, false>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
   }
   return launch_pipe_t<float, false>(m, B, seed, step, offset, tag, S, logp, Zs, Rt, ldB, st);
+}
+
+int sample_pipe_waves() { return SP_NSW + SP_NHW; }
+
+hipError_t launch_sample_pipe_cycles(const vqmc_made& m, int64_t B, uint64_t seed, uint64_t step, int8_t* S,
+                                     float* logp, uint64_t* cycles, hipStream_t st) {
+  const int64_t ldB = round_up(B, kPad);
+  if (m.wdtype == VQMC_BF16) {
+    if (sp_planes(m.n, m.h, m.wdtype))
+      return launch_pipe_t<bf16_t, true, true>(m, B, seed, step, 0, 0, S, logp, nullptr, nullptr, ldB, st, cycles);
+    return launch_pipe_t<bf16_t, false, true>(m, B, seed, step, 0, 0, S, logp, nullptr, nullptr, ldB, st, cycles);
+  }
+  return launch_pipe_t<float, false, true>(m, B, seed, step, 0, 0, S, logp, nullptr, nullptr, ldB, st, cycles);
 }
 
 }  // namespace vqmc

@@ -83,6 +83,14 @@ def test_validation_rejects_before_launch(B):
     assert lib.vqmc_sample(ctypes.byref(dt), 8, 0, 0, 0, 0, fake, None, None) == B.EDTYPE
     ok = B.MadeC(8, 4, B.F32, fake, fake, fake, fake, fake)
     assert lib.vqmc_sample(ctypes.byref(ok), 0, 0, 0, 0, 0, fake, None, None) == B.EINVAL
+    w = ctypes.c_int32(-1)
+    banded = B.MadeC(8, 4, B.F32, fake, fake, fake, fake, fake, fake)
+    assert lib.vqmc_sample_cycles(ctypes.byref(ok), 8, 0, 0, fake, None, fake, ctypes.byref(w), None) == B.EINVAL
+    assert b"band" in lib.vqmc_last_error()
+    assert lib.vqmc_sample_cycles(ctypes.byref(banded), 8, 0, 0, fake, None, None, ctypes.byref(w), None) == B.EINVAL
+    assert lib.vqmc_sample_cycles(ctypes.byref(banded), 0, 0, 0, fake, None, fake, ctypes.byref(w), None) == B.EINVAL
+    assert lib.vqmc_sample_cycles(ctypes.byref(banded), 8, 0, 0, fake + 1, None, fake, ctypes.byref(w), None) == B.EINVAL
+    assert w.value == -1
     assert lib.vqmc_sample(ctypes.byref(ok), 8, 0, 0, -1, 0, fake, None, None) == B.EINVAL
     big = B.MadeC(8, 5000, B.F32, fake, fake, fake, fake, fake)
     assert lib.vqmc_sample(ctypes.byref(big), 8, 0, 0, 0, 0, fake, None, None) == B.EINVAL

@@ -514,6 +514,28 @@ def test_sample_deterministic():
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("wd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,h,B", [(300, 200, 70), (2000, 500, 256)])
+def test_sample_cycles(n, h, B, wd):
+    """vqmc_sample_cycles draws what vqmc_sample draws and counts, per wave, cycles between the
+    block barriers: each wave's working cycles fit in its span, all waves of a workgroup span
+    the same blocks, and the measured shader clock is a plausible rate."""
+    _banner(f"sample cycles n={n} h={h} B={B} {wd}")
+    p, _ = instance(n, h, seed=5, graph=None, scale=2.0)
+    M = build_made(p, B_.F32 if wd == "f32" else B_.BF16)
+    S0, lp0 = B_.sample(M, B, 4, 7)
+    S, lp, cyc = B_.sample_cycles(M, B, 4, 7)
+    assert torch.equal(S, S0) and torch.equal(lp, lp0)
+    assert cyc.shape == ((B + 7) // 8, 12, 3)
+    busy, span, ticks = cyc[..., 0], cyc[..., 1], cyc[..., 2]
+    assert (busy > 0).all() and (busy <= span).all()
+    rel = np.abs(span - span[:, :1]) / span[:, :1]
+    assert rel.max() < 0.05
+    ghz = span / (ticks / 100e6) / 1e9
+    print(f"  sweep {busy[:, :2].mean() / span[:, 0].mean():.2f} of the span, clock {ghz.mean():.2f} GHz")
+    assert 0.5 < ghz.mean() < 4.0
+
+
 @pytest.mark.parametrize("n,h,B", [(20, 40, 128), (67, 33, 70), (130, 130, 64),
                                    # the n = h = 500, B = 4096 workload, and several hidden tiles
                                    (500, 500, 4096), (1000, 2000, 64)])
