@@ -821,7 +821,7 @@ static size_t sr_extra_offset(int n, int h, int64_t B, int dtype) {
   return (size_t)round_up((int64_t)layout(n, h, B, dtype, 1).total, 256);
 }
 size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype) {
-  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(B, h);
+  return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(n, h, B, dtype);
 }
 
 template <typename T>
@@ -854,7 +854,7 @@ static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
   bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
                                                              g.ldB, db1_part, g.ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st);
+  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st, G, S, g.ldn);
 }
 
 // The same Gram from the incremental sampler's byproducts: Zs (s_d z_d) gives G through the
@@ -883,7 +883,7 @@ static hipError_t sr_gram_sampled_t(const vqmc_made& m, const int8_t* S, int64_t
   bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
                                                              g.ldB, db1_part, g.ldh);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st);
+  return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st, G, S, g.ldn);
 }
 
 hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const void* Rt,

@@ -77,10 +77,13 @@ hipError_t launch_sr_jvp(const vqmc_made& m, const int8_t* S, int64_t B, const f
                          const float* gb2, float* v, void* ws, hipStream_t st);
 hipError_t launch_sr_gram_sampled(const vqmc_made& m, const int8_t* S, int64_t B, const float* Zs, const void* Rt,
                                   float* K, void* ws, hipStream_t st);
-size_t sr_gram_parts_bytes(int64_t B, int h);  // partial sums of the sweeps' work items + prefix lengths
+// scratch of the sweeps: FP32, the items' partial sums + prefix lengths; BF16, the segment table and
+// the segment-padded copies of G and S
+size_t sr_gram_parts_bytes(int n, int h, int64_t B, int dtype);
+// G (B x ld(n), the weight dtype) and S (B x ld(n) int8): row-major factors the BF16 form reads
 hipError_t launch_sr_gram_sweeps(int dtype, const void* Gt, const void* Rt, const void* Dt, const void* St,
                                  int64_t ldb, const int32_t* c, int n, int h, int64_t B, float* parts, float* K,
-                                 hipStream_t st);
+                                 hipStream_t st, const void* G, const int8_t* S, int64_t ldn);
 // chol.hip: (K + shift I) y = scale * rhs in FP64 (blocked Cholesky, forward and back substitution)
 size_t sr_solve_ws_bytes(int64_t B);
 hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float* rhs, double scale, float* y,
