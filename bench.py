@@ -216,12 +216,13 @@ def _dominant_desc(call, made, H):
         if H.J is not None:
             return {"kernels": ["energy_dense_kernel", "sum_partials_kernel"], "src": ["energy.hip"],
                     "bound": "mfma", "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s", "metric": "tflops"}
-        return {"kernels": ["energy_csr_kernel<int, long>"], "src": ["energy.hip"], "bound": "hbm",
+        return {"kernels": ["energy_csr_bytes_kernel"], "src": ["energy.hip"], "bound": "hbm",
                 "peak": PEAK["hbm_gbs"], "unit": "GB/s", "metric": "gbs"}
     t = "bf16" if bf16 else "float"
     if call == "backward_sampled" and bf16:
-        return {"kernels": ["grad_out_kernel<bf16>", "mask_w2t_kernel", "bwd_hidden2_kernel", "bwd_weight2_kernel",
-                            "sum_rows_kernel"],
+        # with the sampler tables the masked copy of P^T is ready and the weight-gradient launch
+        # sums the bias partials, so these three are the call's launches
+        return {"kernels": ["grad_out_kernel<bf16>", "bwd_hidden2_kernel", "bwd_weight2_kernel"],
                 "src": ["gemm.hip", "gemm2.hip"], "bound": "mfma", "peak": mm, "unit": "TFLOP/s", "metric": "tflops"}
     if call == "backward_sampled":
         return {"kernels": [f"grad_out_kernel<{t}>", f"bwd_hidden_kernel<{t}>", f"bwd_weight_kernel<{t}, false>",

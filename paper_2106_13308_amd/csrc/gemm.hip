@@ -880,9 +880,19 @@ static hipError_t sr_gram_sampled_t(const vqmc_made& m, const int8_t* S, int64_t
   if ((e = hipGetLastError()) != hipSuccess) return e;
   grad_out_kernel<T><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(Zs, S, g.ldn, ones, m.n, B, G, Gt, St, g.ldB, db2_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
-                                                             g.ldB, db1_part, g.ldh);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (sizeof(T) == 2 && m.band) {
+    // BF16 with the sampler tables: the direct-to-LDS engine on their masked copy of P^T
+    int64_t zo, uo, po;
+    int nzt, nut;
+    sample_tables_layout(m.n, m.h, m.wdtype, &zo, &uo, &po, &nzt, &nut);
+    e = launch_bwd_hidden2(m, B, (const uint16_t*)G, (const uint16_t*)((const uint8_t*)m.band + po),
+                           (const uint16_t*)Rt, (uint16_t*)Dt, db1_part, st);
+  } else {
+    bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                               g.ldB, db1_part, g.ldh);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
   return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st, G, S, g.ldn);
 }
 

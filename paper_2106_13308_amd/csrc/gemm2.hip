@@ -388,6 +388,14 @@ hipError_t launch_mask_w2t(const vqmc_made& m, bf16_t* Pm, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_bwd_hidden2(const vqmc_made& m, int64_t B, const bf16_t* G, const bf16_t* Pm, const bf16_t* Rt,
+                              bf16_t* Dt, float* db1_part, hipStream_t st) {
+  const int64_t ldn = round_up(m.n, kPad), ldB = round_up(B, kPad), ldh = round_up(m.h, kPad);
+  bwd_hidden2_kernel<<<xcd_grid((int)(ldB / HB_BM), (m.h + HB_BN - 1) / HB_BN), 64 * HB_WGM * HB_WGN, 0, st>>>(
+      G, ldn, Pm, m.c, m.n, m.h, B, Rt, Dt, ldB, db1_part, ldh);
+  return hipGetLastError();
+}
+
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const bf16_t* G, const bf16_t* Gt,
                                      const bf16_t* St, const bf16_t* Rt, bf16_t* Dt, bf16_t* Pm,
                                      float* db1_part, int np1, const float* db2_part, int np2, float* dP, float* db1,

@@ -90,6 +90,9 @@ hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float*
                            void* ws, hipStream_t st);
 // gemm2.hip: BF16 backward products on the direct-to-LDS engine; Pm: h x ld(n) bf16 scratch
 size_t mask_w2t_bytes(int n, int h);
+// the hidden adjoint alone: Dt = [Rt > 0] (G Pm^T)^T, db1 partials per 64-sample tile (ld(h) each)
+hipError_t launch_bwd_hidden2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Pm,
+                              const uint16_t* Rt, uint16_t* Dt, float* db1_part, hipStream_t st);
 // db1_part (np1 rows of ld(h)) and db2_part (np2 rows of ld(n)) are summed into db1 and db2
 hipError_t launch_backward_products2(const vqmc_made& m, int64_t B, const uint16_t* G, const uint16_t* Gt,
                                      const uint16_t* St, const uint16_t* Rt, uint16_t* Dt, uint16_t* Pm,
