@@ -30,7 +30,9 @@ FLAGS = [
 
 # per-file flags: the TIM flip kernel keeps its MFMA results in ordinary VGPRs (its epilogue reads
 # every accumulator; in AGPRs each would need a copy, and the guarded K steps added more)
-FILE_FLAGS = {"tim.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "sr.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+FILE_FLAGS = {"tim.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "sr.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              # the panel keeps a row per lane in registers: every column loop must unroll
+              "chol.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def hipcc() -> str:

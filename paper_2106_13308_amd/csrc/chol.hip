@@ -10,10 +10,9 @@
 // factorisation, and a blocked back substitution L^T y = w.
 //
 // Launches per block column j (nb = padded B / 64 of them):
-//   chol_panel_kernel   nb - j workgroups: each factors the diagonal block A_jj, blocked by 16
-//                       columns (the same arithmetic in every workgroup, so the copies agree
-//                       bit for bit);
-//                       workgroup 0 stores L_jj and w_j, workgroup i > 0 solves its block row
+//   chol_factor_kernel  one wave: factors the diagonal block A_jj, a row per lane in registers,
+//                       with the forward substitution of w_j, and stores L_jj and w_j;
+//   chol_trsm_kernel    nb - j - 1 workgroups of one wave: workgroup i - 1 solves its block row
 //                       L_{j+i,j} = A_{j+i,j} L_jj^-T and updates w_{j+i} -= L_{j+i,j} w_j;
 //   chol_update_kernel  one workgroup per block (i, k), j < k <= i: A_ik -= L_ij L_kj^T.
 // and, from the last block column to the first,
@@ -42,156 +41,126 @@ __global__ void chol_init_kernel(const float* __restrict__ K, int64_t B, int64_t
   if (idx < ld) w[idx] = (idx < B) ? scale * (double)rhs[idx] : 0.0;
 }
 
-// The panel is blocked again inside, by 16 columns (SB): a sub-block's columns are factored one
-// after another by the lanes that own its rows (a row per lane, at most 16 dependent updates
-// per column, in registers), then everything to its right is brought up to date by a rank-16
-// update spread over all 256 threads.  The sequential part of a 64-column panel is thus four
-// short chains instead of one long one.
-constexpr int SB = 16;
+// The panel runs on one wave per workgroup.  Lane r holds row r of the 64 x 64 diagonal block
+// in registers and the block is factored right-looking, one column after another: column c's
+// diagonal entry comes from lane c, the lanes below scale their entry and write it to row c of
+// Lt (so that Lt[c][r] = L[r][c]), every lane reads the entries below c back as broadcasts and
+// updates its entries right of c.  The column loops are unrolled, so a row stays in registers,
+// and one wave needs no barriers: the only chain is the sequence of columns.  The block-row
+// solve X L^T = A_ij runs the same way, a row of X per lane, reading L from Lt.
+constexpr int CL = CB + 2;  // LDS row stride (doubles): 16-byte aligned rows
 
-// Lane-per-row solve of the 16 columns [s0, s0 + SB) of one row x against the factored
-// diagonal sub-block D (D[q][c], q >= c, of L): x[c] = (x[c] - sum_{c' < c} x[c'] D[c][c']) / D[c][c].
-__device__ inline void chol_row_solve16(double (&x)[SB], const double (*L)[CB + 1], int s0) {
+// 1 / sqrt(d): the hardware estimate refined by two Newton steps r <- r (3 - d r^2) / 2, each
+// roughly doubling the correct bits of the estimate (about 23 of them), so the result is accurate
+// to a few ulp of double precision; NaN for d < 0, +inf for d = 0.
+__device__ inline double chol_rsqrt(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  return r;
+}
+
+__device__ inline double chol_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// A[r0 .. r0 + 64)[c0 .. c0 + 64) into T (row-major, stride CL), one wave, coalesced by rows
+__device__ inline void chol_load_tile(const double* __restrict__ A, int64_t ld, int64_t r0, int64_t c0,
+                                      double (*T)[CL]) {
+  const int l = threadIdx.x;
+#pragma unroll 8
+  for (int r = 0; r < CB; ++r) T[r][l] = A[(r0 + r) * ld + c0 + l];
+}
+
+// x[c2] -= xc * row[c2] for c2 in (c, CB): the row read from LDS in groups of eight, one group
+// ahead of the multiply-adds, with compiler memory barriers between the groups so that the reads
+// of later columns are not hoisted (their registers would not fit).
+__device__ __attribute__((always_inline)) inline void chol_axpy_tail(double (&x)[CB], int c, double xc, const double* row) {
+  double v[8];
 #pragma unroll
-  for (int c = 0; c < SB; ++c) {
-    double v = x[c];
+  for (int e = 0; e < 8; ++e) v[e] = (c + 1 + e < CB) ? row[c + 1 + e] : 0.0;
 #pragma unroll
-    for (int q = 0; q < c; ++q) v = fma(-x[q], L[s0 + c][s0 + q], v);
-    x[c] = v / L[s0 + c][s0 + c];
+  for (int g0 = c + 1; g0 < CB; g0 += 8) {
+    double u[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) u[e] = (g0 + 8 + e < CB) ? row[g0 + 8 + e] : 0.0;
+    __asm__ __volatile__("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (g0 + e < CB) x[g0 + e] = fma(-xc, v[e], x[g0 + e]);
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = u[e];
   }
 }
 
-// Cholesky of the diagonal block F (lower triangle, in place) with the forward substitution of
-// w (in wc) folded in; 256 threads.
-__device__ inline void chol_factor_block(double (*F)[CB + 1], double* wc) {
-  const int t = threadIdx.x;
-  for (int s0 = 0; s0 < CB; s0 += SB) {
-    // the diagonal sub-block: one lane per row, its 16 entries factored column by column
-    if (t < SB) {
-      const int r = s0 + t;
-      for (int c = 0; c < SB; ++c) {
-        const int cc = s0 + c;
-        if (t == c) {
-          double v = F[cc][cc];
-          for (int q = s0; q < cc; ++q) v = fma(-F[cc][q], F[cc][q], v);
-          F[cc][cc] = sqrt(v);  // NaN if the block is not positive definite
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        if (t > c) {
-          double v = F[r][cc];
-          for (int q = s0; q < cc; ++q) v = fma(-F[r][q], F[cc][q], v);
-          F[r][cc] = v / F[cc][cc];
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-      }
-      // forward substitution of the sub-block's part of w
-      for (int c = 0; c < SB; ++c) {
-        const int cc = s0 + c;
-        if (t == c) {
-          double v = wc[cc];
-          for (int q = s0; q < cc; ++q) v = fma(-F[cc][q], wc[q], v);
-          wc[cc] = v / F[cc][cc];
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __syncthreads();
-    // rows below the sub-block: their 16 entries of these columns, a row per thread
-    const int r = s0 + SB + t;
-    if (t < CB - s0 - SB) {
-      double x[SB];
-#pragma unroll
-      for (int c = 0; c < SB; ++c) x[c] = F[r][s0 + c];
-      chol_row_solve16(x, F, s0);
-#pragma unroll
-      for (int c = 0; c < SB; ++c) F[r][s0 + c] = x[c];
-    }
-    __syncthreads();
-    // rank-16 update of the trailing lower triangle and of the rest of w
-    const int m = CB - s0 - SB;
-    for (int e = t; e < m * m; e += 256) {
-      const int rr = e / m, qq = e - rr * m;
-      if (qq <= rr) {
-        const int r2 = s0 + SB + rr, q2 = s0 + SB + qq;
-        double v = F[r2][q2];
-#pragma unroll
-        for (int c = 0; c < SB; ++c) v = fma(-F[r2][s0 + c], F[q2][s0 + c], v);
-        F[r2][q2] = v;
-      }
-    }
-    if (t < m) {
-      const int r2 = s0 + SB + t;
-      double v = wc[r2];
-#pragma unroll
-      for (int c = 0; c < SB; ++c) v = fma(-F[r2][s0 + c], wc[s0 + c], v);
-      wc[r2] = v;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int64_t ld, int j,
+// Diagonal block of column j (one workgroup): L_jj into A (lower triangle) and w_j' = L_jj^-1 w_j
+// into w.
+__global__ __launch_bounds__(CB) void chol_factor_kernel(double* __restrict__ A, int64_t ld, int j,
                                                          double* __restrict__ w) {
-  __shared__ double F[CB][CB + 1];
-  __shared__ double X[CB][CB + 1];
-  __shared__ double wc[CB];
-  const int t = threadIdx.x;
+  __shared__ __align__(16) double T[CB][CL];   // the loaded block
+  __shared__ __align__(16) double Lt[CB][CL];  // Lt[c][r] = L[r][c] (r >= c)
+  const int l = threadIdx.x;
   const int64_t j0 = (int64_t)j * CB;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & (CB - 1);
-    F[r][c] = A[(j0 + r) * ld + j0 + c];
-  }
-  if (t < CB) wc[t] = w[j0 + t];
-  __syncthreads();
-  chol_factor_block(F, wc);
-  if (blockIdx.x == 0) {
-    for (int e = t; e < CB * CB; e += 256) {
-      const int r = e >> 6, c = e & (CB - 1);
-      if (c <= r) A[(j0 + r) * ld + j0 + c] = F[r][c];
-    }
-    if (t < CB) w[j0 + t] = wc[t];
-    return;
-  }
-  // block row i0 = j0 + 64 blockIdx.x: X L_jj^T = A_ij, blocked by 16 columns like the factor
-  const int64_t i0 = j0 + (int64_t)blockIdx.x * CB;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & (CB - 1);
-    X[r][c] = A[(i0 + r) * ld + j0 + c];
-  }
-  __syncthreads();
-  for (int s0 = 0; s0 < CB; s0 += SB) {
-    if (t < CB) {
-      double x[SB];
+  chol_load_tile(A, ld, j0, j0, T);
+  double x[CB];
 #pragma unroll
-      for (int c = 0; c < SB; ++c) x[c] = X[t][s0 + c];
-      chol_row_solve16(x, F, s0);
+  for (int c = 0; c < CB; ++c) x[c] = T[l][c];
+  double wv = w[j0 + l];
 #pragma unroll
-      for (int c = 0; c < SB; ++c) X[t][s0 + c] = x[c];
-    }
-    __syncthreads();
-    const int m = CB - s0 - SB;  // X[:, later] -= X[:, sub-block] L[later, sub-block]^T
-    for (int e = t; e < CB * m; e += 256) {
-      const int r = e / m, q2 = s0 + SB + (e - (e / m) * m);
-      double v = X[r][q2];
+  for (int c = 0; c < CB; ++c) {
+    const double d = chol_bcast(x[c], c);
+    const double rs = chol_rsqrt(d);              // NaN if the block is not positive definite
+    x[c] = (l == c) ? d * rs : ((l > c) ? x[c] * rs : 0.0);
+    Lt[c][l] = x[c];
+    const double wc = chol_bcast(wv, c) * rs;     // w'_c
+    if (l == c) wv = wc;
+    else if (l > c) wv = fma(-x[c], wc, wv);
+    chol_axpy_tail(x, c, x[c], Lt[c]);
+  }
+  // rows coalesced from Lt
+#pragma unroll 8
+  for (int r = 0; r < CB; ++r)
+    if (l <= r) A[(j0 + r) * ld + j0 + l] = Lt[l][r];
+  w[j0 + l] = wv;
+}
+
+// Block row i of column j (workgroup i - 1, i > j): X L_jj^T = A_ij, a row of X per lane, with L_jj
+// read back from A into Lt; then w_i -= X w_j'.
+__global__ __launch_bounds__(CB) void chol_trsm_kernel(double* __restrict__ A, int64_t ld, int j,
+                                                       double* __restrict__ w) {
+  __shared__ __align__(16) double T[CB][CL];   // A_ij; X on the way out
+  __shared__ __align__(16) double Lt[CB][CL];  // Lt[c][r] = L[r][c]
+  __shared__ double rdl[CB];                   // 1 / L[c][c]
+  __shared__ double wl[CB];                    // w_j'
+  const int l = threadIdx.x;
+  const int64_t j0 = (int64_t)j * CB, i0 = j0 + (int64_t)(blockIdx.x + 1) * CB;
+  chol_load_tile(A, ld, j0, j0, T);
+#pragma unroll 8
+  for (int c = 0; c < CB; ++c) Lt[c][l] = (l >= c) ? T[l][c] : 0.0;
+  rdl[l] = 1.0 / T[l][l];
+  wl[l] = w[j0 + l];
+  chol_load_tile(A, ld, i0, j0, T);
+  double x[CB];
 #pragma unroll
-      for (int c = 0; c < SB; ++c) v = fma(-X[r][s0 + c], F[q2][s0 + c], v);
-      X[r][q2] = v;
-    }
-    __syncthreads();
+  for (int c = 0; c < CB; ++c) x[c] = T[l][c];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    x[c] *= rdl[c];
+    chol_axpy_tail(x, c, x[c], Lt[c]);
   }
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & (CB - 1);
-    A[(i0 + r) * ld + j0 + c] = X[r][c];
-  }
-  if (t < CB) {
-    double s = 0.0;  // (X w_j)[t], w_j the block's substituted values
-    for (int c = 0; c < CB; ++c) s = fma(X[t][c], wc[c], s);
-    w[i0 + t] -= s;
-  }
+  double sdot = 0.0;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) sdot = fma(x[c], wl[c], sdot);
+  w[i0 + l] -= sdot;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) T[c][l] = x[c];
+#pragma unroll 8
+  for (int r = 0; r < CB; ++r) A[(i0 + r) * ld + j0 + l] = T[l][r];
 }
 
 // Trailing update of block column j: A_ik -= L_ij L_kj^T for j < k <= i (the lower
@@ -278,10 +247,12 @@ hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int j = 0; j < nb; ++j) {
-    chol_panel_kernel<<<(unsigned)(nb - j), 256, 0, st>>>(A, ld, j, w);
+    chol_factor_kernel<<<1, CB, 0, st>>>(A, ld, j, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int m = nb - j - 1;
     if (m > 0) {
+      chol_trsm_kernel<<<(unsigned)m, CB, 0, st>>>(A, ld, j, w);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
       chol_update_kernel<<<(unsigned)(m * (m + 1) / 2), 256, 0, st>>>(A, ld, j);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
