@@ -10,11 +10,12 @@
 // factorisation, and a blocked back substitution L^T y = w.
 //
 // Launches per block column j (nb = padded B / 64 of them):
-//   chol_factor_kernel  one wave: factors the diagonal block A_jj, a row per lane in registers,
-//                       with the forward substitution of w_j, and stores L_jj and w_j;
 //   chol_trsm_kernel    nb - j - 1 workgroups of one wave: workgroup i - 1 solves its block row
 //                       L_{j+i,j} = A_{j+i,j} L_jj^-T and updates w_{j+i} -= L_{j+i,j} w_j;
-//   chol_update_kernel  one workgroup per block (i, k), j < k <= i: A_ik -= L_ij L_kj^T.
+//   chol_update_kernel  one workgroup per block (i, k), j < k <= i: A_ik -= L_ij L_kj^T; the one
+//                       on block (j + 1, j + 1) then factors it with one wave, a row per lane in
+//                       registers, with the forward substitution of w_{j+1}, and stores L and w
+//                       (the first diagonal block: chol_factor_kernel).
 // and, from the last block column to the first,
 //   chol_back_kernel    max(j, 1) workgroups: each solves L_jj^T y_j = w_j (workgroup 0
 //                       stores y_j), workgroup i < j updates w_i -= L_ji^T y_j.
@@ -98,15 +99,12 @@ __device__ __attribute__((always_inline)) inline void chol_axpy_tail(double (&x)
   }
 }
 
-// Diagonal block of column j (one workgroup): L_jj into A (lower triangle) and w_j' = L_jj^-1 w_j
-// into w.
-__global__ __launch_bounds__(CB) void chol_factor_kernel(double* __restrict__ A, int64_t ld, int j,
-                                                         double* __restrict__ w) {
-  __shared__ __align__(16) double T[CB][CL];   // the loaded block
-  __shared__ __align__(16) double Lt[CB][CL];  // Lt[c][r] = L[r][c] (r >= c)
+// Diagonal block of column j, one wave: the block in T (row-major, stride CL), L_jj back into A
+// (lower triangle) and w_j' = L_jj^-1 w_j into w.  Lt: scratch for the columns of L.
+__device__ __attribute__((always_inline)) inline void chol_factor_wave(const double (*T)[CL], double (*Lt)[CL],
+                                                                      double* __restrict__ A, int64_t ld,
+                                                                      int64_t j0, double* __restrict__ w) {
   const int l = threadIdx.x;
-  const int64_t j0 = (int64_t)j * CB;
-  chol_load_tile(A, ld, j0, j0, T);
   double x[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) x[c] = T[l][c];
@@ -127,6 +125,16 @@ __global__ __launch_bounds__(CB) void chol_factor_kernel(double* __restrict__ A,
   for (int r = 0; r < CB; ++r)
     if (l <= r) A[(j0 + r) * ld + j0 + l] = Lt[l][r];
   w[j0 + l] = wv;
+}
+
+// The first diagonal block (the later ones are factored by chol_update_kernel).
+__global__ __launch_bounds__(CB) void chol_factor_kernel(double* __restrict__ A, int64_t ld, int j,
+                                                         double* __restrict__ w) {
+  __shared__ __align__(16) double T[CB][CL];
+  __shared__ __align__(16) double Lt[CB][CL];
+  const int64_t j0 = (int64_t)j * CB;
+  chol_load_tile(A, ld, j0, j0, T);
+  chol_factor_wave(T, Lt, A, ld, j0, w);
 }
 
 // Block row i of column j (workgroup i - 1, i > j): X L_jj^T = A_ij, a row of X per lane, with L_jj
@@ -164,10 +172,13 @@ __global__ __launch_bounds__(CB) void chol_trsm_kernel(double* __restrict__ A, i
 }
 
 // Trailing update of block column j: A_ik -= L_ij L_kj^T for j < k <= i (the lower
-// triangle of the trailing matrix; blockIdx.x enumerates its blocks row by row).
-__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A, int64_t ld, int j) {
-  __shared__ double Li[CB][CB + 1];
-  __shared__ double Lk[CB][CB + 1];
+// triangle of the trailing matrix; blockIdx.x enumerates its blocks row by row).  Workgroup 0
+// updates the next diagonal block (j + 1, j + 1), keeps it in LDS and factors it with its first
+// wave (chol_factor_wave), so that the next block column starts with its block-row solves.
+__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A, int64_t ld, int j,
+                                                          double* __restrict__ w) {
+  __shared__ __align__(16) double Li[CB][CL];
+  __shared__ __align__(16) double Lk[CB][CL];
   int ii = 0, rem = blockIdx.x;
   while (rem > ii) {  // row ii holds ii + 1 blocks
     rem -= ii + 1;
@@ -193,8 +204,21 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
   }
+  if (blockIdx.x != 0) {
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] -= acc[a][b];
+    return;
+  }
+  // the next diagonal block: the updated values into LDS (Li is free once every thread has its
+  // products), then its factorisation by the first wave
+  double nv[4][4];
   for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] -= acc[a][b];
+    for (int b = 0; b < 4; ++b) nv[a][b] = A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] - acc[a][b];
+  __syncthreads();
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) Li[4 * ty + a][4 * tx + b] = nv[a][b];
+  __syncthreads();
+  if (t < CB) chol_factor_wave(Li, Lk, A, ld, i0, w);
 }
 
 // Back substitution of block j: L_jj^T y_j = w_j, then workgroup i < j applies
@@ -246,14 +270,15 @@ hipError_t launch_sr_solve(const float* K, int64_t B, double shift, const float*
   chol_init_kernel<<<(unsigned)((ld * ld + 255) / 256), 256, 0, st>>>(K, B, ld, shift, rhs, scale, A, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  chol_factor_kernel<<<1, CB, 0, st>>>(A, ld, 0, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int j = 0; j < nb; ++j) {
-    chol_factor_kernel<<<1, CB, 0, st>>>(A, ld, j, w);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // block column j: its diagonal block is factored (above, or by the previous update)
     const int m = nb - j - 1;
     if (m > 0) {
       chol_trsm_kernel<<<(unsigned)m, CB, 0, st>>>(A, ld, j, w);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      chol_update_kernel<<<(unsigned)(m * (m + 1) / 2), 256, 0, st>>>(A, ld, j);
+      chol_update_kernel<<<(unsigned)(m * (m + 1) / 2), 256, 0, st>>>(A, ld, j, w);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
