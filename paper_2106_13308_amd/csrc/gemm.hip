@@ -824,6 +824,23 @@ size_t sr_gram_ws_bytes(int n, int h, int64_t B, int dtype) {
   return sr_extra_offset(n, h, B, dtype) + (size_t)round_up(B * 4, 256) + sr_gram_parts_bytes(n, h, B, dtype);
 }
 
+// The hidden adjoint of the Gram's factors: BF16 with the sampler tables on the direct-to-LDS
+// engine (their masked copy of P^T), else the register-staged one.
+template <typename T>
+static hipError_t sr_hidden_adjoint(const vqmc_made& m, int64_t B, const Geom& g, const T* G, const T* Rt, T* Dt,
+                                    float* db1_part, hipStream_t st) {
+  if (sizeof(T) == 2 && m.band) {
+    int64_t zo, uo, po;
+    int nzt, nut;
+    sample_tables_layout(m.n, m.h, m.wdtype, &zo, &uo, &po, &nzt, &nut);
+    return launch_bwd_hidden2(m, B, (const uint16_t*)G, (const uint16_t*)((const uint8_t*)m.band + po),
+                              (const uint16_t*)Rt, (uint16_t*)Dt, db1_part, st);
+  }
+  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
+                                                             g.ldB, db1_part, g.ldh);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, float* K, void* ws, hipStream_t st) {
   const Geom g = geom(m.n, m.h, B);
@@ -851,9 +868,7 @@ static hipError_t sr_gram_t(const vqmc_made& m, const int8_t* S, int64_t B, floa
       R, g.ldh, (const T*)m.P, m.b2, m.c, m.n, m.h, B, (int8_t*)S, g.ldn, g.ldn, lp_part, nullptr, ones, G, Gt,
       St, g.ldB, db2_part, 0, 0, 0, 0, 0, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
-                                                             g.ldB, db1_part, g.ldh);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = sr_hidden_adjoint<T>(m, B, g, G, Rt, Dt, db1_part, st)) != hipSuccess) return e;
   return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st, G, S, g.ldn);
 }
 
@@ -880,19 +895,7 @@ static hipError_t sr_gram_sampled_t(const vqmc_made& m, const int8_t* S, int64_t
   if ((e = hipGetLastError()) != hipSuccess) return e;
   grad_out_kernel<T><<<dim3(g.nt_o, g.mt_o), 256, 0, st>>>(Zs, S, g.ldn, ones, m.n, B, G, Gt, St, g.ldB, db2_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (sizeof(T) == 2 && m.band) {
-    // BF16 with the sampler tables: the direct-to-LDS engine on their masked copy of P^T
-    int64_t zo, uo, po;
-    int nzt, nut;
-    sample_tables_layout(m.n, m.h, m.wdtype, &zo, &uo, &po, &nzt, &nut);
-    e = launch_bwd_hidden2(m, B, (const uint16_t*)G, (const uint16_t*)((const uint8_t*)m.band + po),
-                           (const uint16_t*)Rt, (uint16_t*)Dt, db1_part, st);
-  } else {
-    bwd_hidden_kernel<T><<<dim3(g.nt_h, g.mt_h), 256, 0, st>>>(G, g.ldn, (const T*)m.Pt, m.c, m.n, m.h, B, Rt, Dt,
-                                                               g.ldB, db1_part, g.ldh);
-    e = hipGetLastError();
-  }
-  if (e != hipSuccess) return e;
+  if ((e = sr_hidden_adjoint<T>(m, B, g, G, Rt, Dt, db1_part, st)) != hipSuccess) return e;
   return launch_sr_gram_sweeps(m.wdtype, Gt, Rt, Dt, St, g.ldB, m.c, m.n, m.h, B, parts, K, st, G, S, g.ldn);
 }
 

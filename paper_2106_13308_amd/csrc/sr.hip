@@ -229,30 +229,37 @@ __global__ void sr_limits_kernel(const int32_t* __restrict__ c, int n, int h, in
 // segment, seg_choff[j] = first 16-site chunk (SG_C sites) of segment j in the padded copy
 // (seg_choff[nseg] = chunks in all), tab[0] = nseg.  Then sr_seg_inv_kernel: inv[p] = site at
 // padded position p, or -1.
-constexpr int SG_T = 256;
+constexpr int SG_T = 1024;
 constexpr int SG_C = 16;  // sites per chunk of the padded copies (the K of one MFMA)
+// exclusive prefix sum over the workgroup: within each wave by shuffles, then the waves' totals
+// through LDS (sh: SG_T / 64 ints); total = the workgroup's sum
 __device__ inline int block_excl_scan(int v, int* sh, int& total) {
-  // Hillis-Steele inclusive scan over the block in LDS, then exclusive
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < SG_T; o <<= 1) {
-    const int x = (t >= o) ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  total = sh[SG_T - 1];
-  const int incl = sh[t];
+  if (lane == 63) sh[wv] = x;
   __syncthreads();
-  return incl - v;
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < SG_T / 64; ++q) {
+    const int sq = sh[q];
+    off += (q < wv) ? sq : 0;
+    tot += sq;
+  }
+  total = tot;
+  __syncthreads();
+  return off + x - v;
 }
 
 __global__ __launch_bounds__(SG_T) void sr_seg_prep_kernel(const int32_t* __restrict__ c, int n,
                                                            int32_t* __restrict__ seg_start,
                                                            int32_t* __restrict__ seg_gamma,
                                                            int32_t* __restrict__ seg_choff, int32_t* __restrict__ tab) {
-  __shared__ int sh[SG_T];
+  __shared__ int sh[SG_T / 64];
   const int t = threadIdx.x;
   int base = 0;
   for (int d0 = 0; d0 < n; d0 += SG_T) {
@@ -309,56 +316,64 @@ __global__ void sr_seg_inv_kernel(const int32_t* __restrict__ seg_start, const i
 
 // Segment-padded copies, chunk-major (the SG_C positions of chunk q of sample b at
 // (q B + b) SG_C, so that one MFMA operand's 16 samples are 512 contiguous bytes):
-// Gs = G[b][inv[p]], Ss = s_b,inv[p] (BF16 +-1), 0 where inv[p] < 0.  sr_seg_pack_row_kernel:
-// one workgroup per sample, its rows of G and S staged in LDS (n <= SG_ROW_MAX);
-// sr_seg_pack_kernel otherwise.  Eight positions per thread.
+// Gs = G[b][inv[p]], Ss = s_b,inv[p] (BF16 +-1), 0 where inv[p] < 0.
 __device__ inline int64_t seg_pos(int64_t b, int64_t p, int64_t B) { return ((p / SG_C) * B + b) * SG_C + p % SG_C; }
-__global__ __launch_bounds__(256) void sr_seg_pack_kernel(const bf16_t* __restrict__ G, const int8_t* __restrict__ S,
-                                                          int64_t ldn, const int32_t* __restrict__ inv, int64_t ldk,
-                                                          int64_t B, bf16_t* __restrict__ Gs, bf16_t* __restrict__ Ss) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t per_row = ldk / 8;
-  const int64_t b = i / per_row, p0 = (i - b * per_row) * 8;
-  if (b >= B) return;
-  bf16_t gv[8], sv[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int d = inv[p0 + e];
-    gv[e] = d >= 0 ? G[b * ldn + d] : (bf16_t)0;
-    const int sgn = d >= 0 ? S[b * ldn + d] : 0;
-    sv[e] = sgn > 0 ? (bf16_t)0x3F80 : (sgn < 0 ? (bf16_t)0xBF80 : (bf16_t)0);
-  }
-  *(uint4*)(Gs + seg_pos(b, p0, B)) = *(const uint4*)gv;
-  *(uint4*)(Ss + seg_pos(b, p0, B)) = *(const uint4*)sv;
-}
-
-constexpr int SG_ROW_MAX = 20480;
-__global__ __launch_bounds__(256) void sr_seg_pack_row_kernel(const bf16_t* __restrict__ G,
-                                                              const int8_t* __restrict__ S, int64_t ldn, int n,
-                                                              const int32_t* __restrict__ inv, int64_t ldk, int64_t B,
-                                                              bf16_t* __restrict__ Gs, bf16_t* __restrict__ Ss) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t row_smem[];
-  bf16_t* gl = (bf16_t*)row_smem;             // [round_up(n, 8)]
-  int8_t* sl = (int8_t*)(gl + round_up(n, 16));  // [round_up(n, 16)]
-  const int64_t b = blockIdx.x;
+// The same copies by tiles of 16 samples x 64 chunks: the sites the tile's chunks hold (a run of
+// at most 64 SG_C of them, the segments being runs) are staged in LDS for the 16 samples, and
+// each chunk's 16 samples are written as one contiguous 512-byte run.  Workgroups past the last
+// chunk return.
+constexpr int SGP_S = 16, SGP_Q = 64, SGP_SPAN = SGP_Q * SG_C;
+__global__ __launch_bounds__(256) void sr_seg_pack_tile_kernel(const bf16_t* __restrict__ G,
+                                                               const int8_t* __restrict__ S, int64_t ldn,
+                                                               const int32_t* __restrict__ inv,
+                                                               const int32_t* __restrict__ seg_choff,
+                                                               const int32_t* __restrict__ tab, int64_t B,
+                                                               bf16_t* __restrict__ Gs, bf16_t* __restrict__ Ss) {
+  __shared__ __align__(16) bf16_t gl[SGP_S][SGP_SPAN + 16];
+  __shared__ __align__(16) int8_t sl[SGP_S][SGP_SPAN + 32];
   const int t = threadIdx.x;
-  const int n8 = (int)round_up(n, 16);
-  for (int d = 8 * t; d < n8; d += 8 * 256) *(uint4*)(gl + d) = *(const uint4*)(G + b * ldn + d);
-  for (int d = 16 * t; d < n8; d += 16 * 256) *(uint4*)(sl + d) = *(const uint4*)(S + b * ldn + d);
+  const int nch = seg_choff[tab[0]];
+  const int q0 = blockIdx.x * SGP_Q;
+  if (q0 >= nch) return;
+  const int q1 = min(q0 + SGP_Q, nch);
+  const int64_t b0 = (int64_t)blockIdx.y * SGP_S;
+  // sites of the tile: from the first position (a chunk's first position always holds a site) to
+  // the last valid one (a chunk holds at least one site)
+  const int s_lo = inv[(int64_t)q0 * SG_C];
+  int p = q1 * SG_C - 1;
+  while (inv[p] < 0) --p;
+  const int s_hi = inv[p];  // s_hi - s_lo < SGP_SPAN
+  // 16-byte pieces from 16-byte boundaries (rows of ld(n) elements: the last piece stays inside)
+  const int ga = s_lo & ~7, sa = s_lo & ~15;
+  const int gpieces = (s_hi - ga) / 8 + 1, spieces = (s_hi - sa) / 16 + 1;
+  for (int e = t; e < SGP_S * gpieces; e += 256) {
+    const int r = e / gpieces, k = e - r * gpieces;
+    const int64_t b = b0 + r;
+    *(uint4*)&gl[r][8 * k] = (b < B) ? *(const uint4*)(G + b * ldn + ga + 8 * k) : make_uint4(0, 0, 0, 0);
+  }
+  for (int e = t; e < SGP_S * spieces; e += 256) {
+    const int r = e / spieces, k = e - r * spieces;
+    const int64_t b = b0 + r;
+    *(uint4*)&sl[r][16 * k] = (b < B) ? *(const uint4*)(S + b * ldn + sa + 16 * k) : make_uint4(0, 0, 0, 0);
+  }
   __syncthreads();
-  for (int64_t p0 = 8 * t; p0 < ldk; p0 += 8 * 256) {
-    const int4 i0 = *(const int4*)(inv + p0), i1 = *(const int4*)(inv + p0 + 4);
-    const int iv[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+  // thread t: chunk q0 + (t / 32) + 8 i, sample t / 2 % 16, half t % 2 (eight positions)
+  const int r = (t >> 1) & (SGP_S - 1), h = t & 1;
+  const int64_t b = b0 + r;
+  for (int q = q0 + (t >> 5); q < q1; q += 8) {
+    const int64_t pp = (int64_t)q * SG_C + 8 * h;
     bf16_t gv[8], sv[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int d = iv[e];
-      gv[e] = d >= 0 ? gl[d] : (bf16_t)0;
-      const int sg = d >= 0 ? sl[d] : 0;
+      const int d = inv[pp + e];
+      gv[e] = d >= 0 ? gl[r][d - ga] : (bf16_t)0;
+      const int sg = d >= 0 ? sl[r][d - sa] : 0;
       sv[e] = sg > 0 ? (bf16_t)0x3F80 : (sg < 0 ? (bf16_t)0xBF80 : (bf16_t)0);
     }
-    *(uint4*)(Gs + seg_pos(b, p0, B)) = *(const uint4*)gv;
-    *(uint4*)(Ss + seg_pos(b, p0, B)) = *(const uint4*)sv;
+    if (b < B) {
+      *(uint4*)(Gs + seg_pos(b, pp, B)) = *(const uint4*)gv;
+      *(uint4*)(Ss + seg_pos(b, pp, B)) = *(const uint4*)sv;
+    }
   }
 }
 
@@ -589,13 +604,8 @@ static hipError_t launch_sr_gram_mfma(const bf16_t* G, const int8_t* S, int64_t 
   const int64_t ninv = std::max<int64_t>(n, L.ldk);
   sr_seg_inv_kernel<<<(unsigned)((ninv + 255) / 256), 256, 0, st>>>(start, gamma, choff, tab, n, L.ldk, inv, cinfo);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (n <= SG_ROW_MAX) {
-    const size_t smem = (size_t)round_up(n, 16) * 3;
-    sr_seg_pack_row_kernel<<<(unsigned)B, 256, smem, st>>>(G, S, ldn, n, inv, L.ldk, B, Gs, Ss);
-  } else {
-    const int64_t threads = B * (L.ldk / 8);
-    sr_seg_pack_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(G, S, ldn, inv, L.ldk, B, Gs, Ss);
-  }
+  const dim3 pgrid((unsigned)((L.kpmax + SGP_Q - 1) / SGP_Q), (unsigned)((B + SGP_S - 1) / SGP_S));
+  sr_seg_pack_tile_kernel<<<pgrid, 256, 0, st>>>(G, S, ldn, inv, choff, tab, B, Gs, Ss);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nt = (int)((B + GR_T - 1) / GR_T);
   const int64_t pairs = (int64_t)nt * (nt + 1) / 2;
