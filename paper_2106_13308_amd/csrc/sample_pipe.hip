@@ -414,7 +414,8 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (dblk + 4 * q + e < n) lp_part += log_sigmoid(zv[e]);
-      if (Zs && b0 + s < B) *(float4*)(Zs + (b0 + s) * lds + dblk + 4 * q) = z4;
+      // s*z is read again only by the backward, after the energies: a streaming store
+      if (Zs && b0 + s < B) store_nt(Zs + (b0 + s) * lds + dblk + 4 * q, __builtin_bit_cast(uint4, z4));
     };
     // ---- work items.  Push tiles: block b pushes block b-1's spins into the 16-unit tiles
     // hw, hw + SP_NHW, ... of the units [f_b & ~15, h).  Logit tiles: block b adds tiles
