@@ -50,6 +50,9 @@ __global__ void chol_init_kernel(const float* __restrict__ K, int64_t B, int64_t
 // and one wave needs no barriers: the only chain is the sequence of columns.  The block-row
 // solve X L^T = A_ij runs the same way, a row of X per lane, reading L from Lt.
 constexpr int CL = CB + 2;  // LDS row stride (doubles): 16-byte aligned rows
+// groups of eight LDS reads in flight ahead of the multiply-adds of the column loops (depths of one to
+// four give the same time within 1 %)
+constexpr int CHOL_PF = 2;
 
 // 1 / sqrt(d): the hardware estimate refined by two Newton steps r <- r (3 - d r^2) / 2, each
 // roughly doubling the correct bits of the estimate (about 23 of them), so the result is accurate
@@ -67,35 +70,43 @@ __device__ inline double chol_bcast(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// A[r0 .. r0 + 64)[c0 .. c0 + 64) into T (row-major, stride CL), one wave, coalesced by rows
+// A[r0 .. r0 + 64)[c0 .. c0 + 64) into T (row-major, stride CL), one wave: two rows per 16-byte
+// load instruction, all 32 loads issued before the first store to LDS (one memory round trip)
 __device__ inline void chol_load_tile(const double* __restrict__ A, int64_t ld, int64_t r0, int64_t c0,
                                       double (*T)[CL]) {
-  const int l = threadIdx.x;
-#pragma unroll 8
-  for (int r = 0; r < CB; ++r) T[r][l] = A[(r0 + r) * ld + c0 + l];
+  const int l = threadIdx.x, rh = l >> 5, cq = 2 * (l & 31);
+  double2 v[CB / 2];
+#pragma unroll
+  for (int i = 0; i < CB / 2; ++i) v[i] = *(const double2*)(A + (r0 + 2 * i + rh) * ld + c0 + cq);
+#pragma unroll
+  for (int i = 0; i < CB / 2; ++i) *(double2*)&T[2 * i + rh][cq] = v[i];
 }
 
-// x[c2] -= xc * row[c2] for c2 in (c, CB): the row read from LDS in groups of eight, one group
-// ahead of the multiply-adds, with compiler memory barriers between the groups so that the reads
-// of later columns are not hoisted (their registers would not fit).
+// x[c2] -= xc * row[c2] for c2 in (c, CB): the row read from LDS in groups of eight, PF groups
+// ahead of the multiply-adds (a ring of PF + 1 groups in registers), with compiler memory barriers
+// between the groups so that the reads of later groups are not hoisted further (their registers
+// would not fit).
+template <int PF>
 __device__ __attribute__((always_inline)) inline void chol_axpy_tail(double (&x)[CB], int c, double xc, const double* row) {
-  double v[8];
+  constexpr int G = 8;
+  double v[PF + 1][G];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (c + 1 + e < CB) ? row[c + 1 + e] : 0.0;
+  for (int q = 0; q < PF; ++q)
 #pragma unroll
-  for (int g0 = c + 1; g0 < CB; g0 += 8) {
-    double u[8];
+    for (int e = 0; e < G; ++e) v[q][e] = (c + 1 + G * q + e < CB) ? row[c + 1 + G * q + e] : 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) u[e] = (g0 + 8 + e < CB) ? row[g0 + 8 + e] : 0.0;
+  for (int q = 0; c + 1 + G * q < CB; ++q) {
+    const int g0 = c + 1 + G * q, gn = g0 + G * PF;
+#pragma unroll
+    for (int e = 0; e < G; ++e)
+      if (gn + e < CB) v[(q + PF) % (PF + 1)][e] = row[gn + e];
     __asm__ __volatile__("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (g0 + e < CB) x[g0 + e] = fma(-xc, v[e], x[g0 + e]);
+    for (int e = 0; e < G; ++e)
+      if (g0 + e < CB) x[g0 + e] = fma(-xc, v[q % (PF + 1)][e], x[g0 + e]);
     __asm__ __volatile__("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = u[e];
   }
 }
 
@@ -118,7 +129,7 @@ __device__ __attribute__((always_inline)) inline void chol_factor_wave(const dou
     const double wc = chol_bcast(wv, c) * rs;     // w'_c
     if (l == c) wv = wc;
     else if (l > c) wv = fma(-x[c], wc, wv);
-    chol_axpy_tail(x, c, x[c], Lt[c]);
+    chol_axpy_tail<CHOL_PF>(x, c, x[c], Lt[c]);
   }
   // rows coalesced from Lt
 #pragma unroll 8
@@ -159,7 +170,7 @@ __global__ __launch_bounds__(CB) void chol_trsm_kernel(double* __restrict__ A, i
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
     x[c] *= rdl[c];
-    chol_axpy_tail(x, c, x[c], Lt[c]);
+    chol_axpy_tail<CHOL_PF>(x, c, x[c], Lt[c]);
   }
   double sdot = 0.0;
 #pragma unroll
@@ -187,33 +198,59 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A
   const int kk = rem;
   const int64_t j0 = (int64_t)j * CB, i0 = j0 + (int64_t)(ii + 1) * CB, k0 = j0 + (int64_t)(kk + 1) * CB;
   const int t = threadIdx.x;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & (CB - 1);
-    Li[r][c] = A[(i0 + r) * ld + j0 + c];
-    Lk[r][c] = A[(k0 + r) * ld + j0 + c];
+  const int tx = t & 15, ty = t >> 4;
+  // both blocks with 16-byte loads and the block being updated, all issued before the first
+  // store to LDS (one memory round trip); the two blocks are stored transposed (Li[c][r] =
+  // L_ij[r][c]), so that the products read four consecutive rows of a column at once
+  const int rq = t >> 5, cq = 2 * (t & 31);  // rows rq + 8 i, columns cq, cq + 1
+  double2 vi[CB / 8], vk[CB / 8];
+#pragma unroll
+  for (int i = 0; i < CB / 8; ++i) {
+    vi[i] = *(const double2*)(A + (i0 + rq + 8 * i) * ld + j0 + cq);
+    vk[i] = *(const double2*)(A + (k0 + rq + 8 * i) * ld + j0 + cq);
+  }
+  double av0[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const double4 q = *(const double4*)(A + (i0 + 4 * ty + a) * ld + k0 + 4 * tx);
+    av0[a][0] = q.x; av0[a][1] = q.y; av0[a][2] = q.z; av0[a][3] = q.w;
+  }
+#pragma unroll
+  for (int i = 0; i < CB / 8; ++i) {
+    Li[cq][rq + 8 * i] = vi[i].x;
+    Li[cq + 1][rq + 8 * i] = vi[i].y;
+    Lk[cq][rq + 8 * i] = vk[i].x;
+    Lk[cq + 1][rq + 8 * i] = vk[i].y;
   }
   __syncthreads();
-  const int tx = t & 15, ty = t >> 4;
   double acc[4][4];
+#pragma unroll
   for (int a = 0; a < 4; ++a)
+#pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
   for (int c = 0; c < CB; ++c) {
-    double av[4], bv[4];
-    for (int a = 0; a < 4; ++a) av[a] = Li[4 * ty + a][c];
-    for (int b = 0; b < 4; ++b) bv[b] = Lk[4 * tx + b][c];
+    const double2 a01 = *(const double2*)&Li[c][4 * ty], a23 = *(const double2*)&Li[c][4 * ty + 2];
+    const double2 b01 = *(const double2*)&Lk[c][4 * tx], b23 = *(const double2*)&Lk[c][4 * tx + 2];
+    const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
   }
+  double nv[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) nv[a][b] = av0[a][b] - acc[a][b];
   if (blockIdx.x != 0) {
+#pragma unroll
     for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] -= acc[a][b];
+      *(double4*)(A + (i0 + 4 * ty + a) * ld + k0 + 4 * tx) = make_double4(nv[a][0], nv[a][1], nv[a][2], nv[a][3]);
     return;
   }
   // the next diagonal block: the updated values into LDS (Li is free once every thread has its
   // products), then its factorisation by the first wave
-  double nv[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) nv[a][b] = A[(i0 + 4 * ty + a) * ld + k0 + 4 * tx + b] - acc[a][b];
   __syncthreads();
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) Li[4 * ty + a][4 * tx + b] = nv[a][b];
