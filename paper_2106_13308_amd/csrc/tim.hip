@@ -41,8 +41,9 @@
 namespace vqmc {
 
 constexpr int TIM_BM = 64;       // flipped sites per workgroup
-constexpr int TIM_BN = 64;       // sites d per block of the sweep, 16 per wave
-constexpr int TIM_RENORM = 64;   // site blocks between renormalisations of the running products
+constexpr int TIM_BN = 128;      // sites d per block of the sweep: 32 per wave, two groups of 16
+constexpr int TIM_RENORM = 32;   // site blocks between renormalisations of the running products
+                                 // (64 factors in (1/2, 2) each: far inside the float range)
 constexpr float TIM_L2E = 1.4426950408889634f;   // log2(e)
 constexpr float TIM_LN2 = 0.6931471805599453f;   // ln(2)
 
@@ -216,36 +217,51 @@ __global__ __launch_bounds__(256) void tim_flip_kernel(
     const tim_rsrc_t rs = tim_rsrc(P2, (uint32_t)((int64_t)n * ldh * 2));
     const bf16_t* arow = (const bf16_t*)dR + (size_t)gcol * ldr + 8 * grow;
     auto kend = [&](int qd) -> int {   // wave-uniform K end of block qd (kbase when it is past n)
-      const int dw = qd * TIM_BN + 16 * wv;
+      const int dw = qd * TIM_BN + 32 * wv;
       if (dw >= n) return kbase;
-      return min((int)round_up(c[min(dw + 15, n - 1)], 32), kwmax);
+      return min((int)round_up(c[min(dw + 31, n - 1)], 32), kwmax);
     };
-    uint4 bfr[NF];
-    int nk = (kend(q) - kbase) / 32;
-    int dl = min(q * TIM_BN + 16 * wv + gcol, n - 1);
-    int s_raw = Sb[dl];
-    float z_raw = Zb[dl];
-    uint32_t roff = (uint32_t)(((int64_t)dl * ldh + kbase + 8 * grow) * 2);
+    // the sweep starts at the site block holding the first flipped site (sites d <= i add 0)
+    const int qd0 = i0 / TIM_BN;
+    uint4 bfr[2][NF];  // the two column groups' B fragments
+    int nk = (kend(qd0) - kbase) / 32;
+    int dl[2], s_raw[2];
+    float z_raw[2];
+    uint32_t roff[2];
+    auto operands = [&](int dw) {  // spins, logits and B row offsets of the wave's 32 columns from dw
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        dl[g] = min(dw + 16 * g + gcol, n - 1);
+        s_raw[g] = Sb[dl[g]];
+        z_raw[g] = Zb[dl[g]];
+        roff[g] = (uint32_t)(((int64_t)dl[g] * ldh + kbase + 8 * grow) * 2);
+      }
+    };
+    operands(qd0 * TIM_BN + 32 * wv);
     // B fragments in groups of four behind a uniform branch: the out-of-range loads still pass
     // through the address unit, so only the last group of a block carries any
     auto fetch_b = [&](int need) {
 #pragma unroll
-      for (int g = 0; g < NF / 4; ++g) {
-        if (4 * g < need) {
+      for (int g4 = 0; g4 < NF / 4; ++g4) {
+        if (4 * g4 < need) {
 #pragma unroll
-          for (int f = 4 * g; f < 4 * g + 4; ++f) bfr[f] = tim_ld16(rs, f < need ? roff : TIM_OOB, 64u * f);
+          for (int f = 4 * g4; f < 4 * g4 + 4; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) bfr[g][f] = tim_ld16(rs, f < need ? roff[g] : TIM_OOB, 64u * f);
         }
       }
     };
     fetch_b(nk);
-    for (int qd = q;; ++qd) {
-      const int dw = qd * TIM_BN + 16 * wv;
+    for (int qd = qd0;; ++qd) {
+      const int dw = qd * TIM_BN + 32 * wv;
       if (dw >= n) break;
       const int nk_next = (kend(qd + 1) - kbase) / 32;
-      floatx4_t acc[4];
+      floatx4_t acc[2][4];
       if (nk <= 0) {
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int mi = 0; mi < 4; ++mi) acc[g][mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
       } else {
         constexpr int LDR = tim_ldr<bf16_t>(32 * NF);   // == ldr: every LDS offset below is an immediate
         uint4 a[2][4];
@@ -261,70 +277,79 @@ __global__ __launch_bounds__(256) void tim_flip_kernel(
               for (int mi = 0; mi < 4; ++mi)
                 a[(f + 1) & 1][mi] = *(const uint4*)(arow + 16 * mi * LDR + 32 * (f + 1));
             }
-            const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bfr[f]);
+            // each A fragment serves both column groups: half the LDS reads per product
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
-              acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  __builtin_bit_cast(bf16x8_t, a[f & 1][mi]), bf,
-                  f == 0 ? (floatx4_t){0.f, 0.f, 0.f, 0.f} : acc[mi], 0, 0, 0);
+            for (int g = 0; g < 2; ++g) {
+              const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, bfr[g][f]);
+#pragma unroll
+              for (int mi = 0; mi < 4; ++mi)
+                acc[g][mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, a[f & 1][mi]), bf,
+                    f == 0 ? (floatx4_t){0.f, 0.f, 0.f, 0.f} : acc[g][mi], 0, 0, 0);
+            }
           }
         }
       }
-      const bool valid = dw + gcol < n;
-      const float sd = valid ? (float)s_raw : 0.f;
-      const float td = valid ? sd * z_raw : 0.f;
-      const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
-      const float rd = __builtin_amdgcn_rcpf(1.f + pd);
-      const float nmt = -0.5f * (td - fabsf(td));
+      float sd[2], td[2], pd[2], rd[2], nmt[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const bool valid = dw + 16 * g + gcol < n;
+        sd[g] = valid ? (float)s_raw[g] : 0.f;
+        td[g] = valid ? sd[g] * z_raw[g] : 0.f;
+        pd[g] = __builtin_amdgcn_exp2f(-fabsf(td[g]) * TIM_L2E);
+        rd[g] = __builtin_amdgcn_rcpf(1.f + pd[g]);
+        nmt[g] = -0.5f * (td[g] - fabsf(td[g]));
+      }
       // the next block's operands
-      dl = min(dw + TIM_BN + gcol, n - 1);
-      s_raw = Sb[dl];
-      z_raw = Zb[dl];
-      roff = (uint32_t)(((int64_t)dl * ldh + kbase + 8 * grow) * 2);
+      operands(dw + TIM_BN);
       fetch_b(nk_next);
-      tim_epilogue(acc, sd, td, pd, rd, nmt, lin, prod);
+#pragma unroll
+      for (int g = 0; g < 2; ++g) tim_epilogue(acc[g], sd[g], td[g], pd[g], rd[g], nmt[g], lin, prod);
       renorm();
       nk = nk_next;
     }
   } else {
-    for (int qd = q; qd < nbd; ++qd) {
-      const int dw = qd * TIM_BN + 16 * wv;   // first column of this wave
-      if (dw >= n) break;                      // wave-uniform: nothing left for this wave
-      const int d = dw + gcol;
-      const bool valid = d < n;
-      const float sd = valid ? (float)Sb[d] : 0.f;
-      const float td = valid ? sd * Zb[d] : 0.f;
-      const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
-      const float rd = __builtin_amdgcn_rcpf(1.f + pd);
-      const float nmt = -0.5f * (td - fabsf(td));
-      // K end of the wave: the units feeding its last valid column
-      const int kd = min((int)round_up(__builtin_amdgcn_readfirstlane(c[min(dw + 15, n - 1)]), KS), kwmax);
-      floatx4_t acc[4];
+    for (int qd = i0 / TIM_BN; qd < nbd; ++qd) {
+      const int dw0 = qd * TIM_BN + 32 * wv;   // first column of this wave
+      if (dw0 >= n) break;                      // wave-uniform: nothing left for this wave
+      for (int g = 0; g < 2; ++g) {           // two groups of 16 columns
+        const int dw = dw0 + 16 * g;
+        const int d = dw + gcol;
+        const bool valid = d < n;
+        const float sd = valid ? (float)Sb[d] : 0.f;
+        const float td = valid ? sd * Zb[d] : 0.f;
+        const float pd = __builtin_amdgcn_exp2f(-fabsf(td) * TIM_L2E);
+        const float rd = __builtin_amdgcn_rcpf(1.f + pd);
+        const float nmt = -0.5f * (td - fabsf(td));
+        // K end of the wave: the units feeding its last valid column
+        const int kd = min((int)round_up(__builtin_amdgcn_readfirstlane(c[min(dw + 15, n - 1)]), KS), kwmax);
+        floatx4_t acc[4];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
-      const T* brow = P2 + (int64_t)(valid ? d : n - 1) * ldh;
-      if constexpr (sizeof(T) == 2) {
-        for (int k = kbase; k < kd; k += KS) {
-          const int kc = k + 8 * grow;
-          const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, *(const uint4*)(brow + kc));
+        for (int mi = 0; mi < 4; ++mi) acc[mi] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+        const T* brow = P2 + (int64_t)(valid ? d : n - 1) * ldh;
+        if constexpr (sizeof(T) == 2) {
+          for (int k = kbase; k < kd; k += KS) {
+            const int kc = k + 8 * grow;
+            const bf16x8_t bf = __builtin_bit_cast(bf16x8_t, *(const uint4*)(brow + kc));
 #pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const uint4 av = *(const uint4*)(dR + (size_t)(16 * mi + gcol) * ldr + (kc - kbase));
-            acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av), bf, acc[mi], 0, 0, 0);
+            for (int mi = 0; mi < 4; ++mi) {
+              const uint4 av = *(const uint4*)(dR + (size_t)(16 * mi + gcol) * ldr + (kc - kbase));
+              acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av), bf, acc[mi], 0, 0, 0);
+            }
+          }
+        } else {
+          for (int k = kbase; k < kd; k += KS) {
+            const int kc = k + grow;
+            const float bv = (float)brow[kc];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) {
+              const float av = (float)dR[(size_t)(16 * mi + gcol) * ldr + (kc - kbase)];
+              acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi], 0, 0, 0);
+            }
           }
         }
-      } else {
-        for (int k = kbase; k < kd; k += KS) {
-          const int kc = k + grow;
-          const float bv = (float)brow[kc];
-#pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const float av = (float)dR[(size_t)(16 * mi + gcol) * ldr + (kc - kbase)];
-            acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi], 0, 0, 0);
-          }
-        }
+        tim_epilogue(acc, sd, td, pd, rd, nmt, lin, prod);
       }
-      tim_epilogue(acc, sd, td, pd, rd, nmt, lin, prod);
       renorm();
     }
   }
