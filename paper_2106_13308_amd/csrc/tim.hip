@@ -29,10 +29,10 @@
 //
 // Workgroup = (block of 64 flipped sites, one sample), 4 waves.  The block's dR rows (K from
 // the first unit any of its sites feeds to h) are built once into LDS; the workgroup then sweeps
-// the site blocks d from its own to the last, each wave taking 16 columns d: A fragments from
-// LDS, B fragments (rows of the masked second layer) from global memory, 4 MFMA blocks of 16 x 16
-// per K step.  Elements with d <= i contribute exactly 0 (their dz is an exact 0), so the
-// diagonal block needs no mask.  Workgroups are numbered block-major: the ones that run together
+// the 128-site blocks d from the one holding its first site to the last, each wave taking 32
+// columns d in two groups of 16: A fragments from LDS, each used by both groups, B fragments (rows
+// of the masked second layer) from global memory, 8 MFMA blocks of 16 x 16 per K step.  Elements
+// with d <= i contribute exactly 0 (their dz is an exact 0), so the diagonal blocks need no mask.  Workgroups are numbered block-major: the ones that run together
 // on an XCD share their flip block and so stream the same rows of the second layer through that
 // XCD's L2, and the longest sweeps (the first blocks) start first.
 #include "common.hpp"
