@@ -519,13 +519,14 @@ def main():
         forms["fp32_plain"] = {"ms_per_step": msp, "samples_per_s": w.B / (msp / 1e3),
                                "note": "one timed step, no warmup step (launch-bound form)"}
         log(f"fp32 plain step: {msp:.1f} ms")
+    wname = "bf16" if wd == B.BF16 else "f32"  # the weights the timed step computes with
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": wname, "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "h": w.h, "global_batch": w.B,
                    "graph": GRAPH_DESC.get(w.name, w.description),
-                   "sampler": "incremental", "weights": "bf16", "parallelism": "single GPU"},
+                   "sampler": "incremental", "weights": wname, "parallelism": "single GPU"},
         "roofline": roof, "kernels": kernels, "forms": forms,
         "step_stats": {"mean_E": st["mean"], "min_E": st["min"], "var_E": st["var"]},
     }
