@@ -553,9 +553,10 @@ __global__ __launch_bounds__(SP_THREADS) void sample_pipe_kernel(
 
     // Ring depths: every pass reloads every slot, so a deeper ring costs loads and issue on each
     // pass; with BF16 weights two slots of each kind (about one block of prefetch) are fastest
-    // (three: 3 % slower, one: 5-20 % slower).
-    constexpr int PDU = (ES == 2) ? 2 : 3;
-    constexpr int PDZ = (ES == 2) ? 2 : 6;
+    // (three: 3 % slower, one: 5-20 % slower); FP32 weights (smaller logit tiles): two push and
+    // three logit slots (1.4 % faster than three and six).
+    constexpr int PDU = 2;
+    constexpr int PDZ = (ES == 2) ? 2 : 3;
     typename F::U fu[PDU];
     typename F::Z fz[PDZ];
     It su[PDU], sz[PDZ];  // item held by each slot
