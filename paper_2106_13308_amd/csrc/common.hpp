@@ -63,20 +63,14 @@ __device__ inline float4 site_uniforms(uint64_t seed, uint64_t step, uint32_t ta
 }
 
 // ---------------------------------------------------------------- streaming stores
-// Non-temporal stores (global_store ... nt) for large outputs that no later kernel of the same
-// call reads while they could still be cached: they do not displace the lines the following
-// kernels reuse.
+// A non-temporal 16-byte store (global_store_dwordx4 ... nt), for a large output that no later
+// kernel of the same call reads while it could still be cached: it does not displace the lines
+// the following kernels reuse.
 __device__ inline void store_nt(void* p, uint4 v) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const u32x4 x = {v.x, v.y, v.z, v.w};
   __builtin_nontemporal_store(x, (u32x4*)p);
 }
-__device__ inline void store_nt(void* p, uint2 v) {
-  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-  const u32x2 x = {v.x, v.y};
-  __builtin_nontemporal_store(x, (u32x2*)p);
-}
-__device__ inline void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
 // ---------------------------------------------------------------- numerics
 // log(1 + x) for x >= 0 without the cancellation of log(1 + x) near 0: with u = 1 + x
