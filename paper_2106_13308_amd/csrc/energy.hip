@@ -437,11 +437,13 @@ template <typename ET>
 __global__ __launch_bounds__(1024) void stats_kernel(const ET* __restrict__ E, int64_t B,
                                                       vqmc_stats* __restrict__ out,
                                                       float* __restrict__ coef) {
-  __shared__ ET ssum[1024];
-  __shared__ double sd[1024];
-  __shared__ ET smin[1024];
-  __shared__ int64_t sarg[1024];
-  const int t = threadIdx.x;
+  constexpr int NW = 1024 / 64;
+  __shared__ ET wsum[NW];
+  __shared__ ET wmin[NW];
+  __shared__ int64_t warg[NW];
+  __shared__ double wsd[NW];
+  __shared__ double s_mean;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   ET s = 0;
   ET mn = 0;
   int64_t am = -1;
@@ -453,40 +455,57 @@ __global__ __launch_bounds__(1024) void stats_kernel(const ET* __restrict__ E, i
       am = b;
     }
   }
-  ssum[t] = s;
-  smin[t] = mn;
-  sarg[t] = am;
+  // butterflies over the wave (lane 0's result is used), then the sixteen waves in order
+  auto better = [](ET m1, int64_t a1, ET m0, int64_t a0) {  // (m1, a1) replaces (m0, a0)
+    return a1 >= 0 && (a0 < 0 || m1 < m0 || (m1 == m0 && a1 < a0));
+  };
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o);
+    const ET mo = __shfl_xor(mn, o);
+    const int64_t ao = __shfl_xor(am, o);
+    if (better(mo, ao, mn, am)) {
+      mn = mo;
+      am = ao;
+    }
+  }
+  if (lane == 0) {
+    wsum[wv] = s;
+    wmin[wv] = mn;
+    warg[wv] = am;
+  }
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) {
-      ssum[t] += ssum[t + w];
-      const int64_t ao = sarg[t + w];
-      if (ao >= 0 && (sarg[t] < 0 || smin[t + w] < smin[t] ||
-                      (smin[t + w] == smin[t] && ao < sarg[t]))) {
-        smin[t] = smin[t + w];
-        sarg[t] = ao;
+  if (t == 0) {
+    ET ts = wsum[0], tm = wmin[0];
+    int64_t ta = warg[0];
+    for (int k = 1; k < NW; ++k) {
+      ts += wsum[k];
+      if (better(wmin[k], warg[k], tm, ta)) {
+        tm = wmin[k];
+        ta = warg[k];
       }
     }
-    __syncthreads();
+    s_mean = (double)ts / (double)B;
+    out->mean_E = s_mean;
+    out->min_E = (double)tm;
+    out->argmin = ta;
+    out->sum_E = (double)ts;
   }
-  const double mean = (double)ssum[0] / (double)B;
+  __syncthreads();
+  const double mean = s_mean;
   double v2 = 0.0;
   for (int64_t b = t; b < B; b += 1024) {
     const double dv = (double)E[b] - mean;
     v2 += dv * dv;
   }
-  sd[t] = v2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v2 += __shfl_xor(v2, o);
+  if (lane == 0) wsd[wv] = v2;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) sd[t] += sd[t + w];
-    __syncthreads();
-  }
   if (t == 0) {
-    out->mean_E = mean;
-    out->var_E = sd[0] / (double)B;
-    out->min_E = (double)smin[0];
-    out->argmin = sarg[0];
-    out->sum_E = (double)ssum[0];
+    double tv = wsd[0];
+    for (int k = 1; k < NW; ++k) tv += wsd[k];
+    out->var_E = tv / (double)B;
   }
   if (coef)
     for (int64_t b = t; b < B; b += 1024) coef[b] = (float)(((double)E[b] - mean) / (double)B);
